@@ -1,0 +1,163 @@
+"""FP64 CPU oracle for the AO -> MO value/gradient/Laplacian path (test
+infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The library never does; the two share no code.  The arithmetic
+lives in ``oracle.c`` (plain C, FP64, no BLAS); this module builds it with gcc
+and marshals numpy arrays through ctypes.
+
+Layouts (C order): AO and MO results are ``[point][component][function]`` with
+components (value, d/dx, d/dy, d/dz, Laplacian); with ``nq=14`` the AO result
+also carries the Hessian (xx xy xz yy yz zz) and the gradient of the
+Laplacian (components 5..13).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NQ_FULL = 14
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.oracle_ao_num.argtypes = [I64, P]
+        lib.oracle_ao_num.restype = I64
+        lib.oracle_normalisation.argtypes = [I64, P, P, P, P, P, P, P]
+        lib.oracle_normalisation.restype = None
+        lib.oracle_ao_derivs.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, ctypes.c_double,
+                                         ctypes.c_int, P]
+        lib.oracle_ao_derivs.restype = ctypes.c_int
+        lib.oracle_mo_vgl.argtypes = [I64, I64, I64, P, P, P]
+        lib.oracle_mo_vgl.restype = ctypes.c_int
+        lib.oracle_adjoint.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, ctypes.c_double,
+                                       I64, P, P, P, P, P, P, P, P]
+        lib.oracle_adjoint.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Basis:
+    def __init__(self, s):
+        self.nucl = _c(s.nucl_coord, np.float64)
+        self.sn = _c(s.shell_nucleus, np.int64)
+        self.sl = _c(s.shell_ang_mom, np.int32)
+        self.so = _c(s.shell_prim_offset, np.int64)
+        self.ex = _c(s.exponent, np.float64)
+        self.co = _c(s.coefficient, np.float64)
+        self.ao_num = int(_load().oracle_ao_num(self.sl.shape[0], _ptr(self.sl)))
+
+    def args(self):
+        return (self.nucl.shape[0], _ptr(self.nucl), self.sl.shape[0], _ptr(self.sn), _ptr(self.sl),
+                _ptr(self.so), _ptr(self.ex), _ptr(self.co))
+
+
+def normalisation(sys_):
+    """(prim_factor f, shell_factor N_s, ao_factor M) as the oracle derives them."""
+    b = _Basis(sys_)
+    f = np.empty(b.ex.shape[0])
+    ns = np.empty(b.sl.shape[0])
+    m = np.empty(b.ao_num)
+    _load().oracle_normalisation(b.sl.shape[0], _ptr(b.sl), _ptr(b.so), _ptr(b.ex), _ptr(b.co),
+                                 _ptr(f), _ptr(ns), _ptr(m))
+    return f, ns, m
+
+
+def ao_derivs(sys_, points: np.ndarray, B: float = 53.0, nq: int = 5) -> np.ndarray:
+    """AO quantities at `points` [P,3]: returns [P, nq, ao_num] (nq = 5 or 14).
+    B <= 0 disables the exponent cutoff."""
+    b = _Basis(sys_)
+    pts = _c(points, np.float64).reshape(-1, 3)
+    out = np.empty((pts.shape[0], nq, b.ao_num))
+    rc = _load().oracle_ao_derivs(*b.args(), pts.shape[0], _ptr(pts), float(B), int(nq), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_ao_derivs failed ({rc})")
+    return out
+
+
+def ao_vgl(sys_, points: Optional[np.ndarray] = None, B: float = 53.0) -> np.ndarray:
+    """AO value/gradient/Laplacian [P, 5, ao_num] (default points: all walkers)."""
+    return ao_derivs(sys_, sys_.points() if points is None else points, B, 5)
+
+
+def mo_vgl_from_ao(ao: np.ndarray, coef: np.ndarray) -> np.ndarray:
+    ao = _c(ao, np.float64)
+    coef = _c(coef, np.float64)
+    P, five, K = ao.shape
+    N = coef.shape[0]
+    assert five == 5 and coef.shape[1] == K
+    out = np.empty((P, 5, N))
+    _load().oracle_mo_vgl(P, K, N, _ptr(ao), _ptr(coef), _ptr(out))
+    return out
+
+
+def mo_vgl(sys_, points: Optional[np.ndarray] = None, B: float = 53.0,
+           coef: Optional[np.ndarray] = None) -> np.ndarray:
+    """mo_vgl [P, 5, mo_num] at `points` (default: every walker's electrons)."""
+    ao = ao_vgl(sys_, points, B)
+    return mo_vgl_from_ao(ao, sys_.mo_coef if coef is None else coef)
+
+
+def adjoint(sys_, w: np.ndarray, points: Optional[np.ndarray] = None, B: float = 53.0,
+            coef: Optional[np.ndarray] = None, nucl: Optional[np.ndarray] = None,
+            with_abs: bool = True):
+    """Gradients of sum(W * mo_vgl): returns dict with d_coef [mo, ao],
+    d_elec [P, 3], d_nucl [nucl, 3] and the matching *_abs sums."""
+    import copy
+    s = sys_
+    if nucl is not None:
+        s = copy.copy(sys_)
+        s.nucl_coord = nucl
+    b = _Basis(s)
+    pts = _c(sys_.points() if points is None else points, np.float64).reshape(-1, 3)
+    C = _c(sys_.mo_coef if coef is None else coef, np.float64)
+    N = C.shape[0]
+    W = _c(w, np.float64).reshape(pts.shape[0], 5, N)
+    out = {
+        "d_coef": np.empty((N, b.ao_num)),
+        "d_elec": np.empty((pts.shape[0], 3)),
+        "d_nucl": np.empty((b.nucl.shape[0], 3)),
+    }
+    if with_abs:
+        out.update({"d_coef_abs": np.empty((N, b.ao_num)), "d_elec_abs": np.empty((pts.shape[0], 3)),
+                    "d_nucl_abs": np.empty((b.nucl.shape[0], 3))})
+    rc = _load().oracle_adjoint(*b.args(), pts.shape[0], _ptr(pts), float(B), N, _ptr(C), _ptr(W),
+                                _ptr(out["d_coef"]), _ptr(out["d_elec"]), _ptr(out["d_nucl"]),
+                                _ptr(out.get("d_coef_abs")), _ptr(out.get("d_elec_abs")),
+                                _ptr(out.get("d_nucl_abs")))
+    if rc:
+        raise RuntimeError(f"oracle_adjoint failed ({rc})")
+    return out
