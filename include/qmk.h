@@ -1,0 +1,212 @@
+/*
+ * qmk.h -- C ABI of the MI355X AO -> MO value/gradient/Laplacian library.
+ *
+ * The calls follow the problem statement of the QMCkl paper (arXiv
+ * 2512.16677): create a context, set the nuclei, the basis set and the MO
+ * coefficients, set the electron (or grid) coordinates, get the molecular
+ * orbitals with their gradients and Laplacians, destroy the context
+ * (Section 5.1 usage example; Section 2.2 context and get/provide/compute
+ * call structure; Section 2.3 plain C ABI with simple types).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns a qmk_status; 0 (QMK_OK) is success.  Functions
+ *     never abort or exit.  On error the outputs are untouched, the context
+ *     stays valid and qmk_last_error() returns a message.  An invalid
+ *     argument returns QMK_INVALID_ARG_BASE + k, k the 1-based position of
+ *     the offending argument.
+ *   - Lengths are in bohr (atomic units).  Arrays are C-contiguous.
+ *   - set_* calls copy their inputs: the caller may free its arrays on
+ *     return.  They are synchronous.
+ *   - get_* and adjoint calls write into DEVICE buffers owned by the caller
+ *     (for example a torch tensor's data pointer) on the given HIP stream
+ *     (NULL = the null stream); they return once the work is enqueued.  The
+ *     library never frees caller memory.
+ *   - A context is not thread-safe: use one context per host thread, as in
+ *     the paper's parallelisation model (Section 2.4).  Contexts are
+ *     independent of each other (Section 2.2).
+ *   - Component order of every *_vgl quantity: value, d/dx, d/dy, d/dz,
+ *     Laplacian (Section 3.2, equations for phi, grad phi, Laplacian phi).
+ *     AOs of a shell are ordered lexicographically with the x power
+ *     descending (d: xx xy xz yy yz zz; f: xxx xxy xxz xyy xyz xzz yyy yyz
+ *     yzz zzz), shells in input order.
+ */
+#ifndef QMK_H
+#define QMK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qmk_status;
+typedef struct qmk_ctx_s* qmk_ctx;
+typedef struct qmk_batch_s* qmk_batch;
+
+enum {
+  QMK_OK = 0,
+  QMK_INVALID_CONTEXT = 1, /* NULL or destroyed context                      */
+  QMK_NOT_SET = 2,         /* a prerequisite (nuclei, basis, ...) is missing */
+  QMK_SIZE = 3,            /* size_max smaller than the result               */
+  QMK_OUT_OF_MEMORY = 4,   /* device or host allocation failed              */
+  QMK_HIP_ERROR = 5,       /* HIP runtime error; text in qmk_last_error     */
+  QMK_NONFINITE = 6,       /* NaN or Inf in an input array                   */
+  QMK_UNSUPPORTED = 7,     /* valid request this build does not support      */
+  QMK_INVALID_ARG_BASE = 100
+};
+
+/* Precision modes (qmk_set_precision). */
+enum {
+  QMK_FP64 = 0,         /* FP64 AOs, FP64 MFMA contraction                   */
+  QMK_MIXED_F32 = 1,    /* FP32 AOs, FP32 MFMA contraction                   */
+  QMK_MIXED_BF16X3 = 2  /* FP32 AOs, three-product BF16-split MFMA contraction
+                           with FP32 accumulation and compensated summation */
+};
+
+/* Element types of caller buffers. */
+enum { QMK_F64 = 0, QMK_F32 = 1 };
+
+/* Status code -> static string ("QMK_OK", ...). Never NULL. */
+const char* qmk_status_string(qmk_status status);
+
+/* Last error message of a context ("" if none); valid until the next call on
+ * the context.  qmk_last_error(NULL) returns the last error of a failed
+ * qmk_ctx_create on this thread. */
+const char* qmk_last_error(qmk_ctx ctx);
+
+/* Create a context bound to HIP device `hip_device` (Section 2.2: one
+ * context holds all inputs, cached intermediates and their time stamps).
+ * *out receives the handle. */
+qmk_status qmk_ctx_create(qmk_ctx* out, int32_t hip_device);
+
+/* Free everything the context owns (Section 5.1, context_destroy).  The
+ * handle is invalid afterwards.  Waits for the context's pending work. */
+qmk_status qmk_ctx_destroy(qmk_ctx ctx);
+
+/* Precision parameter B, bits requested (Section 3.1: default 53).  A
+ * primitive of exponent g at squared distance u contributes iff
+ * g*u < (B-1)*ln 2; otherwise it and all its derivatives are zero.
+ * bits in 2..53.  mode: QMK_FP64, QMK_MIXED_F32 or QMK_MIXED_BF16X3; the
+ * mixed modes are meant for bits = 24.  Invalidates cached results. */
+qmk_status qmk_set_precision(qmk_ctx ctx, int32_t bits, int32_t mode);
+
+/* Nuclear coordinates coord[nucl_num][3] (host memory).  nucl_num >= 1.
+ * Invalidates cached results.  The number of nuclei may only change while no
+ * basis is set. */
+qmk_status qmk_set_nucleus(qmk_ctx ctx, int64_t nucl_num, const double* coord);
+
+/* Contracted Cartesian Gaussian basis (Section 3.1, radial part with p = 2,
+ * n_s = 0; angular part up to l = 3).  Host arrays:
+ *   shell_nucleus[shell_num]       nucleus index of each shell (0-based)
+ *   shell_ang_mom[shell_num]       l in 0..3
+ *   shell_prim_offset[shell_num+1] primitives of shell s are
+ *                                  offset[s] .. offset[s+1]-1; offset[0] = 0,
+ *                                  non-decreasing, offset[shell_num] = prim_num
+ *   exponent[prim_num]             gamma > 0
+ *   coefficient[prim_num]          contraction coefficient a
+ *   prim_factor[prim_num]          f_k, or NULL: normalised axis primitive
+ *   shell_factor[shell_num]        N_s, or NULL: unit-norm contracted shell
+ *   ao_factor[ao_num]              M_n, or NULL: every Cartesian AO unit-norm
+ * Primitives need not be sorted: the library sorts each shell by ascending
+ * exponent (Section 3.1), which makes the cutoff an early exit.  Requires
+ * the nuclei.  Invalidates cached results. */
+qmk_status qmk_set_basis(qmk_ctx ctx, int64_t shell_num, int64_t prim_num,
+                         const int64_t* shell_nucleus, const int32_t* shell_ang_mom,
+                         const int64_t* shell_prim_offset, const double* exponent,
+                         const double* coefficient, const double* prim_factor,
+                         const double* shell_factor, const double* ao_factor);
+
+/* MO coefficients coef[mo_num][ao_num] (host), MO n = sum_k C[n][k] chi_k
+ * (Section 3.2).  ao_num must match the basis.  Invalidates cached MOs. */
+qmk_status qmk_set_mo_coef(qmk_ctx ctx, int64_t mo_num, int64_t ao_num, const double* coef);
+
+/* Electron / grid coordinates for walk_num walkers of elec_num electrons
+ * (Section 5.1, set_point).  transp = 'N': coord[walk][elec][3];
+ * transp = 'T': coord[3][walk*elec].  coord_on_device = 0: host memory,
+ * copied now; = 1: device memory, NOT copied -- it must hold the
+ * coordinates until the last get/adjoint call that uses them has run on its
+ * stream.  Increments the context's time stamp (Section 2.2), so the next
+ * get recomputes every intermediate that depends on the points. */
+qmk_status qmk_set_point(qmk_ctx ctx, char transp, int64_t walk_num, int64_t elec_num,
+                         const double* coord, int32_t coord_on_device);
+
+/* Dimensions; any pointer may be NULL.  point_num = walk_num * elec_num. */
+qmk_status qmk_get_dims(qmk_ctx ctx, int64_t* nucl_num, int64_t* ao_num, int64_t* mo_num,
+                        int64_t* walk_num, int64_t* elec_num);
+
+/* AO values, gradients, Laplacians into out[walk][elec][5][ao] (device
+ * buffer of size_max elements of type dtype, QMK_F64 or QMK_F32).
+ * Intended for inspection and tests: the contraction consumes the AOs in
+ * the library's own layout. */
+qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                          void* hip_stream);
+
+/* MO values, gradients, Laplacians: mo_vgl[walk][elec][5][mo] =
+ * sum_k C[mo][k] ao_vgl[walk][elec][5][k] (Section 3.2), into a device
+ * buffer of size_max >= walk*elec*5*mo elements of type dtype.  The AO stage
+ * is recomputed only if the points, basis or precision changed since it was
+ * last computed (time stamps, Section 2.2). */
+qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                          void* hip_stream);
+
+/* Adjoint of L = sum(W * mo_vgl) for the current points (Section 3.6 and
+ * Section 3.5 motivate these derivatives; the nuclei carry their shells
+ * rigidly, basis parameters are fixed):
+ *   w       [walk][elec][5][mo] device buffer of type w_dtype
+ *   d_coef  [mo][ao]    device FP64, dL/dC          (or NULL)
+ *   d_elec  [walk][elec][3] device FP64, dL/dr      (or NULL)
+ *   d_nucl  [nucl][3]   device FP64, dL/dR_nucleus  (or NULL)
+ * Outputs are overwritten (not accumulated).  AO derivatives up to third
+ * order are recomputed from the coordinates, never stored.  Deterministic:
+ * the same inputs give bitwise the same outputs. */
+qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, double* d_coef,
+                              double* d_elec, double* d_nucl, void* hip_stream);
+
+/* Number of kernel launches issued by the context so far (for tests of the
+ * time-stamp logic). */
+qmk_status qmk_get_launch_count(qmk_ctx ctx, int64_t* count);
+
+/* Kernel timing (tracing).  With timing enabled, every kernel the context
+ * launches is bracketed by two HIP events recorded on the launch stream;
+ * qmk_get_timing waits for the recorded events and returns the summed
+ * device time (ms) and the number of launches of one kernel class since
+ * timing was last enabled.  qmk_set_timing(ctx, 1) also resets the sums. */
+enum {
+  QMK_KERNEL_AO = 0,         /* AO value/gradient/Laplacian stage      */
+  QMK_KERNEL_MO = 1,         /* AO -> MO contraction                   */
+  QMK_KERNEL_GBAR = 2,       /* adjoint: W C product                   */
+  QMK_KERNEL_AO_ADJOINT = 3, /* adjoint: AO derivatives contracted     */
+  QMK_KERNEL_DCOEF = 4,      /* adjoint: W^T ao split-K product        */
+  QMK_KERNEL_REDUCE = 5,     /* deterministic reductions               */
+  QMK_KERNEL_CLASSES = 6
+};
+qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
+qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------- */
+/* Batches: many independent contexts (Section 2.2) -- molecules of uneven
+ * sizes, each with its own walkers -- evaluated together.  The contexts
+ * must all be fully set (nuclei, basis, MO coefficients, points) on the
+ * same device and the same precision mode; the batch reads them at each
+ * run, so set_point between runs is allowed as long as no dimension
+ * changes (a change makes qmk_batch_run return QMK_NOT_SET-free
+ * re-planning automatically).  The batch does not own the contexts. */
+qmk_status qmk_batch_create(qmk_batch* out, const qmk_ctx* ctxs, int64_t n);
+qmk_status qmk_batch_destroy(qmk_batch batch);
+
+/* Forward mo_vgl of every context into outs[i] (device, [walk][elec][5][mo]
+ * of context i, type dtype), and, if ws != NULL, the adjoint with weights
+ * ws[i] (type dtype) into d_coefs[i], d_elecs[i], d_nucls[i] (each array of
+ * pointers may be NULL; entries may be NULL).  The whole batch runs as one
+ * HIP graph launch, captured on the first run and replayed afterwards;
+ * persistent kernels walk a longest-first work list of (molecule, tile)
+ * items. */
+qmk_status qmk_batch_run(qmk_batch batch, void* const* outs, int32_t dtype, const void* const* ws,
+                         double* const* d_coefs, double* const* d_elecs, double* const* d_nucls,
+                         void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMK_H */

@@ -1,0 +1,162 @@
+// AO value / gradient / Laplacian kernels (QMCkl paper, Section 3.1).
+//
+// Mapping: one lane per point, so every store of one (AO, component) pair by
+// a wavefront covers 64 consecutive points (coalesced along the point axis
+// of the [ao][5][point] layout).  A block serves 256 points and one group
+// of nuclei: it stages that group's nucleus, shell and primitive tables in
+// LDS, then walks the nuclei in order.  For each nucleus the wavefront
+// takes one ballot on gmin*u < T (the per-nucleus radius of Section 3.1 in
+// squared form); if no lane is inside, the nucleus' AOs are stored as zeros
+// without touching a primitive.  Inside a shell the primitives are sorted by
+// ascending exponent, so once gamma*u >= T holds for every lane the rest of
+// the shell is skipped (Section 3.1, early exit after the first negligible
+// primitive).  Radial sums g0 = R, g1 = dR/du, g2 = d2R/du2 live in
+// registers; powers of the displacement are built by repeated
+// multiplication (Section 3.1, angular part) and never stored.
+#include "qmk_internal.h"
+
+namespace qmk {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ void st(T* p, double v) { *p = static_cast<T>(v); }
+
+// Stores value, gradient and Laplacian of the (L+1)(L+2)/2 Cartesian AOs of
+// one shell for this lane's point.
+//   chi      = M P g0
+//   d_i chi  = M (d_i P g0 + 2 d_i P g1)          (d_i: displacement)
+//   lap chi  = M (lap P g0 + (4L+6) P g1 + 4 u P g2)
+template <int L, typename OutT>
+__device__ __forceinline__ void shell_vgl(double dx, double dy, double dz, double u, double g0,
+                                          double g1, double g2, const double* __restrict__ M,
+                                          OutT* __restrict__ o, int64_t sK, int64_t sC, bool store) {
+  double px[L + 2], py[L + 2], pz[L + 2];
+  px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+  for (int i = 1; i <= L; ++i) {
+    px[i] = px[i - 1] * dx;
+    py[i] = py[i - 1] * dy;
+    pz[i] = pz[i - 1] * dz;
+  }
+  const double c1 = (4.0 * L + 6.0) * g1;
+  const double c2 = 4.0 * u * g2;
+  int idx = 0;
+#pragma unroll
+  for (int a = L; a >= 0; --a) {
+#pragma unroll
+    for (int b = L - a; b >= 0; --b, ++idx) {
+      const int c = L - a - b;
+      const double xa = px[a], yb = py[b], zc = pz[c];
+      const double P = xa * yb * zc;
+      const double Px = a > 0 ? a * px[a > 0 ? a - 1 : 0] * yb * zc : 0.0;
+      const double Py = b > 0 ? b * xa * py[b > 0 ? b - 1 : 0] * zc : 0.0;
+      const double Pz = c > 0 ? c * xa * yb * pz[c > 0 ? c - 1 : 0] : 0.0;
+      double lapP = 0.0;
+      if (a > 1) lapP += a * (a - 1) * px[a > 1 ? a - 2 : 0] * yb * zc;
+      if (b > 1) lapP += b * (b - 1) * xa * py[b > 1 ? b - 2 : 0] * zc;
+      if (c > 1) lapP += c * (c - 1) * xa * yb * pz[c > 1 ? c - 2 : 0];
+      const double m = M[idx];
+      const double tg = 2.0 * P * g1;
+      if (store) {
+        OutT* q = o + idx * sK;
+        st(q, m * P * g0);
+        st(q + sC, m * (Px * g0 + dx * tg));
+        st(q + 2 * sC, m * (Py * g0 + dy * tg));
+        st(q + 3 * sC, m * (Pz * g0 + dz * tg));
+        st(q + 4 * sC, m * (lapP * g0 + P * (c1 + c2)));
+      }
+    }
+  }
+}
+
+template <typename OutT>
+__device__ __forceinline__ void shell_zero(int l, OutT* __restrict__ o, int64_t sK, int64_t sC,
+                                           bool store) {
+  if (!store) return;
+  const int n = (l + 1) * (l + 2) / 2;
+  for (int i = 0; i < n; ++i) {
+    OutT* q = o + i * sK;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) q[c * sC] = OutT(0);
+  }
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const NucGroup g = t.group[blockIdx.y];
+  const int np = g.p_end - g.p_begin, ns = g.sh_end - g.sh_begin, nn = g.nuc_end - g.nuc_begin;
+  PrimDev* s_prim = reinterpret_cast<PrimDev*>(smem);
+  ShellDev* s_shell = reinterpret_cast<ShellDev*>(s_prim + np);
+  NucDev* s_nuc = reinterpret_cast<NucDev*>(s_shell + ns);
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s_prim[i] = t.prim[g.p_begin + i];
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) s_shell[i] = t.shell[g.sh_begin + i];
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) s_nuc[i] = t.nuc[g.nuc_begin + i];
+  __syncthreads();
+
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool valid = p < pts.P;
+  double rx = 0.0, ry = 0.0, rz = 0.0;
+  if (valid) {
+    rx = pts.coord[p * pts.s_pt];
+    ry = pts.coord[p * pts.s_pt + pts.s_ax];
+    rz = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
+  }
+  OutT* const obase = static_cast<OutT*>(out.out) + p * out.sP;
+  const double T = t.T;
+
+  for (int a = 0; a < nn; ++a) {
+    const NucDev nu = s_nuc[a];
+    const double dx = rx - nu.x, dy = ry - nu.y, dz = rz - nu.z;
+    const double u = dx * dx + dy * dy + dz * dz;
+    const bool near = valid && (nu.gmin * u < T);
+    if (!__any(near)) {
+      for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
+        const ShellDev sh = s_shell[s];
+        shell_zero(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, valid);
+      }
+      continue;
+    }
+    for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
+      const ShellDev sh = s_shell[s];
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+      for (int k = sh.p_begin; k < sh.p_end; ++k) {
+        const PrimDev pr = s_prim[k];
+        const double x = pr.gamma * u;
+        const bool on = near && (x < T);
+        if (!__any(on)) break;  // ascending exponents: every later one is cut too
+        if (on) {
+          const double e = pr.coef * exp(-x);
+          g0 += e;
+          g1 -= pr.gamma * e;
+          g2 += pr.gamma * pr.gamma * e;
+        }
+      }
+      OutT* o = obase + sh.ao_off * out.sK;
+      const double* M = t.ao_factor + sh.ao_off;
+      switch (sh.l) {
+        case 0: shell_vgl<0>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
+        case 1: shell_vgl<1>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
+        case 2: shell_vgl<2>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
+        default: shell_vgl<3>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
+                         int fp32_compute, hipStream_t s) {
+  (void)fp32_compute;
+  if (pts.P <= 0 || t.n_groups <= 0) return hipSuccess;
+  const size_t smem = static_cast<size_t>(t.smem_bytes);
+  dim3 grid(static_cast<unsigned>((pts.P + 255) / 256), static_cast<unsigned>(t.n_groups));
+  if (out_is_f32)
+    hipLaunchKernelGGL(ao_vgl_kernel<float>, grid, dim3(256), smem, s, t, pts, out);
+  else
+    hipLaunchKernelGGL(ao_vgl_kernel<double>, grid, dim3(256), smem, s, t, pts, out);
+  return hipGetLastError();
+}
+
+}  // namespace qmk

@@ -1,0 +1,898 @@
+// Host runtime of the C ABI declared in include/qmk.h: contexts, input
+// validation, basis preprocessing, time stamps and kernel orchestration.
+//
+// Structure follows the QMCkl paper's call model (Section 2.2): a context
+// holds the inputs, the cached intermediates and their time stamps; a get
+// call "provides" each dependency -- recomputing it only if its time stamp
+// is older than the inputs it depends on -- and then computes the
+// requested quantity.  Here the cached intermediate is the AO array (and
+// the device copies of the basis tables and MO coefficients); the MO array
+// is written straight into the caller's buffer by the contraction.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/qmk.h"
+#include "qmk_internal.h"
+
+using namespace qmk;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x514d4b43u;  // "QMKC"
+thread_local std::string g_create_error;
+
+int n_cart(int l) { return (l + 1) * (l + 2) / 2; }
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, n > 0 ? n : 16);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = n;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Normalisation (QMCkl paper, Section 3.1: the factors f_ks, N_s and M_n),
+// written through Gaussian moments
+//   I(n, alpha) = int t^(2n) exp(-alpha t^2) dt = Gamma(n + 1/2) alpha^-(n+1/2)
+// f normalises the axis primitive x^l exp(-g r^2): f^-2 = I(l,2g) I(0,2g)^2;
+// N_s normalises the contracted axis function; M(a,b,c)^2 is the ratio of the
+// axis moment to the moment of x^a y^b z^c, which makes every Cartesian AO
+// unit-norm.
+double moment(int n, double alpha) {
+  return std::tgamma(n + 0.5) / std::pow(alpha, n + 0.5);
+}
+double axis_norm2(int l, double alpha) {
+  const double i0 = moment(0, alpha);
+  return moment(l, alpha) * i0 * i0;
+}
+
+}  // namespace
+
+struct qmk_ctx_s {
+  uint32_t magic = kMagic;
+  int device = 0;
+  std::string err;
+
+  // time stamps: `date` moves with everything the AOs depend on
+  int64_t date = 1;
+  int32_t bits = 53;
+  int32_t mode = QMK_FP64;
+
+  int64_t nucl_num = 0;
+  std::vector<double> nucl;
+
+  bool has_basis = false;
+  int64_t shell_num = 0, prim_num = 0, ao_num = 0;
+  std::vector<int64_t> sh_nuc, sh_off;
+  std::vector<int32_t> sh_l;
+  std::vector<double> expo, coef, pf, sf, af;  // factors as used (given or computed)
+
+  bool has_coef = false;
+  int64_t mo_num = 0;
+  std::vector<double> C;  // [mo][ao]
+
+  bool has_points = false;
+  int64_t walk_num = 0, elec_num = 0;
+  char transp = 'N';
+  const double* pts = nullptr;
+  DevBuf own_pts;
+
+  // device tables
+  bool tables_dirty = true;
+  DevBuf d_nuc, d_shell, d_prim, d_aofac, d_group, d_devof;
+  AoTables tab{};
+  int32_t n_groups = 0, nucl_dev = 0;
+
+  // MO coefficient copies for the current mode
+  bool coef_dirty = true;
+  int coef_mode = -1;
+  int64_t Kp = 0, Np = 0;
+  DevBuf d_Ct, d_C;
+
+  // AO array [Kp][5][Pp] (double or float), valid at ao_date
+  DevBuf ao;
+  int64_t ao_Pp = 0, ao_Kp = 0, ao_date = -1;
+  int ao_f32 = -1;
+
+  DevBuf gbar, ws_dc, ws_nuc, ws_elec;
+  int64_t gbar_Pp = 0, gbar_Kp = 0;
+  int gbar_f32 = -1;
+
+  int64_t launches = 0;
+
+  // tracing: events around launches, per kernel class
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  double t_ms[QMK_KERNEL_CLASSES] = {};
+  int64_t t_n[QMK_KERNEL_CLASSES] = {};
+  ~qmk_ctx_s() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : event_pool) (void)hipEventDestroy(e);
+  }
+
+  int64_t P() const { return walk_num * elec_num; }
+  bool f32_storage() const { return mode != QMK_FP64; }
+};
+
+namespace {
+
+qmk_status fail(qmk_ctx ctx, qmk_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+qmk_status bad_arg(qmk_ctx ctx, int k, const std::string& msg) {
+  return fail(ctx, QMK_INVALID_ARG_BASE + k, "argument " + std::to_string(k) + ": " + msg);
+}
+qmk_status hip_fail(qmk_ctx ctx, hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(ctx, QMK_OUT_OF_MEMORY, std::string(what) + ": " + hipGetErrorString(e));
+  return fail(ctx, QMK_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+bool valid_ctx(qmk_ctx ctx) { return ctx != nullptr && ctx->magic == kMagic; }
+
+hipEvent_t take_event(qmk_ctx ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when timing is enabled.
+struct LaunchTimer {
+  qmk_ctx ctx;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  LaunchTimer(qmk_ctx c, int k, hipStream_t st) : ctx(c), kind(k), s(st) {
+    ++ctx->launches;
+    if (!ctx->timing) return;
+    a = take_event(ctx);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~LaunchTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(ctx);
+    if (!b) {
+      ctx->event_pool.push_back(a);
+      return;
+    }
+    (void)hipEventRecord(b, s);
+    ctx->pending.push_back({kind, a, b});
+  }
+};
+
+void collect_timing(qmk_ctx ctx) {
+  for (auto& p : ctx->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->t_ms[p.kind] += ms;
+      ctx->t_n[p.kind] += 1;
+    }
+    ctx->event_pool.push_back(p.a);
+    ctx->event_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+#define QMK_CHECK_CTX(ctx) \
+  do {                     \
+    if (!valid_ctx(ctx)) return QMK_INVALID_CONTEXT; \
+  } while (0)
+#define QMK_HIP(ctx, expr, what)                      \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+// Builds the device nucleus / shell / primitive tables and nucleus groups.
+qmk_status build_tables(qmk_ctx ctx) {
+  const int64_t S = ctx->shell_num;
+  std::vector<std::vector<int64_t>> shells_of(ctx->nucl_num);
+  for (int64_t s = 0; s < S; ++s) shells_of[ctx->sh_nuc[s]].push_back(s);
+  std::vector<int64_t> ao_off(S + 1, 0);
+  for (int64_t s = 0; s < S; ++s) ao_off[s + 1] = ao_off[s] + n_cart(ctx->sh_l[s]);
+
+  std::vector<NucDev> nuc;
+  std::vector<ShellDev> shell;
+  std::vector<PrimDev> prim;
+  std::vector<NucGroup> group;
+  std::vector<int32_t> dev_of(ctx->nucl_num, -1);
+  NucGroup cur{0, 0, 0, 0, 0, 0, 0, 0};
+  size_t smem = 0;
+  auto close_group = [&]() {
+    if (cur.nuc_end > cur.nuc_begin) {
+      group.push_back(cur);
+      smem = std::max(smem, (cur.p_end - cur.p_begin) * sizeof(PrimDev) +
+                                (cur.sh_end - cur.sh_begin) * sizeof(ShellDev) +
+                                (cur.nuc_end - cur.nuc_begin) * sizeof(NucDev));
+    }
+    cur = NucGroup{(int32_t)nuc.size(), (int32_t)nuc.size(), (int32_t)shell.size(),
+                   (int32_t)shell.size(), (int32_t)prim.size(), (int32_t)prim.size(), 0, 0};
+  };
+  for (int64_t A = 0; A < ctx->nucl_num; ++A) {
+    if (shells_of[A].empty()) continue;
+    int64_t np = 0;
+    for (int64_t s : shells_of[A]) np += ctx->sh_off[s + 1] - ctx->sh_off[s];
+    const int64_t nsh = static_cast<int64_t>(shells_of[A].size());
+    if (np > kGroupMaxPrim || nsh > kGroupMaxShell)
+      return fail(ctx, QMK_UNSUPPORTED, "nucleus " + std::to_string(A) + " has more than " +
+                                            std::to_string(kGroupMaxPrim) + " primitives or " +
+                                            std::to_string(kGroupMaxShell) + " shells");
+    if ((cur.p_end - cur.p_begin) + np > kGroupMaxPrim ||
+        (cur.sh_end - cur.sh_begin) + nsh > kGroupMaxShell ||
+        (cur.nuc_end - cur.nuc_begin) + 1 > kGroupMaxNuc)
+      close_group();
+    NucDev nd{};
+    nd.x = ctx->nucl[3 * A];
+    nd.y = ctx->nucl[3 * A + 1];
+    nd.z = ctx->nucl[3 * A + 2];
+    nd.gmin = INFINITY;
+    nd.sh_begin = static_cast<int32_t>(shell.size()) - cur.sh_begin;
+    nd.orig = static_cast<int32_t>(A);
+    for (int64_t s : shells_of[A]) {
+      ShellDev sd{};
+      sd.ao_off = static_cast<int32_t>(ao_off[s]);
+      sd.l = ctx->sh_l[s];
+      sd.p_begin = static_cast<int32_t>(prim.size()) - cur.p_begin;
+      // primitives of the shell by ascending exponent (Section 3.1)
+      std::vector<int64_t> order(ctx->sh_off[s + 1] - ctx->sh_off[s]);
+      std::iota(order.begin(), order.end(), ctx->sh_off[s]);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int64_t a, int64_t b) { return ctx->expo[a] < ctx->expo[b]; });
+      for (int64_t k : order) {
+        PrimDev pd{ctx->expo[k], ctx->coef[k] * ctx->pf[k] * ctx->sf[s]};
+        prim.push_back(pd);
+        nd.gmin = std::min(nd.gmin, ctx->expo[k]);
+      }
+      sd.p_end = static_cast<int32_t>(prim.size()) - cur.p_begin;
+      shell.push_back(sd);
+    }
+    nd.sh_end = static_cast<int32_t>(shell.size()) - cur.sh_begin;
+    dev_of[A] = static_cast<int32_t>(nuc.size());
+    nuc.push_back(nd);
+    cur.nuc_end = static_cast<int32_t>(nuc.size());
+    cur.sh_end = static_cast<int32_t>(shell.size());
+    cur.p_end = static_cast<int32_t>(prim.size());
+  }
+  close_group();
+  if (group.empty()) return fail(ctx, QMK_NOT_SET, "basis has no shells");
+
+  auto up = [&](DevBuf& b, const void* src, size_t n) -> hipError_t {
+    hipError_t e = b.ensure(n);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.p, src, n, hipMemcpyHostToDevice);
+  };
+  QMK_HIP(ctx, up(ctx->d_nuc, nuc.data(), nuc.size() * sizeof(NucDev)), "upload nuclei");
+  QMK_HIP(ctx, up(ctx->d_shell, shell.data(), shell.size() * sizeof(ShellDev)), "upload shells");
+  QMK_HIP(ctx, up(ctx->d_prim, prim.data(), prim.size() * sizeof(PrimDev)), "upload primitives");
+  QMK_HIP(ctx, up(ctx->d_aofac, ctx->af.data(), ctx->af.size() * sizeof(double)), "upload M");
+  QMK_HIP(ctx, up(ctx->d_group, group.data(), group.size() * sizeof(NucGroup)), "upload groups");
+  QMK_HIP(ctx, up(ctx->d_devof, dev_of.data(), dev_of.size() * sizeof(int32_t)), "upload map");
+
+  ctx->n_groups = static_cast<int32_t>(group.size());
+  ctx->nucl_dev = static_cast<int32_t>(nuc.size());
+  AoTables& t = ctx->tab;
+  t.nuc = ctx->d_nuc.as<NucDev>();
+  t.shell = ctx->d_shell.as<ShellDev>();
+  t.prim = ctx->d_prim.as<PrimDev>();
+  t.ao_factor = ctx->d_aofac.as<double>();
+  t.group = ctx->d_group.as<NucGroup>();
+  t.n_groups = ctx->n_groups;
+  t.ao_num = static_cast<int32_t>(ctx->ao_num);
+  t.smem_bytes = static_cast<int32_t>(smem);
+  t.nucl_dev = ctx->nucl_dev;
+  ctx->tables_dirty = false;
+  return QMK_OK;
+}
+
+qmk_status ensure_tables(qmk_ctx ctx) {
+  if (ctx->tables_dirty) {
+    qmk_status st = build_tables(ctx);
+    if (st != QMK_OK) return st;
+  }
+  ctx->tab.T = (ctx->bits - 1) * std::log(2.0);
+  return QMK_OK;
+}
+
+qmk_status ensure_coef(qmk_ctx ctx) {
+  const int want = ctx->f32_storage() ? 1 : 0;
+  if (!ctx->coef_dirty && ctx->coef_mode == want) return QMK_OK;
+  const int64_t K = ctx->ao_num, N = ctx->mo_num;
+  ctx->Kp = round_up(K, kAoPad);
+  ctx->Np = round_up(N, kMoPad);
+  const int64_t Kp = ctx->Kp, Np = ctx->Np;
+  const size_t esz = want ? sizeof(float) : sizeof(double);
+  std::vector<unsigned char> ct(static_cast<size_t>(Kp * Np) * esz, 0), cn(ct.size(), 0);
+  for (int64_t n = 0; n < N; ++n)
+    for (int64_t k = 0; k < K; ++k) {
+      const double v = ctx->C[n * K + k];
+      if (want) {
+        reinterpret_cast<float*>(ct.data())[k * Np + n] = static_cast<float>(v);
+        reinterpret_cast<float*>(cn.data())[n * Kp + k] = static_cast<float>(v);
+      } else {
+        reinterpret_cast<double*>(ct.data())[k * Np + n] = v;
+        reinterpret_cast<double*>(cn.data())[n * Kp + k] = v;
+      }
+    }
+  QMK_HIP(ctx, ctx->d_Ct.ensure(ct.size()), "alloc C^T");
+  QMK_HIP(ctx, hipMemcpy(ctx->d_Ct.p, ct.data(), ct.size(), hipMemcpyHostToDevice), "upload C^T");
+  QMK_HIP(ctx, ctx->d_C.ensure(cn.size()), "alloc C");
+  QMK_HIP(ctx, hipMemcpy(ctx->d_C.p, cn.data(), cn.size(), hipMemcpyHostToDevice), "upload C");
+  ctx->coef_dirty = false;
+  ctx->coef_mode = want;
+  return QMK_OK;
+}
+
+PointArgs point_args(qmk_ctx ctx) {
+  PointArgs a{};
+  a.coord = ctx->pts;
+  a.P = ctx->P();
+  if (ctx->transp == 'N') {
+    a.s_pt = 3;
+    a.s_ax = 1;
+  } else {
+    a.s_pt = 1;
+    a.s_ax = a.P;
+  }
+  return a;
+}
+
+qmk_status check_ready(qmk_ctx ctx, bool need_coef) {
+  if (ctx->nucl_num <= 0) return fail(ctx, QMK_NOT_SET, "nuclei not set");
+  if (!ctx->has_basis) return fail(ctx, QMK_NOT_SET, "basis not set");
+  if (!ctx->has_points) return fail(ctx, QMK_NOT_SET, "points not set");
+  if (need_coef) {
+    if (!ctx->has_coef) return fail(ctx, QMK_NOT_SET, "MO coefficients not set");
+    if (ctx->C.size() != static_cast<size_t>(ctx->mo_num * ctx->ao_num))
+      return fail(ctx, QMK_NOT_SET, "MO coefficients do not match the basis (ao_num changed)");
+  }
+  return QMK_OK;
+}
+
+// provide(ao_vgl): recompute the AO array iff its time stamp is stale.
+qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
+  qmk_status st = ensure_tables(ctx);
+  if (st != QMK_OK) return st;
+  const int f32 = ctx->f32_storage() ? 1 : 0;
+  const int64_t Pp = round_up(ctx->P(), kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
+  if (ctx->ao_date == ctx->date && ctx->ao_f32 == f32 && ctx->ao_Pp == Pp && ctx->ao_Kp == Kp)
+    return QMK_OK;
+  if (ctx->ao_Pp != Pp || ctx->ao_Kp != Kp || ctx->ao_f32 != f32 || !ctx->ao.p) {
+    const size_t bytes = static_cast<size_t>(Kp * 5 * Pp) * (f32 ? 4 : 8);
+    ctx->ao.release();
+    QMK_HIP(ctx, ctx->ao.ensure(bytes), "alloc AO array");
+    // padding rows (AO >= ao_num, point >= P) stay zero for the contractions
+    QMK_HIP(ctx, hipMemsetAsync(ctx->ao.p, 0, bytes, s), "clear AO array");
+    ctx->ao_Pp = Pp;
+    ctx->ao_Kp = Kp;
+    ctx->ao_f32 = f32;
+  }
+  AoOut o{ctx->ao.p, 5 * Pp, Pp, 1};
+  {
+    LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
+    QMK_HIP(ctx, launch_ao_vgl(ctx->tab, point_args(ctx), o, f32, f32, s), "AO kernel");
+  }
+  ctx->ao_date = ctx->date;
+  return QMK_OK;
+}
+
+Prec gemm_prec(qmk_ctx ctx) {
+  return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16x3);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* qmk_status_string(qmk_status st) {
+  switch (st) {
+    case QMK_OK: return "QMK_OK";
+    case QMK_INVALID_CONTEXT: return "QMK_INVALID_CONTEXT";
+    case QMK_NOT_SET: return "QMK_NOT_SET";
+    case QMK_SIZE: return "QMK_SIZE";
+    case QMK_OUT_OF_MEMORY: return "QMK_OUT_OF_MEMORY";
+    case QMK_HIP_ERROR: return "QMK_HIP_ERROR";
+    case QMK_NONFINITE: return "QMK_NONFINITE";
+    case QMK_UNSUPPORTED: return "QMK_UNSUPPORTED";
+    default: break;
+  }
+  if (st > QMK_INVALID_ARG_BASE && st < QMK_INVALID_ARG_BASE + 100) return "QMK_INVALID_ARG";
+  return "QMK_UNKNOWN_STATUS";
+}
+
+const char* qmk_last_error(qmk_ctx ctx) {
+  if (ctx == nullptr) return g_create_error.c_str();
+  if (!valid_ctx(ctx)) return "invalid context";
+  return ctx->err.c_str();
+}
+
+qmk_status qmk_ctx_create(qmk_ctx* out, int32_t hip_device) {
+  if (out == nullptr) {
+    g_create_error = "argument 1: NULL output pointer";
+    return QMK_INVALID_ARG_BASE + 1;
+  }
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || hip_device < 0 || hip_device >= n) {
+    g_create_error = std::string("argument 2: no HIP device ") + std::to_string(hip_device) +
+                     (e != hipSuccess ? std::string(" (") + hipGetErrorString(e) + ")" : "");
+    return e != hipSuccess ? QMK_HIP_ERROR : QMK_INVALID_ARG_BASE + 2;
+  }
+  qmk_ctx c = new (std::nothrow) qmk_ctx_s();
+  if (!c) {
+    g_create_error = "out of host memory";
+    return QMK_OUT_OF_MEMORY;
+  }
+  c->device = hip_device;
+  *out = c;
+  return QMK_OK;
+}
+
+qmk_status qmk_ctx_destroy(qmk_ctx ctx) {
+  QMK_CHECK_CTX(ctx);
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->magic = 0;
+    delete ctx;
+  }
+  return QMK_OK;
+}
+
+qmk_status qmk_set_precision(qmk_ctx ctx, int32_t bits, int32_t mode) {
+  QMK_CHECK_CTX(ctx);
+  if (bits < 2 || bits > 53) return bad_arg(ctx, 2, "bits must be in 2..53");
+  if (mode != QMK_FP64 && mode != QMK_MIXED_F32 && mode != QMK_MIXED_BF16X3)
+    return bad_arg(ctx, 3, "unknown precision mode");
+  ctx->bits = bits;
+  ctx->mode = mode;
+  ++ctx->date;
+  return QMK_OK;
+}
+
+qmk_status qmk_set_nucleus(qmk_ctx ctx, int64_t nucl_num, const double* coord) {
+  QMK_CHECK_CTX(ctx);
+  if (nucl_num < 1 || nucl_num > (1 << 24)) return bad_arg(ctx, 2, "nucl_num must be >= 1");
+  if (!coord) return bad_arg(ctx, 3, "NULL coordinates");
+  if (ctx->has_basis && nucl_num != ctx->nucl_num)
+    return bad_arg(ctx, 2, "number of nuclei changed while a basis is set");
+  for (int64_t i = 0; i < 3 * nucl_num; ++i)
+    if (!std::isfinite(coord[i])) return fail(ctx, QMK_NONFINITE, "non-finite nuclear coordinate");
+  ctx->nucl.assign(coord, coord + 3 * nucl_num);
+  ctx->nucl_num = nucl_num;
+  ctx->tables_dirty = true;
+  ++ctx->date;
+  return QMK_OK;
+}
+
+qmk_status qmk_set_basis(qmk_ctx ctx, int64_t shell_num, int64_t prim_num,
+                         const int64_t* shell_nucleus, const int32_t* shell_ang_mom,
+                         const int64_t* shell_prim_offset, const double* exponent,
+                         const double* coefficient, const double* prim_factor,
+                         const double* shell_factor, const double* ao_factor) {
+  QMK_CHECK_CTX(ctx);
+  if (ctx->nucl_num <= 0) return fail(ctx, QMK_NOT_SET, "set the nuclei before the basis");
+  if (shell_num < 1 || shell_num > (1 << 24)) return bad_arg(ctx, 2, "shell_num must be >= 1");
+  if (prim_num < shell_num || prim_num > (1 << 26))
+    return bad_arg(ctx, 3, "prim_num must be >= shell_num");
+  if (!shell_nucleus) return bad_arg(ctx, 4, "NULL");
+  if (!shell_ang_mom) return bad_arg(ctx, 5, "NULL");
+  if (!shell_prim_offset) return bad_arg(ctx, 6, "NULL");
+  if (!exponent) return bad_arg(ctx, 7, "NULL");
+  if (!coefficient) return bad_arg(ctx, 8, "NULL");
+  int64_t ao_num = 0;
+  for (int64_t s = 0; s < shell_num; ++s) {
+    if (shell_nucleus[s] < 0 || shell_nucleus[s] >= ctx->nucl_num)
+      return bad_arg(ctx, 4, "shell " + std::to_string(s) + " refers to a missing nucleus");
+    if (shell_ang_mom[s] < 0 || shell_ang_mom[s] > kMaxL)
+      return bad_arg(ctx, 5, "angular momentum must be in 0..3");
+    ao_num += n_cart(shell_ang_mom[s]);
+  }
+  if (shell_prim_offset[0] != 0 || shell_prim_offset[shell_num] != prim_num)
+    return bad_arg(ctx, 6, "offsets must start at 0 and end at prim_num");
+  for (int64_t s = 0; s < shell_num; ++s)
+    if (shell_prim_offset[s + 1] <= shell_prim_offset[s])
+      return bad_arg(ctx, 6, "every shell needs at least one primitive");
+  for (int64_t k = 0; k < prim_num; ++k) {
+    if (!std::isfinite(exponent[k]) || !std::isfinite(coefficient[k]))
+      return fail(ctx, QMK_NONFINITE, "non-finite exponent or coefficient");
+    if (!(exponent[k] > 0.0)) return bad_arg(ctx, 7, "exponents must be > 0");
+    if (prim_factor && !std::isfinite(prim_factor[k]))
+      return fail(ctx, QMK_NONFINITE, "non-finite primitive factor");
+  }
+  if (shell_factor)
+    for (int64_t s = 0; s < shell_num; ++s)
+      if (!std::isfinite(shell_factor[s])) return fail(ctx, QMK_NONFINITE, "non-finite shell factor");
+  if (ao_factor)
+    for (int64_t k = 0; k < ao_num; ++k)
+      if (!std::isfinite(ao_factor[k])) return fail(ctx, QMK_NONFINITE, "non-finite AO factor");
+
+  ctx->sh_nuc.assign(shell_nucleus, shell_nucleus + shell_num);
+  ctx->sh_l.assign(shell_ang_mom, shell_ang_mom + shell_num);
+  ctx->sh_off.assign(shell_prim_offset, shell_prim_offset + shell_num + 1);
+  ctx->expo.assign(exponent, exponent + prim_num);
+  ctx->coef.assign(coefficient, coefficient + prim_num);
+  ctx->pf.resize(prim_num);
+  ctx->sf.resize(shell_num);
+  ctx->af.resize(ao_num);
+  for (int64_t s = 0; s < shell_num; ++s) {
+    const int l = shell_ang_mom[s];
+    for (int64_t k = shell_prim_offset[s]; k < shell_prim_offset[s + 1]; ++k)
+      ctx->pf[k] = prim_factor ? prim_factor[k] : 1.0 / std::sqrt(axis_norm2(l, 2.0 * exponent[k]));
+    if (shell_factor) {
+      ctx->sf[s] = shell_factor[s];
+    } else {
+      double ovl = 0.0;
+      for (int64_t k = shell_prim_offset[s]; k < shell_prim_offset[s + 1]; ++k)
+        for (int64_t q = shell_prim_offset[s]; q < shell_prim_offset[s + 1]; ++q)
+          ovl += coefficient[k] * ctx->pf[k] * coefficient[q] * ctx->pf[q] *
+                 axis_norm2(l, exponent[k] + exponent[q]);
+      if (!(ovl > 0.0) || !std::isfinite(ovl))
+        return bad_arg(ctx, 8, "shell " + std::to_string(s) + " has zero norm");
+      ctx->sf[s] = 1.0 / std::sqrt(ovl);
+    }
+  }
+  {
+    int64_t k = 0;
+    for (int64_t s = 0; s < shell_num; ++s) {
+      const int l = shell_ang_mom[s];
+      for (int a = l; a >= 0; --a)
+        for (int b = l - a; b >= 0; --b, ++k) {
+          const int c = l - a - b;
+          ctx->af[k] = ao_factor ? ao_factor[k]
+                                 : std::sqrt(moment(l, 1.0) * moment(0, 1.0) * moment(0, 1.0) /
+                                             (moment(a, 1.0) * moment(b, 1.0) * moment(c, 1.0)));
+        }
+    }
+  }
+  ctx->shell_num = shell_num;
+  ctx->prim_num = prim_num;
+  ctx->ao_num = ao_num;
+  ctx->has_basis = true;
+  ctx->tables_dirty = true;
+  ctx->coef_dirty = true;
+  ++ctx->date;
+  return QMK_OK;
+}
+
+qmk_status qmk_set_mo_coef(qmk_ctx ctx, int64_t mo_num, int64_t ao_num, const double* coef) {
+  QMK_CHECK_CTX(ctx);
+  if (!ctx->has_basis) return fail(ctx, QMK_NOT_SET, "set the basis before the MO coefficients");
+  if (mo_num < 1 || mo_num > (1 << 24)) return bad_arg(ctx, 2, "mo_num must be >= 1");
+  if (ao_num != ctx->ao_num) return bad_arg(ctx, 3, "ao_num does not match the basis");
+  if (!coef) return bad_arg(ctx, 4, "NULL");
+  for (int64_t i = 0; i < mo_num * ao_num; ++i)
+    if (!std::isfinite(coef[i])) return fail(ctx, QMK_NONFINITE, "non-finite MO coefficient");
+  ctx->C.assign(coef, coef + mo_num * ao_num);
+  ctx->mo_num = mo_num;
+  ctx->has_coef = true;
+  ctx->coef_dirty = true;
+  return QMK_OK;
+}
+
+qmk_status qmk_set_point(qmk_ctx ctx, char transp, int64_t walk_num, int64_t elec_num,
+                         const double* coord, int32_t coord_on_device) {
+  QMK_CHECK_CTX(ctx);
+  if (transp != 'N' && transp != 'T') return bad_arg(ctx, 2, "transp must be 'N' or 'T'");
+  if (walk_num < 1) return bad_arg(ctx, 3, "walk_num must be >= 1");
+  if (elec_num < 1) return bad_arg(ctx, 4, "elec_num must be >= 1");
+  if (walk_num * elec_num > (int64_t(1) << 31)) return bad_arg(ctx, 3, "too many points");
+  if (!coord) return bad_arg(ctx, 5, "NULL");
+  if (coord_on_device != 0 && coord_on_device != 1) return bad_arg(ctx, 6, "must be 0 or 1");
+  const int64_t n = 3 * walk_num * elec_num;
+  if (coord_on_device) {
+    ctx->pts = coord;
+  } else {
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(coord[i])) return fail(ctx, QMK_NONFINITE, "non-finite coordinate");
+    DeviceGuard g(ctx->device);
+    QMK_HIP(ctx, ctx->own_pts.ensure(static_cast<size_t>(n) * sizeof(double)), "alloc points");
+    QMK_HIP(ctx, hipMemcpy(ctx->own_pts.p, coord, n * sizeof(double), hipMemcpyHostToDevice),
+            "upload points");
+    ctx->pts = ctx->own_pts.as<double>();
+  }
+  ctx->transp = transp;
+  ctx->walk_num = walk_num;
+  ctx->elec_num = elec_num;
+  ctx->has_points = true;
+  ++ctx->date;
+  return QMK_OK;
+}
+
+qmk_status qmk_get_dims(qmk_ctx ctx, int64_t* nucl_num, int64_t* ao_num, int64_t* mo_num,
+                        int64_t* walk_num, int64_t* elec_num) {
+  QMK_CHECK_CTX(ctx);
+  if (nucl_num) *nucl_num = ctx->nucl_num;
+  if (ao_num) *ao_num = ctx->ao_num;
+  if (mo_num) *mo_num = ctx->mo_num;
+  if (walk_num) *walk_num = ctx->walk_num;
+  if (elec_num) *elec_num = ctx->elec_num;
+  return QMK_OK;
+}
+
+qmk_status qmk_get_launch_count(qmk_ctx ctx, int64_t* count) {
+  QMK_CHECK_CTX(ctx);
+  if (!count) return bad_arg(ctx, 2, "NULL");
+  *count = ctx->launches;
+  return QMK_OK;
+}
+
+qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable) {
+  QMK_CHECK_CTX(ctx);
+  if (enable != 0 && enable != 1) return bad_arg(ctx, 2, "must be 0 or 1");
+  DeviceGuard g(ctx->device);
+  collect_timing(ctx);
+  if (enable) {
+    for (int k = 0; k < QMK_KERNEL_CLASSES; ++k) {
+      ctx->t_ms[k] = 0.0;
+      ctx->t_n[k] = 0;
+    }
+  }
+  ctx->timing = enable != 0;
+  return QMK_OK;
+}
+
+qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches) {
+  QMK_CHECK_CTX(ctx);
+  if (kernel_class < 0 || kernel_class >= QMK_KERNEL_CLASSES) return bad_arg(ctx, 2, "unknown kernel class");
+  DeviceGuard g(ctx->device);
+  collect_timing(ctx);
+  if (total_ms) *total_ms = ctx->t_ms[kernel_class];
+  if (launches) *launches = ctx->t_n[kernel_class];
+  return QMK_OK;
+}
+
+qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                          void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (!out) return bad_arg(ctx, 2, "NULL");
+  if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
+  qmk_status st = check_ready(ctx, false);
+  if (st != QMK_OK) return st;
+  const int64_t need = ctx->P() * 5 * ctx->ao_num;
+  if (size_max < need)
+    return fail(ctx, QMK_SIZE, "size_max " + std::to_string(size_max) + " < " + std::to_string(need));
+  DeviceGuard g(ctx->device);
+  st = ensure_tables(ctx);
+  if (st != QMK_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  AoOut o{out, 1, ctx->ao_num, 5 * ctx->ao_num};
+  LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
+  QMK_HIP(ctx, launch_ao_vgl(ctx->tab, point_args(ctx), o, dtype == QMK_F32, ctx->f32_storage(), s),
+          "AO kernel");
+  return QMK_OK;
+}
+
+qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                          void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (!out) return bad_arg(ctx, 2, "NULL");
+  if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
+  qmk_status st = check_ready(ctx, true);
+  if (st != QMK_OK) return st;
+  const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
+  if (size_max < P * 5 * N)
+    return fail(ctx, QMK_SIZE, "size_max " + std::to_string(size_max) + " < " + std::to_string(P * 5 * N));
+  if (ctx->mode == QMK_MIXED_BF16X3) return fail(ctx, QMK_UNSUPPORTED, "BF16x3 not built yet");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure_coef(ctx)) != QMK_OK) return st;
+  if ((st = provide_ao(ctx, s)) != QMK_OK) return st;
+  const int64_t Pp = ctx->ao_Pp;
+  GemmArgs ga{};
+  ga.A = ctx->ao.p;
+  ga.sAi = 1;
+  ga.sAl = 5 * Pp;
+  ga.oAc = Pp;
+  ga.B = ctx->d_Ct.p;
+  ga.sBl = ctx->Np;
+  ga.sBj = 1;
+  ga.D = out;
+  ga.sDi = 5 * N;
+  ga.sDj = 1;
+  ga.oDz = N;
+  ga.M = P;
+  ga.N = N;
+  ga.L = K;
+  ga.Lchunk = K;
+  ga.nsplit = 1;
+  ga.nbatch = 5;
+  LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
+  QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, gemm_prec(ctx), ga, 0, dtype == QMK_F32, s),
+          "MO contraction");
+  return QMK_OK;
+}
+
+qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, double* d_coef,
+                              double* d_elec, double* d_nucl, void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (!w) return bad_arg(ctx, 2, "NULL");
+  if (w_dtype != QMK_F64 && w_dtype != QMK_F32) return bad_arg(ctx, 3, "dtype must be QMK_F64 or QMK_F32");
+  qmk_status st = check_ready(ctx, true);
+  if (st != QMK_OK) return st;
+  if (ctx->mode == QMK_MIXED_BF16X3) return fail(ctx, QMK_UNSUPPORTED, "BF16x3 not built yet");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure_coef(ctx)) != QMK_OK) return st;
+  if ((st = provide_ao(ctx, s)) != QMK_OK) return st;
+  const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
+  const int64_t Pp = ctx->ao_Pp, Kp = ctx->Kp, Np = ctx->Np;
+  const int w32 = w_dtype == QMK_F32;
+  const int f32 = ctx->f32_storage() ? 1 : 0;
+  const Prec prec = gemm_prec(ctx);
+
+  if (d_elec || d_nucl) {
+    // Gbar[k][c][p] = sum_n W[p][c][n] C[n][k]
+    if (ctx->gbar_Pp != Pp || ctx->gbar_Kp != Kp || ctx->gbar_f32 != f32 || !ctx->gbar.p) {
+      ctx->gbar.release();
+      QMK_HIP(ctx, ctx->gbar.ensure(static_cast<size_t>(Kp * 5 * Pp) * (f32 ? 4 : 8)), "alloc Gbar");
+      ctx->gbar_Pp = Pp;
+      ctx->gbar_Kp = Kp;
+      ctx->gbar_f32 = f32;
+    }
+    GemmArgs ga{};
+    ga.A = w;
+    ga.sAi = 5 * N;
+    ga.sAl = 1;
+    ga.oAc = N;
+    ga.B = ctx->d_C.p;
+    ga.sBl = Kp;
+    ga.sBj = 1;
+    ga.D = ctx->gbar.p;
+    ga.sDi = 1;
+    ga.sDj = 5 * Pp;
+    ga.oDz = Pp;
+    ga.M = P;
+    ga.N = K;
+    ga.L = N;
+    ga.Lchunk = N;
+    ga.nsplit = 1;
+    ga.nbatch = 5;
+    {
+      LaunchTimer lt(ctx, QMK_KERNEL_GBAR, s);
+      QMK_HIP(ctx, launch_gemm_typed(GemmKind::kGbar, prec, ga, w32, f32, s), "Gbar product");
+    }
+
+    const int64_t n_waves = (P + 255) / 256 * 4;
+    QMK_HIP(ctx, ctx->ws_nuc.ensure(static_cast<size_t>(n_waves * ctx->nucl_dev * 3) * 8), "alloc nuc partials");
+    double* elec_out = d_elec;
+    int64_t gstride = 0;
+    if (ctx->n_groups > 1 || !d_elec) {
+      QMK_HIP(ctx, ctx->ws_elec.ensure(static_cast<size_t>(ctx->n_groups * P * 3) * 8), "alloc elec partials");
+      elec_out = ctx->ws_elec.as<double>();
+      gstride = P * 3;
+    }
+    int64_t nw = 0;
+    {
+      LaunchTimer lt(ctx, QMK_KERNEL_AO_ADJOINT, s);
+      QMK_HIP(ctx, launch_ao_adjoint(ctx->tab, point_args(ctx), ctx->gbar.p, f32, 5 * Pp, Pp, elec_out,
+                                     gstride, ctx->ws_nuc.as<double>(), &nw, s),
+              "AO adjoint kernel");
+    }
+    if (d_elec && elec_out != d_elec) {
+      LaunchTimer lt(ctx, QMK_KERNEL_REDUCE, s);
+      QMK_HIP(ctx, launch_reduce_splits(elec_out, ctx->n_groups, P, 3, 3, P * 3, d_elec, 3, s),
+              "reduce electron gradient");
+    }
+    if (d_nucl) {
+      LaunchTimer lt(ctx, QMK_KERNEL_REDUCE, s);
+      QMK_HIP(ctx, launch_reduce_nuc(ctx->ws_nuc.as<double>(), nw, ctx->nucl_dev,
+                                     ctx->d_devof.as<int32_t>(), static_cast<int32_t>(ctx->nucl_num),
+                                     d_nucl, s),
+              "reduce nuclear gradient");
+    }
+  }
+  if (d_coef) {
+    // dC[n][k] = sum_{c, p} W[p][c][n] ao[k][c][p], split over (c, point chunk)
+    const int64_t tiles = ((N + 127) / 128) * ((K + 127) / 128);
+    int64_t nsplit = std::max<int64_t>(1, (2048 + tiles * 5 - 1) / (tiles * 5));
+    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, (P + 255) / 256));
+    int64_t chunk = (P + nsplit - 1) / nsplit;
+    chunk = round_up(chunk, 16);
+    nsplit = (P + chunk - 1) / chunk;
+    const int64_t nz = 5 * nsplit;
+    QMK_HIP(ctx, ctx->ws_dc.ensure(static_cast<size_t>(nz * Np * Kp) * 8), "alloc dC partials");
+    GemmArgs ga{};
+    ga.A = w;
+    ga.sAi = 1;
+    ga.sAl = 5 * N;
+    ga.oAc = N;
+    ga.oAs = chunk * 5 * N;
+    ga.B = ctx->ao.p;
+    ga.sBl = 1;
+    ga.sBj = 5 * Pp;
+    ga.oBc = Pp;
+    ga.oBs = chunk;
+    ga.D = ctx->ws_dc.p;
+    ga.sDi = Kp;
+    ga.sDj = 1;
+    ga.oDz = Np * Kp;
+    ga.M = N;
+    ga.N = K;
+    ga.L = P;
+    ga.Lchunk = chunk;
+    ga.nsplit = static_cast<int32_t>(nsplit);
+    ga.nbatch = 5;
+    {
+      LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);
+      QMK_HIP(ctx, launch_gemm_typed(GemmKind::kDcoef, prec, ga, w32, 0, s), "dC product");
+    }
+    {
+      LaunchTimer lt(ctx, QMK_KERNEL_REDUCE, s);
+      QMK_HIP(ctx, launch_reduce_splits(ctx->ws_dc.as<double>(), nz, N, K, Kp, Np * Kp, d_coef, K, s),
+              "reduce dC");
+    }
+  }
+  return QMK_OK;
+}
+
+qmk_status qmk_batch_create(qmk_batch* out, const qmk_ctx* ctxs, int64_t n) {
+  (void)out;
+  (void)ctxs;
+  (void)n;
+  return QMK_UNSUPPORTED;
+}
+qmk_status qmk_batch_destroy(qmk_batch batch) {
+  (void)batch;
+  return QMK_UNSUPPORTED;
+}
+qmk_status qmk_batch_run(qmk_batch batch, void* const* outs, int32_t dtype, const void* const* ws,
+                         double* const* d_coefs, double* const* d_elecs, double* const* d_nucls,
+                         void* hip_stream) {
+  (void)batch; (void)outs; (void)dtype; (void)ws; (void)d_coefs; (void)d_elecs; (void)d_nucls;
+  (void)hip_stream;
+  return QMK_UNSUPPORTED;
+}
+
+}  // extern "C"

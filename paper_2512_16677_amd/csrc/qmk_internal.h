@@ -1,0 +1,114 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+// Not part of the public ABI (include/qmk.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qmk {
+
+constexpr int kMaxL = 3;            // highest angular momentum supported (f)
+constexpr int kGroupMaxPrim = 2048; // primitives staged in LDS per nucleus group
+constexpr int kGroupMaxShell = 512;
+constexpr int kGroupMaxNuc = 128;
+constexpr int kPointPad = 256;      // points are padded to a multiple of this
+constexpr int kAoPad = 128;         // AOs (K) padded to a multiple of this
+constexpr int kMoPad = 128;         // MOs (N) padded to a multiple of this
+
+// One nucleus as the AO kernels see it.  gmin = smallest exponent of all its
+// primitives: if gmin*u >= T for every point of a wavefront, the whole
+// nucleus is skipped (the per-nucleus radius test, in squared form).
+struct NucDev {
+  double x, y, z, gmin;
+  int32_t sh_begin, sh_end;  // shells, indices local to the nucleus' group
+  int32_t orig;              // index of the nucleus in the caller's array
+  int32_t pad1;
+};
+
+// One shell: its AOs are ao_off .. ao_off + (l+1)(l+2)/2 - 1; its primitives
+// p_begin .. p_end-1 are sorted by ascending exponent.
+struct ShellDev {
+  int32_t ao_off, l, p_begin, p_end;
+};
+
+// Contiguous range of nuclei whose shells and primitives fit in LDS.
+struct NucGroup {
+  int32_t nuc_begin, nuc_end, sh_begin, sh_end, p_begin, p_end, pad0, pad1;
+};
+
+// Primitive table entry: exponent gamma and folded coefficient a*f*N_s.
+struct PrimDev {
+  double gamma, coef;
+};
+
+struct AoTables {
+  const NucDev* nuc;
+  const ShellDev* shell;
+  const PrimDev* prim;
+  const double* ao_factor;  // M_n per AO
+  const NucGroup* group;
+  int32_t n_groups;
+  int32_t ao_num;
+  double T;                 // cutoff on gamma*u: (B-1) ln 2
+  int32_t smem_bytes;       // LDS needed by the largest group
+  int32_t nucl_dev;         // number of nuclei with at least one shell
+};
+
+struct PointArgs {
+  const double* coord;      // device
+  int64_t s_pt, s_ax;       // coord of point p, axis i: coord[p*s_pt + i*s_ax]
+  int64_t P;                // number of points
+};
+
+// Strided AO output: element (k, c, p) at out[k*sK + c*sC + p*sP].
+struct AoOut {
+  void* out;
+  int64_t sK, sC, sP;
+};
+
+// Generic strided batched GEMM  D(i,j) = sum_l A(i,l) B(l,j)  for a batch
+// index z = c*nsplit + s:
+//   A(i,l) = A[c*oAc + s*oAs + i*sAi + l*sAl]     (l restricted to split s)
+//   B(l,j) = B[c*oBc + s*oBs + l*sBl + j*sBj]
+//   D(i,j) = D[z*oDz + i*sDi + j*sDj]
+// Loads outside i < M, l < L_s, j < N read zero; stores are guarded the same
+// way.  L_s = min(Lchunk, L - s*Lchunk).
+struct GemmArgs {
+  const void* A;
+  int64_t sAi, sAl, oAc, oAs;
+  const void* B;
+  int64_t sBl, sBj, oBc, oBs;
+  void* D;
+  int64_t sDi, sDj, oDz;
+  int64_t M, N, L, Lchunk;
+  int32_t nsplit, nbatch;   // gridDim.y = nbatch * nsplit
+};
+
+enum class GemmKind { kForward, kGbar, kDcoef };
+enum class Prec { kF64, kF32, kBF16x3 };
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
+                         int fp32_compute, hipStream_t s);
+hipError_t launch_gemm_typed(GemmKind kind, Prec prec, const GemmArgs& g, int w_is_f32,
+                             int out_is_f32, hipStream_t s);
+hipError_t launch_reduce_splits(const double* ws, int64_t nz, int64_t rows, int64_t cols,
+                                int64_t ld_ws, int64_t z_stride, double* out, int64_t ld_out,
+                                hipStream_t s);
+// Adjoint AO stage.  gbar: [ao][5][point] with strides (sK, sC, 1).
+// elec_out + blockIdx.y*elec_group_stride receives sum_k t[p][k][:] of the
+// group's nuclei as [point][3]; nuc_partial[(wave*nucl_dev + a)*3 + i]
+// receives minus the wave's sum over its points for device nucleus a.
+// Returns the number of waves through *n_waves.
+hipError_t launch_ao_adjoint(const AoTables& t, const PointArgs& pts, const void* gbar,
+                             int gbar_is_f32, int64_t sK, int64_t sC, double* elec_out,
+                             int64_t elec_group_stride, double* nuc_partial, int64_t* n_waves,
+                             hipStream_t s);
+// d_nucl[A][i] = sum_w nuc_partial[(w*nucl_dev + dev_of[A])*3 + i], or 0 for
+// nuclei without shells (dev_of[A] < 0).
+hipError_t launch_reduce_nuc(const double* nuc_partial, int64_t n_waves, int32_t nucl_dev,
+                             const int32_t* dev_of, int32_t nucl_num, double* d_nucl,
+                             hipStream_t s);
+
+}  // namespace qmk
