@@ -183,6 +183,17 @@ enum {
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
 
+/* Tile shapes of the MFMA products (QMK_KERNEL_MO, QMK_KERNEL_GBAR,
+ * QMK_KERNEL_DCOEF).  By default the library's autotuner times every tile
+ * shape on the first call of each distinct product size and keeps the
+ * fastest (process-wide; QMK_TUNE_CACHE=<file> persists the choices,
+ * QMK_TUNE=0 picks by least padded work without timing).  qmk_set_tile
+ * forces tile `tile` (0 .. count-1) for one product class of this context,
+ * or restores the autotuned choice with -1; every tile gives the same
+ * result up to rounding. */
+qmk_status qmk_get_tile_count(qmk_ctx ctx, int32_t* count);
+qmk_status qmk_set_tile(qmk_ctx ctx, int32_t kernel_class, int32_t tile);
+
 /* ---------------------------------------------------------------------- */
 /* Batches: many independent contexts (Section 2.2) -- molecules of uneven
  * sizes, each with its own walkers -- evaluated together.  The contexts

@@ -44,6 +44,7 @@ EXPORTED = [
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
+    "qmk_get_tile_count", "qmk_set_tile",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_run",
 ]
 
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_launch_count": ([P, P], I32),
         "qmk_set_timing": ([P, I32], I32),
         "qmk_get_timing": ([P, I32, P, P], I32),
+        "qmk_get_tile_count": ([P, P], I32),
+        "qmk_set_tile": ([P, I32, I32], I32),
         "qmk_batch_create": ([P, P, I64], I32),
         "qmk_batch_destroy": ([P], I32),
         "qmk_batch_run": ([P, P, I32, P, P, P, P, P], I32),
@@ -225,6 +228,15 @@ class Context:
             self._check(self._lib.qmk_get_timing(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
             out[name] = {"ms": ms.value, "launches": n.value}
         return out
+
+    def tile_count(self) -> int:
+        v = ctypes.c_int32()
+        self._check(self._lib.qmk_get_tile_count(self._h, ctypes.byref(v)))
+        return v.value
+
+    def set_tile(self, kernel: str, tile: int):
+        """Force MFMA tile `tile` for kernel class 'mo', 'gbar' or 'dcoef' (-1: autotune)."""
+        self._check(self._lib.qmk_set_tile(self._h, KERNEL_CLASSES.index(kernel), int(tile)))
 
     def _out(self, out, shape, dtype):
         import torch

@@ -19,103 +19,63 @@
 namespace qmk {
 namespace {
 
-template <typename GT>
-__device__ __forceinline__ double ldg(const GT* p) { return static_cast<double>(*p); }
-
-// Contracts the third-order AO derivatives of one shell with Gbar.
+// Contracts the third-order AO derivatives of one shell with Gbar.  l is
+// wave-uniform and the Cartesian components run in a uniform loop.
 //   d_i chi     = M (P_i g0 + 2 d_i P g1)
 //   d_i d_j chi = M (P_ij g0 + 2 (d_j P_i + d_i P_j) g1 + 2 delta_ij P g1
 //                    + 4 d_i d_j P g2)
-//   d_i lap chi = M (lapP_i g0 + (2 d_i lapP + (4L+6) P_i) g1
-//                    + ((8L+20) d_i P + 4 u P_i) g2 + 8 u d_i P g3)
-template <int L, typename GT>
-__device__ __forceinline__ void shell_adjoint(double dx, double dy, double dz, double u, double g0,
-                                              double g1, double g2, double g3,
+//   d_i lap chi = M (lapP_i g0 + (2 d_i lapP + (4l+6) P_i) g1
+//                    + ((8l+20) d_i P + 4 u P_i) g2 + 8 u d_i P g3)
+// Summed against Gbar as  sum_j Gj d_i d_j chi  =  M (g0 (Hess P . G)_i
+//   + 2 g1 (P_i (G.d) + d_i (G.grad P) + G_i P) + 4 g2 d_i P (G.d)).
+template <typename GT>
+__device__ __forceinline__ void shell_adjoint(int l, double dx, double dy, double dz, double u,
+                                              double g0, double g1, double g2, double g3,
                                               const double* __restrict__ M,
                                               const GT* __restrict__ gb, int64_t sK, int64_t sC,
                                               double& tx, double& ty, double& tz) {
-  // D[axis][m][e]: m-th derivative of d^e, for e <= L, m <= 3.
-  double px[L + 1], py[L + 1], pz[L + 1];
-  px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-  for (int i = 1; i <= L; ++i) {
-    px[i] = px[i - 1] * dx;
-    py[i] = py[i - 1] * dy;
-    pz[i] = pz[i - 1] * dz;
-  }
-  const double d[3] = {dx, dy, dz};
+  const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
+  const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
+  const double c1 = 4.0 * l + 6.0, c2 = 8.0 * l + 20.0;
+  const double tg1 = 2.0 * g1, fg2 = 4.0 * g2, eug3 = 8.0 * u * g3, fug2 = 4.0 * u * g2;
   int idx = 0;
-#pragma unroll
-  for (int a = L; a >= 0; --a) {
-#pragma unroll
-    for (int b = L - a; b >= 0; --b, ++idx) {
-      const int c = L - a - b;
-      const int e[3] = {a, b, c};
-      const double* pw[3] = {px, py, pz};
-      double D[3][4];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int n = e[ax] - m;
-          double coef = 1.0;
-#pragma unroll
-          for (int q = 0; q < m; ++q) coef *= static_cast<double>(e[ax] - q);
-          D[ax][m] = n >= 0 ? coef * pw[ax][n >= 0 ? n : 0] : 0.0;
-        }
-      }
-      const double P = D[0][0] * D[1][0] * D[2][0];
-      const double Pi[3] = {D[0][1] * D[1][0] * D[2][0], D[0][0] * D[1][1] * D[2][0],
-                            D[0][0] * D[1][0] * D[2][1]};
-      double Pij[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          int m[3] = {0, 0, 0};
-          m[i] += 1;
-          m[j] += 1;
-          Pij[i][j] = D[0][m[0]] * D[1][m[1]] * D[2][m[2]];
-        }
-      const double lapP = Pij[0][0] + Pij[1][1] + Pij[2][2];
-      double glP[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        double sacc = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          int m[3] = {0, 0, 0};
-          m[i] += 1;
-          m[j] += 2;
-          sacc += D[0][m[0]] * D[1][m[1]] * D[2][m[2]];
-        }
-        glP[i] = sacc;
-      }
+#pragma unroll 1
+  for (int a = l; a >= 0; --a) {
+#pragma unroll 1
+    for (int b = l - a; b >= 0; --b, ++idx) {
+      const int c = l - a - b;
+      const AxisD X = axis_derivs(a, dx, dx2, dx3);
+      const AxisD Y = axis_derivs(b, dy, dy2, dy3);
+      const AxisD Z = axis_derivs(c, dz, dz2, dz3);
       const GT* q = gb + idx * sK;
-      const double G0 = ldg(q), G1 = ldg(q + sC), G2 = ldg(q + 2 * sC), G3 = ldg(q + 3 * sC),
-                   G4 = ldg(q + 4 * sC);
-      const double Gj[3] = {G1, G2, G3};
+      const double G0 = static_cast<double>(q[0]), G1 = static_cast<double>(q[sC]),
+                   G2 = static_cast<double>(q[2 * sC]), G3 = static_cast<double>(q[3 * sC]),
+                   G4 = static_cast<double>(q[4 * sC]);
+      const double P = X.v0 * Y.v0 * Z.v0;
+      const double Px = X.v1 * Y.v0 * Z.v0, Py = X.v0 * Y.v1 * Z.v0, Pz = X.v0 * Y.v0 * Z.v1;
+      const double Pxx = X.v2 * Y.v0 * Z.v0, Pyy = X.v0 * Y.v2 * Z.v0, Pzz = X.v0 * Y.v0 * Z.v2;
+      const double Pxy = X.v1 * Y.v1 * Z.v0, Pxz = X.v1 * Y.v0 * Z.v1, Pyz = X.v0 * Y.v1 * Z.v1;
+      const double lapP = Pxx + Pyy + Pzz;
+      const double lPx = X.v3 * Y.v0 * Z.v0 + X.v1 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
+      const double lPy = Y.v3 * X.v0 * Z.v0 + Y.v1 * (X.v2 * Z.v0 + X.v0 * Z.v2);
+      const double lPz = Z.v3 * X.v0 * Y.v0 + Z.v1 * (X.v2 * Y.v0 + X.v0 * Y.v2);
+      const double Gd = G1 * dx + G2 * dy + G3 * dz;
+      const double GdP = G1 * Px + G2 * Py + G3 * Pz;
+      const double HGx = Pxx * G1 + Pxy * G2 + Pxz * G3;
+      const double HGy = Pxy * G1 + Pyy * G2 + Pyz * G3;
+      const double HGz = Pxz * G1 + Pyz * G2 + Pzz * G3;
       const double m = M[idx];
-      double t[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const double gi = Pi[i] * g0 + 2.0 * d[i] * P * g1;
-        double hs = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          double h = Pij[i][j] * g0 + 2.0 * (d[j] * Pi[i] + d[i] * Pi[j]) * g1 +
-                     4.0 * d[i] * d[j] * P * g2;
-          if (i == j) h += 2.0 * P * g1;
-          hs += Gj[j] * h;
-        }
-        const double gl = glP[i] * g0 + (2.0 * d[i] * lapP + (4.0 * L + 6.0) * Pi[i]) * g1 +
-                          ((8.0 * L + 20.0) * d[i] * P + 4.0 * u * Pi[i]) * g2 +
-                          8.0 * u * d[i] * P * g3;
-        t[i] = m * (G0 * gi + hs + G4 * gl);
-      }
-      tx += t[0];
-      ty += t[1];
-      tz += t[2];
+      // per direction i: G0 d_i chi + sum_j Gj d_i d_j chi + G4 d_i lap chi (over M)
+      const double Pg = P * Gd * fg2, Pe = P * eug3, Pl = P * c2 * g2;
+      tx += m * (G0 * (Px * g0 + dx * P * tg1) + g0 * HGx + tg1 * (Px * Gd + dx * GdP + G1 * P) +
+                 dx * Pg + G4 * (lPx * g0 + (2.0 * dx * lapP + c1 * Px) * g1 + dx * Pl + fug2 * Px +
+                                 dx * Pe));
+      ty += m * (G0 * (Py * g0 + dy * P * tg1) + g0 * HGy + tg1 * (Py * Gd + dy * GdP + G2 * P) +
+                 dy * Pg + G4 * (lPy * g0 + (2.0 * dy * lapP + c1 * Py) * g1 + dy * Pl + fug2 * Py +
+                                 dy * Pe));
+      tz += m * (G0 * (Pz * g0 + dz * P * tg1) + g0 * HGz + tg1 * (Pz * Gd + dz * GdP + G3 * P) +
+                 dz * Pg + G4 * (lPz * g0 + (2.0 * dz * lapP + c1 * Pz) * g1 + dz * Pl + fug2 * Pz +
+                                 dz * Pe));
     }
   }
 }
@@ -181,16 +141,9 @@ __global__ __launch_bounds__(256) void ao_adjoint_kernel(AoTables t, PointArgs p
             g3 -= pr.gamma * pr.gamma * ge;
           }
         }
-        if (near) {
-          const GT* q = gb_p + sh.ao_off * sK;
-          const double* M = t.ao_factor + sh.ao_off;
-          switch (sh.l) {
-            case 0: shell_adjoint<0>(dx, dy, dz, u, g0, g1, g2, g3, M, q, sK, sC, tx, ty, tz); break;
-            case 1: shell_adjoint<1>(dx, dy, dz, u, g0, g1, g2, g3, M, q, sK, sC, tx, ty, tz); break;
-            case 2: shell_adjoint<2>(dx, dy, dz, u, g0, g1, g2, g3, M, q, sK, sC, tx, ty, tz); break;
-            default: shell_adjoint<3>(dx, dy, dz, u, g0, g1, g2, g3, M, q, sK, sC, tx, ty, tz); break;
-          }
-        }
+        if (near)
+          shell_adjoint(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2, g3,
+                        t.ao_factor + sh.ao_off, gb_p + sh.ao_off * sK, sK, sC, tx, ty, tz);
       }
     }
     ex += tx;
@@ -212,17 +165,26 @@ __global__ __launch_bounds__(256) void ao_adjoint_kernel(AoTables t, PointArgs p
   }
 }
 
-__global__ void reduce_nuc_kernel(const double* __restrict__ part, int64_t n_waves,
-                                  int32_t nucl_dev, const int32_t* __restrict__ dev_of,
-                                  int32_t nucl_num, double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nucl_num * 3) return;
+// One block per output entry: strided partial sums then a fixed-order tree
+// in LDS, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void reduce_nuc_kernel(const double* __restrict__ part,
+                                                         int64_t n_waves, int32_t nucl_dev,
+                                                         const int32_t* __restrict__ dev_of,
+                                                         double* __restrict__ out) {
+  __shared__ double red[256];
+  const int e = blockIdx.x;
   const int A = e / 3, i = e - 3 * A;
   const int a = dev_of[A];
   double acc = 0.0;
   if (a >= 0)
-    for (int64_t w = 0; w < n_waves; ++w) acc += part[(w * nucl_dev + a) * 3 + i];
-  out[e] = acc;
+    for (int64_t w = threadIdx.x; w < n_waves; w += 256) acc += part[(w * nucl_dev + a) * 3 + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = red[0];
 }
 
 }  // namespace
@@ -252,8 +214,8 @@ hipError_t launch_reduce_nuc(const double* nuc_partial, int64_t n_waves, int32_t
                              hipStream_t s) {
   const int n = nucl_num * 3;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_nuc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, nuc_partial,
-                     n_waves, nucl_dev, dev_of, nucl_num, d_nucl);
+  hipLaunchKernelGGL(reduce_nuc_kernel, dim3(n), dim3(256), 0, s, nuc_partial, n_waves, nucl_dev,
+                     dev_of, d_nucl);
   return hipGetLastError();
 }
 

@@ -21,50 +21,41 @@ namespace {
 template <typename T>
 __device__ __forceinline__ void st(T* p, double v) { *p = static_cast<T>(v); }
 
-// Stores value, gradient and Laplacian of the (L+1)(L+2)/2 Cartesian AOs of
-// one shell for this lane's point.
+// Stores value, gradient and Laplacian of the (l+1)(l+2)/2 Cartesian AOs of
+// one shell for this lane's point.  l is wave-uniform; the components run in
+// a uniform loop, one at a time, which keeps register pressure low.
 //   chi      = M P g0
 //   d_i chi  = M (d_i P g0 + 2 d_i P g1)          (d_i: displacement)
-//   lap chi  = M (lap P g0 + (4L+6) P g1 + 4 u P g2)
-template <int L, typename OutT>
-__device__ __forceinline__ void shell_vgl(double dx, double dy, double dz, double u, double g0,
-                                          double g1, double g2, const double* __restrict__ M,
-                                          OutT* __restrict__ o, int64_t sK, int64_t sC, bool store) {
-  double px[L + 2], py[L + 2], pz[L + 2];
-  px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-  for (int i = 1; i <= L; ++i) {
-    px[i] = px[i - 1] * dx;
-    py[i] = py[i - 1] * dy;
-    pz[i] = pz[i - 1] * dz;
-  }
-  const double c1 = (4.0 * L + 6.0) * g1;
-  const double c2 = 4.0 * u * g2;
+//   lap chi  = M (lap P g0 + (4l+6) P g1 + 4 u P g2)
+template <typename OutT>
+__device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz, double u,
+                                          double g0, double g1, double g2,
+                                          const double* __restrict__ M, OutT* __restrict__ o,
+                                          int64_t sK, int64_t sC) {
+  const double lapr = (4.0 * l + 6.0) * g1 + 4.0 * u * g2;
+  const double tg1 = 2.0 * g1;
+  const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
+  const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
   int idx = 0;
-#pragma unroll
-  for (int a = L; a >= 0; --a) {
-#pragma unroll
-    for (int b = L - a; b >= 0; --b, ++idx) {
-      const int c = L - a - b;
-      const double xa = px[a], yb = py[b], zc = pz[c];
-      const double P = xa * yb * zc;
-      const double Px = a > 0 ? a * px[a > 0 ? a - 1 : 0] * yb * zc : 0.0;
-      const double Py = b > 0 ? b * xa * py[b > 0 ? b - 1 : 0] * zc : 0.0;
-      const double Pz = c > 0 ? c * xa * yb * pz[c > 0 ? c - 1 : 0] : 0.0;
-      double lapP = 0.0;
-      if (a > 1) lapP += a * (a - 1) * px[a > 1 ? a - 2 : 0] * yb * zc;
-      if (b > 1) lapP += b * (b - 1) * xa * py[b > 1 ? b - 2 : 0] * zc;
-      if (c > 1) lapP += c * (c - 1) * xa * yb * pz[c > 1 ? c - 2 : 0];
+#pragma unroll 1
+  for (int a = l; a >= 0; --a) {
+#pragma unroll 1
+    for (int b = l - a; b >= 0; --b, ++idx) {
+      const int c = l - a - b;
+      const AxisD X = axis_derivs(a, dx, dx2, dx3);
+      const AxisD Y = axis_derivs(b, dy, dy2, dy3);
+      const AxisD Z = axis_derivs(c, dz, dz2, dz3);
+      const double yz = Y.v0 * Z.v0;
+      const double P = X.v0 * yz;
+      const double lapP = X.v2 * yz + X.v0 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
       const double m = M[idx];
-      const double tg = 2.0 * P * g1;
-      if (store) {
-        OutT* q = o + idx * sK;
-        st(q, m * P * g0);
-        st(q + sC, m * (Px * g0 + dx * tg));
-        st(q + 2 * sC, m * (Py * g0 + dy * tg));
-        st(q + 3 * sC, m * (Pz * g0 + dz * tg));
-        st(q + 4 * sC, m * (lapP * g0 + P * (c1 + c2)));
-      }
+      const double tp = P * tg1;
+      OutT* q = o + idx * sK;
+      st(q, m * P * g0);
+      st(q + sC, m * (X.v1 * yz * g0 + dx * tp));
+      st(q + 2 * sC, m * (X.v0 * Y.v1 * Z.v0 * g0 + dy * tp));
+      st(q + 3 * sC, m * (X.v0 * Y.v0 * Z.v1 * g0 + dz * tp));
+      st(q + 4 * sC, m * (lapP * g0 + P * lapr));
     }
   }
 }
@@ -132,14 +123,9 @@ __global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, 
           g2 += pr.gamma * pr.gamma * e;
         }
       }
-      OutT* o = obase + sh.ao_off * out.sK;
-      const double* M = t.ao_factor + sh.ao_off;
-      switch (sh.l) {
-        case 0: shell_vgl<0>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
-        case 1: shell_vgl<1>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
-        case 2: shell_vgl<2>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
-        default: shell_vgl<3>(dx, dy, dz, u, g0, g1, g2, M, o, out.sK, out.sC, valid); break;
-      }
+      if (valid)
+        shell_vgl(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2,
+                  t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK, out.sC);
     }
   }
 }

@@ -9,6 +9,7 @@
 // the device copies of the basis tables and MO coefficients); the MO array
 // is written straight into the caller's buffer by the contraction.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -137,6 +138,7 @@ struct qmk_ctx_s {
   int gbar_f32 = -1;
 
   int64_t launches = 0;
+  int forced_tile[3] = {-1, -1, -1};  // per GemmKind; -1 = autotuned
 
   // tracing: events around launches, per kernel class
   struct Pending {
@@ -426,6 +428,20 @@ qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
   return QMK_OK;
 }
 
+// Tile for one product: forced by qmk_set_tile, else the autotuner's choice.
+qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
+                     const std::function<hipError_t(int)>& enqueue, int* cfg) {
+  const int forced = ctx->forced_tile[static_cast<int>(pb.kind)];
+  if (forced >= 0) {
+    *cfg = forced;
+    return QMK_OK;
+  }
+  hipError_t e = hipSuccess;
+  *cfg = choose_tile(pb, ctx->device, s, enqueue, &e);
+  if (e != hipSuccess) return hip_fail(ctx, e, "tile autotuning");
+  return QMK_OK;
+}
+
 Prec gemm_prec(qmk_ctx ctx) {
   return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16x3);
 }
@@ -668,6 +684,27 @@ qmk_status qmk_get_launch_count(qmk_ctx ctx, int64_t* count) {
   return QMK_OK;
 }
 
+qmk_status qmk_set_tile(qmk_ctx ctx, int32_t kernel_class, int32_t tile) {
+  QMK_CHECK_CTX(ctx);
+  int kind = -1;
+  if (kernel_class == QMK_KERNEL_MO) kind = static_cast<int>(GemmKind::kForward);
+  if (kernel_class == QMK_KERNEL_GBAR) kind = static_cast<int>(GemmKind::kGbar);
+  if (kernel_class == QMK_KERNEL_DCOEF) kind = static_cast<int>(GemmKind::kDcoef);
+  if (kind < 0) return bad_arg(ctx, 2, "kernel class has no tile choice");
+  if (tile < -1 || tile >= gemm_num_tiles(Prec::kF64)) return bad_arg(ctx, 3, "unknown tile");
+  if (tile >= 0 && !tile_feasible(Prec::kF64, tile) && ctx->mode == QMK_FP64)
+    return bad_arg(ctx, 3, "tile does not fit in LDS");
+  ctx->forced_tile[kind] = tile;
+  return QMK_OK;
+}
+
+qmk_status qmk_get_tile_count(qmk_ctx ctx, int32_t* count) {
+  QMK_CHECK_CTX(ctx);
+  if (!count) return bad_arg(ctx, 2, "NULL");
+  *count = gemm_num_tiles(gemm_prec(ctx));
+  return QMK_OK;
+}
+
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable) {
   QMK_CHECK_CTX(ctx);
   if (enable != 0 && enable != 1) return bad_arg(ctx, 2, "must be 0 or 1");
@@ -748,9 +785,16 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   ga.Lchunk = K;
   ga.nsplit = 1;
   ga.nbatch = 5;
+  const Prec prec = gemm_prec(ctx);
+  const int o32 = dtype == QMK_F32;
+  const GemmProblem pb{GemmKind::kForward, prec, 0, o32, P, N, K};
+  int cfg = 0;
+  if ((st = pick_tile(ctx, pb, s, [&](int c) {
+         return launch_gemm_typed(GemmKind::kForward, prec, c, ga, 0, o32, s);
+       }, &cfg)) != QMK_OK)
+    return st;
   LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
-  QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, gemm_prec(ctx), ga, 0, dtype == QMK_F32, s),
-          "MO contraction");
+  QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, prec, cfg, ga, 0, o32, s), "MO contraction");
   return QMK_OK;
 }
 
@@ -799,9 +843,15 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     ga.Lchunk = N;
     ga.nsplit = 1;
     ga.nbatch = 5;
+    const GemmProblem pb{GemmKind::kGbar, prec, w32, f32, P, K, N};
+    int cfg = 0;
+    if ((st = pick_tile(ctx, pb, s, [&](int c) {
+           return launch_gemm_typed(GemmKind::kGbar, prec, c, ga, w32, f32, s);
+         }, &cfg)) != QMK_OK)
+      return st;
     {
       LaunchTimer lt(ctx, QMK_KERNEL_GBAR, s);
-      QMK_HIP(ctx, launch_gemm_typed(GemmKind::kGbar, prec, ga, w32, f32, s), "Gbar product");
+      QMK_HIP(ctx, launch_gemm_typed(GemmKind::kGbar, prec, cfg, ga, w32, f32, s), "Gbar product");
     }
 
     const int64_t n_waves = (P + 255) / 256 * 4;
@@ -834,45 +884,61 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     }
   }
   if (d_coef) {
-    // dC[n][k] = sum_{c, p} W[p][c][n] ao[k][c][p], split over (c, point chunk)
-    const int64_t tiles = ((N + 127) / 128) * ((K + 127) / 128);
-    int64_t nsplit = std::max<int64_t>(1, (2048 + tiles * 5 - 1) / (tiles * 5));
-    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, (P + 255) / 256));
-    int64_t chunk = (P + nsplit - 1) / nsplit;
-    chunk = round_up(chunk, 16);
-    nsplit = (P + chunk - 1) / chunk;
-    const int64_t nz = 5 * nsplit;
-    QMK_HIP(ctx, ctx->ws_dc.ensure(static_cast<size_t>(nz * Np * Kp) * 8), "alloc dC partials");
-    GemmArgs ga{};
-    ga.A = w;
-    ga.sAi = 1;
-    ga.sAl = 5 * N;
-    ga.oAc = N;
-    ga.oAs = chunk * 5 * N;
-    ga.B = ctx->ao.p;
-    ga.sBl = 1;
-    ga.sBj = 5 * Pp;
-    ga.oBc = Pp;
-    ga.oBs = chunk;
-    ga.D = ctx->ws_dc.p;
-    ga.sDi = Kp;
-    ga.sDj = 1;
-    ga.oDz = Np * Kp;
-    ga.M = N;
-    ga.N = K;
-    ga.L = P;
-    ga.Lchunk = chunk;
-    ga.nsplit = static_cast<int32_t>(nsplit);
-    ga.nbatch = 5;
-    {
-      LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);
-      QMK_HIP(ctx, launch_gemm_typed(GemmKind::kDcoef, prec, ga, w32, 0, s), "dC product");
+    // dC[n][k] = sum_{c, p} W[p][c][n] ao[k][c][p], split over (c, point chunk);
+    // the number of point chunks follows from the tile so that the grid holds
+    // about 2048 workgroups.
+    auto split_of = [&](int cfg, int64_t* chunk_out) {
+      const TileCfg t = gemm_tile(prec, cfg);
+      const int64_t tiles = ((N + t.bm() - 1) / t.bm()) * ((K + t.bn() - 1) / t.bn());
+      int64_t ns = std::max<int64_t>(1, (2048 + tiles * 5 - 1) / (tiles * 5));
+      ns = std::min<int64_t>(ns, std::max<int64_t>(1, (P + 255) / 256));
+      int64_t chunk = round_up((P + ns - 1) / ns, 32);
+      *chunk_out = chunk;
+      return (P + chunk - 1) / chunk;
+    };
+    int64_t nz_max = 0;
+    for (int c = 0; c < gemm_num_tiles(prec); ++c) {
+      int64_t ch = 0;
+      if (tile_feasible(prec, c)) nz_max = std::max(nz_max, 5 * split_of(c, &ch));
     }
-    {
+    QMK_HIP(ctx, ctx->ws_dc.ensure(static_cast<size_t>(nz_max * Np * Kp) * 8), "alloc dC partials");
+    auto enqueue = [&](int cfg) -> hipError_t {
+      int64_t chunk = 0;
+      const int64_t nsplit = split_of(cfg, &chunk);
+      GemmArgs ga{};
+      ga.A = w;
+      ga.sAi = 1;
+      ga.sAl = 5 * N;
+      ga.oAc = N;
+      ga.oAs = chunk * 5 * N;
+      ga.B = ctx->ao.p;
+      ga.sBl = 1;
+      ga.sBj = 5 * Pp;
+      ga.oBc = Pp;
+      ga.oBs = chunk;
+      ga.D = ctx->ws_dc.p;
+      ga.sDi = Kp;
+      ga.sDj = 1;
+      ga.oDz = Np * Kp;
+      ga.M = N;
+      ga.N = K;
+      ga.L = P;
+      ga.Lchunk = chunk;
+      ga.nsplit = static_cast<int32_t>(nsplit);
+      ga.nbatch = 5;
+      hipError_t e;
+      {
+        LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);
+        e = launch_gemm_typed(GemmKind::kDcoef, prec, cfg, ga, w32, 0, s);
+      }
+      if (e != hipSuccess) return e;
       LaunchTimer lt(ctx, QMK_KERNEL_REDUCE, s);
-      QMK_HIP(ctx, launch_reduce_splits(ctx->ws_dc.as<double>(), nz, N, K, Kp, Np * Kp, d_coef, K, s),
-              "reduce dC");
-    }
+      return launch_reduce_splits(ctx->ws_dc.as<double>(), 5 * nsplit, N, K, Kp, Np * Kp, d_coef, K, s);
+    };
+    const GemmProblem pb{GemmKind::kDcoef, prec, w32, 0, N, K, P};
+    int cfg = 0;
+    if ((st = pick_tile(ctx, pb, s, enqueue, &cfg)) != QMK_OK) return st;
+    QMK_HIP(ctx, enqueue(cfg), "dC product");
   }
   return QMK_OK;
 }

@@ -6,9 +6,11 @@
 //   forward   mo[p][c][n]   = sum_k ao[k][c][p] Ct[k][n]        (batch c)
 //   Gbar      Gb[k][c][p]   = sum_n W[p][c][n]  C[n][k]         (batch c)
 //   dC        ws[c,s][n][k] = sum_{p in split s} W[p][c][n] ao[k][c][p]
-// (see GemmArgs for the index algebra).  Tiles are 128 x 128 with a K step
-// of 16, four wavefronts in a 2 x 2 arrangement, each owning a 64 x 64
-// sub-tile as 4 x 4 MFMA 16x16x4 blocks (FP64 or FP32).  Operand tiles go
+// (see GemmArgs for the index algebra).  A tile is WGM x WGN wavefronts,
+// each owning TM x TN MFMA 16x16x4 blocks (FP64 or FP32); the shapes on
+// offer are listed in QMK_TILE_LIST and chosen per problem by the host
+// autotuner (padding waste of N_MO = 400 on 128-wide tiles is 22%, on
+// 80-wide tiles zero).  Operand tiles go
 // global -> registers -> LDS with one tile of prefetch (double-buffered
 // LDS, one barrier per K step).  Tile order is XCD-aware: the eight
 // consecutive workgroup ids land on the eight XCDs, so ids are remapped so
@@ -58,12 +60,16 @@ __device__ __forceinline__ bool tile_of_block(int nM, int nN, int& mt, int& nt) 
   return mt < nM;
 }
 
-template <typename T, typename TA, typename TB, typename TD, int BM, int BN, int BK, bool A_I,
-          bool B_J>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int nM, int nN) {
+// Tile: WGM x WGN wavefronts, each owning TM x TN MFMA blocks of 16 x 16,
+// so the workgroup tile is BM = 16 WGM TM rows by BN = 16 WGN TN columns,
+// with a reduction step of BK.
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmArgs g, int nM, int nN) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   constexpr int PAD = 16 / sizeof(T);
-  constexpr int EA = BM * BK / 256, EB = BK * BN / 256;
-  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
   typedef typename Mfma<T>::v4 v4;
   __shared__ T As[2][BK][BM + PAD];
   __shared__ T Bs[2][BK][BN + PAD];
@@ -80,35 +86,65 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int nM, int nN) {
   const int tid = threadIdx.x;
 
   T ra[EA], rb[EB];
+  // Operand tiles fully inside the matrices take an unguarded path (uniform
+  // branch per K step); only edge tiles test every element.
+  const bool a_rows_in = i0 + BM <= g.M, b_cols_in = j0 + BN <= g.N;
   auto load = [&](int64_t l0) {
+    const bool l_in = l0 + BK <= Ls;
+    if (a_rows_in && l_in && BM * BK % NT == 0) {
+      const TA* base = Ap + i0 * g.sAi + l0 * g.sAl;
 #pragma unroll
-    for (int r = 0; r < EA; ++r) {
-      const int e = tid + 256 * r;
-      const int i = A_I ? e % BM : e / BK;
-      const int l = A_I ? e / BM : e % BK;
-      const int64_t gi = i0 + i, gl = l0 + l;
-      ra[r] = (gi < g.M && gl < Ls) ? static_cast<T>(Ap[gi * g.sAi + gl * g.sAl]) : T(0);
+      for (int r = 0; r < EA; ++r) {
+        const int e = tid + NT * r;
+        const int i = A_I ? e % BM : e / BK;
+        const int l = A_I ? e / BM : e % BK;
+        ra[r] = static_cast<T>(base[i * g.sAi + l * g.sAl]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < EA; ++r) {
+        const int e = tid + NT * r;
+        const int i = A_I ? e % BM : e / BK;
+        const int l = A_I ? e / BM : e % BK;
+        const int64_t gi = i0 + i, gl = l0 + l;
+        const bool in = (BM * BK % NT == 0 || e < BM * BK) && gi < g.M && gl < Ls;
+        ra[r] = in ? static_cast<T>(Ap[gi * g.sAi + gl * g.sAl]) : T(0);
+      }
     }
+    if (b_cols_in && l_in && BK * BN % NT == 0) {
+      const TB* base = Bp + l0 * g.sBl + j0 * g.sBj;
 #pragma unroll
-    for (int r = 0; r < EB; ++r) {
-      const int e = tid + 256 * r;
-      const int j = B_J ? e % BN : e / BK;
-      const int l = B_J ? e / BN : e % BK;
-      const int64_t gj = j0 + j, gl = l0 + l;
-      rb[r] = (gj < g.N && gl < Ls) ? static_cast<T>(Bp[gl * g.sBl + gj * g.sBj]) : T(0);
+      for (int r = 0; r < EB; ++r) {
+        const int e = tid + NT * r;
+        const int j = B_J ? e % BN : e / BK;
+        const int l = B_J ? e / BN : e % BK;
+        rb[r] = static_cast<T>(base[l * g.sBl + j * g.sBj]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < EB; ++r) {
+        const int e = tid + NT * r;
+        const int j = B_J ? e % BN : e / BK;
+        const int l = B_J ? e / BN : e % BK;
+        const int64_t gj = j0 + j, gl = l0 + l;
+        const bool in = (BK * BN % NT == 0 || e < BK * BN) && gj < g.N && gl < Ls;
+        rb[r] = in ? static_cast<T>(Bp[gl * g.sBl + gj * g.sBj]) : T(0);
+      }
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < EA; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
+      if (BM * BK % NT != 0 && e >= BM * BK) continue;
       const int i = A_I ? e % BM : e / BK;
       const int l = A_I ? e / BM : e % BK;
       As[buf][l][i] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < EB; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
+      if (BK * BN % NT != 0 && e >= BK * BN) continue;
       const int j = B_J ? e % BN : e / BK;
       const int l = B_J ? e / BN : e % BK;
       Bs[buf][l][j] = rb[r];
@@ -116,7 +152,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int nM, int nN) {
   };
 
   const int lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WGN, wn = w % WGN;
   v4 acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -137,9 +173,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int nM, int nN) {
       const int kr = kk * 4 + (lane >> 4), ci = lane & 15;
       T fa[TM], fb[TN];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) fa[a] = As[buf][kr][wm * WM + a * 16 + ci];
+      for (int a = 0; a < TM; ++a) fa[a] = As[buf][kr][(wm * TM + a) * 16 + ci];
 #pragma unroll
-      for (int b = 0; b < TN; ++b) fb[b] = Bs[buf][kr][wn * WN + b * 16 + ci];
+      for (int b = 0; b < TN; ++b) fb[b] = Bs[buf][kr][(wn * TN + b) * 16 + ci];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -155,8 +191,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g, int nM, int nN) {
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wm * WM + a * 16 + Mfma<T>::row(lane, r);
-        const int64_t gj = j0 + wn * WN + b * 16 + (lane & 15);
+        const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
         if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
       }
 }
@@ -172,45 +208,98 @@ __global__ void reduce_splits_kernel(const double* __restrict__ ws, int64_t nz, 
   out[r * ld_out + c] = acc;
 }
 
-template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
-hipError_t run(const GemmArgs& g, hipStream_t s) {
-  constexpr int BM = 128, BN = 128, BK = 16;
+// Tile configurations offered to the autotuner: {WGM, WGN, TM, TN, BK}.
+#define QMK_TILE_LIST(X) \
+  X(0, 2, 2, 4, 4, 16)   \
+  X(1, 4, 1, 4, 5, 16)   \
+  X(2, 2, 2, 4, 5, 16)   \
+  X(3, 2, 2, 5, 4, 16)   \
+  X(4, 1, 2, 5, 5, 16)   \
+  X(5, 2, 2, 2, 5, 16)   \
+  X(6, 2, 2, 4, 4, 32)   \
+  X(7, 2, 2, 4, 3, 16)   \
+  X(8, 2, 1, 5, 5, 16)   \
+  X(9, 4, 1, 2, 5, 32)
+
+constexpr TileCfg kTiles[] = {
+#define QMK_TILE_ENTRY(id, wgm, wgn, tm, tn, bk) {wgm, wgn, tm, tn, bk},
+    QMK_TILE_LIST(QMK_TILE_ENTRY)
+#undef QMK_TILE_ENTRY
+};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+hipError_t run_tile(const GemmArgs& g, hipStream_t s) {
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
   if (nM <= 0 || nN <= 0) return hipSuccess;
   const int gx = nM >= 8 ? 8 * nN * ((nM + 7) / 8) : nM * nN;
   dim3 grid(gx, g.nbatch * g.nsplit);
-  hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TD, BM, BN, BK, A_I, B_J>), grid, dim3(256), 0, s, g,
-                     nM, nN);
+  hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>), grid,
+                     dim3(64 * WGM * WGN), 0, s, g, nM, nN);
   return hipGetLastError();
+}
+
+template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
+hipError_t run(int cfg, const GemmArgs& g, hipStream_t s) {
+  switch (cfg) {
+#define QMK_TILE_CASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                      \
+    return run_tile<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J>(g, s);
+    QMK_TILE_LIST(QMK_TILE_CASE)
+#undef QMK_TILE_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_gemm_typed(GemmKind kind, Prec prec, const GemmArgs& g, int w_is_f32,
+int gemm_num_tiles(Prec prec) {
+  (void)prec;
+  return kNumTiles;
+}
+
+TileCfg gemm_tile(Prec prec, int cfg) {
+  (void)prec;
+  return kTiles[cfg];
+}
+
+size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
+  const TileCfg& t = kTiles[cfg];
+  const size_t esz = prec == Prec::kF64 ? 8 : 4;
+  const size_t pad = 16 / esz;
+  return 2 * static_cast<size_t>(t.bk) *
+         ((16 * t.wgm * t.tm + pad) + (16 * t.wgn * t.tn + pad)) * esz;
+}
+
+hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s) {
+  if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   if (prec == Prec::kF64) {
     switch (kind) {
       case GemmKind::kForward:
-        return out_is_f32 ? run<double, double, double, float, true, true>(g, s)
-                          : run<double, double, double, double, true, true>(g, s);
+        return out_is_f32 ? run<double, double, double, float, true, true>(cfg, g, s)
+                          : run<double, double, double, double, true, true>(cfg, g, s);
       case GemmKind::kGbar:
-        return w_is_f32 ? run<double, float, double, double, false, true>(g, s)
-                        : run<double, double, double, double, false, true>(g, s);
+        return w_is_f32 ? run<double, float, double, double, false, true>(cfg, g, s)
+                        : run<double, double, double, double, false, true>(cfg, g, s);
       case GemmKind::kDcoef:
-        return w_is_f32 ? run<double, float, double, double, true, false>(g, s)
-                        : run<double, double, double, double, true, false>(g, s);
+        return w_is_f32 ? run<double, float, double, double, true, false>(cfg, g, s)
+                        : run<double, double, double, double, true, false>(cfg, g, s);
     }
   } else {
     switch (kind) {
       case GemmKind::kForward:
-        return out_is_f32 ? run<float, float, float, float, true, true>(g, s)
-                          : run<float, float, float, double, true, true>(g, s);
+        return out_is_f32 ? run<float, float, float, float, true, true>(cfg, g, s)
+                          : run<float, float, float, double, true, true>(cfg, g, s);
       case GemmKind::kGbar:
-        return w_is_f32 ? run<float, float, float, float, false, true>(g, s)
-                        : run<float, double, float, float, false, true>(g, s);
+        return w_is_f32 ? run<float, float, float, float, false, true>(cfg, g, s)
+                        : run<float, double, float, float, false, true>(cfg, g, s);
       case GemmKind::kDcoef:
-        return w_is_f32 ? run<float, float, float, double, true, false>(g, s)
-                        : run<float, double, float, double, true, false>(g, s);
+        return w_is_f32 ? run<float, float, float, double, true, false>(cfg, g, s)
+                        : run<float, double, float, double, true, false>(cfg, g, s);
     }
   }
   return hipErrorInvalidValue;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 
 namespace qmk {
 
@@ -85,14 +86,52 @@ struct GemmArgs {
   int32_t nsplit, nbatch;   // gridDim.y = nbatch * nsplit
 };
 
+// Derivatives of t^e (e in 0..3, wave-uniform) of order 0..3, given t, t^2,
+// t^3: v0 = t^e, v1 = e t^(e-1), v2 = e(e-1) t^(e-2), v3 = e(e-1)(e-2) t^(e-3).
+struct AxisD {
+  double v0, v1, v2, v3;
+};
+__device__ __forceinline__ AxisD axis_derivs(int e, double t, double t2, double t3) {
+  AxisD r;
+  r.v0 = e == 0 ? 1.0 : (e == 1 ? t : (e == 2 ? t2 : t3));
+  r.v1 = e == 0 ? 0.0 : (e == 1 ? 1.0 : (e == 2 ? 2.0 * t : 3.0 * t2));
+  r.v2 = e < 2 ? 0.0 : (e == 2 ? 2.0 : 6.0 * t);
+  r.v3 = e == 3 ? 6.0 : 0.0;
+  return r;
+}
+
 enum class GemmKind { kForward, kGbar, kDcoef };
 enum class Prec { kF64, kF32, kBF16x3 };
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                          int fp32_compute, hipStream_t s);
-hipError_t launch_gemm_typed(GemmKind kind, Prec prec, const GemmArgs& g, int w_is_f32,
+// GEMM tile shape: WGM x WGN wavefronts of TM x TN 16x16 MFMA blocks, K step BK.
+struct TileCfg {
+  int wgm, wgn, tm, tn, bk;
+  constexpr int bm() const { return 16 * wgm * tm; }
+  constexpr int bn() const { return 16 * wgn * tn; }
+};
+int gemm_num_tiles(Prec prec);
+TileCfg gemm_tile(Prec prec, int cfg);
+size_t gemm_tile_lds_bytes(Prec prec, int cfg);
+hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s);
+
+// Autotuner (tuner.cpp).
+struct GemmProblem {
+  GemmKind kind;
+  Prec prec;
+  int w32, o32;
+  int64_t M, N, L;
+};
+bool tile_feasible(Prec prec, int cfg);
+int default_tile(const GemmProblem& p);
+// Returns the tile for p, timing every feasible tile through `enqueue` on
+// stream s the first time p is seen.  *err receives a HIP error, if any.
+int choose_tile(const GemmProblem& p, int device, hipStream_t s,
+                const std::function<hipError_t(int)>& enqueue, hipError_t* err);
+void forget_tuning();
 hipError_t launch_reduce_splits(const double* ws, int64_t nz, int64_t rows, int64_t cols,
                                 int64_t ld_ws, int64_t z_stride, double* out, int64_t ld_out,
                                 hipStream_t s);

@@ -240,3 +240,31 @@ def test_autograd_function():
     assert grad_err(C.grad.cpu().numpy(), r["d_coef"], r["d_coef_abs"]) <= 1e-11
     assert grad_err(Rn.grad.cpu().numpy(), r["d_nucl"], r["d_nucl_abs"]) <= 1e-11
     assert grad_err(Re.grad.cpu().numpy().reshape(-1, 3), r["d_elec"], r["d_elec_abs"]) <= 1e-11
+
+
+def test_every_tile_shape_matches_oracle():
+    """The autotuner may pick any tile shape: each one must give the oracle's
+    result (forward contraction, W C product and split-K W^T ao product)."""
+    q = qmk()
+    s = synth.medium(walkers=1)  # 280 points, 800 AOs, 400 MOs
+    w = synth.adjoint_weights(s, seed=4)
+    ref_mo = oracle.mo_vgl(s)
+    ref = oracle.adjoint(s, w)
+    wt = torch.from_numpy(w).cuda()
+    ctx = q.Context.from_system(s)
+    tried = 0
+    for t in range(ctx.tile_count()):
+        try:
+            for k in ("mo", "gbar", "dcoef"):
+                ctx.set_tile(k, t)
+        except q.QmkError:
+            continue  # does not fit in LDS
+        tried += 1
+        mo = ctx.get_mo_vgl().cpu().numpy().reshape(-1, 5, s.mo_num)
+        assert rownorm_err(mo, ref_mo).max() <= TOL, t
+        g = ctx.adjoint(wt)
+        for k in ("d_coef", "d_elec", "d_nucl"):
+            e = grad_err(g[k].cpu().numpy().reshape(ref[k].shape), ref[k], ref[k + "_abs"])
+            assert e <= 1e-11, (t, k, e)
+    assert tried >= 6
+    ctx.close()
