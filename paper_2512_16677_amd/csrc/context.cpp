@@ -126,7 +126,9 @@ struct qmk_ctx_s {
   bool coef_dirty = true;
   int coef_mode = -1;
   int64_t Kp = 0, Np = 0;
-  DevBuf d_Ct, d_C;
+  DevBuf d_Ct, d_C;          // FP64 or FP32 copies: C^T [Kp][Np], C [Np][Kp]
+  DevBuf d_Cb_hi, d_Cb_lo;   // BF16x3: C [Np][Kp] split into bf16 hi / lo
+  DevBuf d_Ctb_hi, d_Ctb_lo; // BF16x3: C^T [Kp][Np] split
 
   // AO array [Kp][5][Pp] (double or float), valid at ao_date
   DevBuf ao;
@@ -346,9 +348,53 @@ qmk_status ensure_tables(qmk_ctx ctx) {
   return QMK_OK;
 }
 
+// Round-to-nearest-even FP32 -> BF16 (bit pattern) and back.
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 qmk_status ensure_coef(qmk_ctx ctx) {
-  const int want = ctx->f32_storage() ? 1 : 0;
+  const int want = ctx->mode == QMK_FP64 ? 0 : (ctx->mode == QMK_MIXED_F32 ? 1 : 2);
   if (!ctx->coef_dirty && ctx->coef_mode == want) return QMK_OK;
+  if (want == 2) {
+    // C split once into bf16 hi + lo (hi = bf16(c), lo = bf16(c - hi)), in
+    // the two layouts the products read: [n][k] and [k][n].
+    const int64_t K = ctx->ao_num, N = ctx->mo_num;
+    ctx->Kp = round_up(K, kAoPad);
+    ctx->Np = round_up(N, kMoPad);
+    const int64_t Kp = ctx->Kp, Np = ctx->Np;
+    std::vector<uint16_t> ch(Kp * Np, 0), cl(Kp * Np, 0), th(Kp * Np, 0), tl(Kp * Np, 0);
+    for (int64_t n = 0; n < N; ++n)
+      for (int64_t k = 0; k < K; ++k) {
+        const double v = ctx->C[n * K + k];
+        const uint16_t h = bf16_bits(static_cast<float>(v));
+        const uint16_t l = bf16_bits(static_cast<float>(v - static_cast<double>(bf16_value(h))));
+        ch[n * Kp + k] = h;
+        cl[n * Kp + k] = l;
+        th[k * Np + n] = h;
+        tl[k * Np + n] = l;
+      }
+    const size_t bytes = static_cast<size_t>(Kp * Np) * 2;
+    DevBuf* bufs[4] = {&ctx->d_Cb_hi, &ctx->d_Cb_lo, &ctx->d_Ctb_hi, &ctx->d_Ctb_lo};
+    const std::vector<uint16_t>* src[4] = {&ch, &cl, &th, &tl};
+    for (int i = 0; i < 4; ++i) {
+      QMK_HIP(ctx, bufs[i]->ensure(bytes), "alloc split C");
+      QMK_HIP(ctx, hipMemcpy(bufs[i]->p, src[i]->data(), bytes, hipMemcpyHostToDevice), "upload split C");
+    }
+    ctx->coef_dirty = false;
+    ctx->coef_mode = want;
+    return QMK_OK;
+  }
   const int64_t K = ctx->ao_num, N = ctx->mo_num;
   ctx->Kp = round_up(K, kAoPad);
   ctx->Np = round_up(N, kMoPad);
@@ -440,6 +486,12 @@ qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
   *cfg = choose_tile(pb, ctx->device, s, enqueue, &e);
   if (e != hipSuccess) return hip_fail(ctx, e, "tile autotuning");
   return QMK_OK;
+}
+
+// Rows of W ([point][5][mo]) allow 16-byte vector loads in the BF16x3 product.
+bool w_vec_ok(const void* w, int64_t N, int w32) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(w);
+  return a % 16 == 0 && (w32 ? N % 4 == 0 : N % 2 == 0);
 }
 
 Prec gemm_prec(qmk_ctx ctx) {
@@ -761,7 +813,6 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
   if (size_max < P * 5 * N)
     return fail(ctx, QMK_SIZE, "size_max " + std::to_string(size_max) + " < " + std::to_string(P * 5 * N));
-  if (ctx->mode == QMK_MIXED_BF16X3) return fail(ctx, QMK_UNSUPPORTED, "BF16x3 not built yet");
   DeviceGuard g(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
@@ -772,9 +823,17 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   ga.sAi = 1;
   ga.sAl = 5 * Pp;
   ga.oAc = Pp;
-  ga.B = ctx->d_Ct.p;
-  ga.sBl = ctx->Np;
-  ga.sBj = 1;
+  if (ctx->mode == QMK_MIXED_BF16X3) {
+    ga.B = ctx->d_Cb_hi.p;  // C [n][k]: reduction index contiguous
+    ga.B2 = ctx->d_Cb_lo.p;
+    ga.sBl = 1;
+    ga.sBj = ctx->Kp;
+    ga.vec_ok = 3;
+  } else {
+    ga.B = ctx->d_Ct.p;
+    ga.sBl = ctx->Np;
+    ga.sBj = 1;
+  }
   ga.D = out;
   ga.sDi = 5 * N;
   ga.sDj = 1;
@@ -805,7 +864,6 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   if (w_dtype != QMK_F64 && w_dtype != QMK_F32) return bad_arg(ctx, 3, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
-  if (ctx->mode == QMK_MIXED_BF16X3) return fail(ctx, QMK_UNSUPPORTED, "BF16x3 not built yet");
   DeviceGuard g(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
@@ -830,9 +888,17 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     ga.sAi = 5 * N;
     ga.sAl = 1;
     ga.oAc = N;
-    ga.B = ctx->d_C.p;
-    ga.sBl = Kp;
-    ga.sBj = 1;
+    if (prec == Prec::kBF16x3) {
+      ga.B = ctx->d_Ctb_hi.p;  // C^T [k][n]: reduction index contiguous
+      ga.B2 = ctx->d_Ctb_lo.p;
+      ga.sBl = 1;
+      ga.sBj = Np;
+      ga.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
+    } else {
+      ga.B = ctx->d_C.p;
+      ga.sBl = Kp;
+      ga.sBj = 1;
+    }
     ga.D = ctx->gbar.p;
     ga.sDi = 1;
     ga.sDj = 5 * Pp;
@@ -926,6 +992,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ga.Lchunk = chunk;
       ga.nsplit = static_cast<int32_t>(nsplit);
       ga.nbatch = 5;
+      ga.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
       hipError_t e;
       {
         LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);

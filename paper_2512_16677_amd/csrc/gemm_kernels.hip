@@ -257,16 +257,15 @@ hipError_t run(int cfg, const GemmArgs& g, hipStream_t s) {
 }  // namespace
 
 int gemm_num_tiles(Prec prec) {
-  (void)prec;
-  return kNumTiles;
+  return prec == Prec::kBF16x3 ? gemm_bf16_num_tiles() : kNumTiles;
 }
 
 TileCfg gemm_tile(Prec prec, int cfg) {
-  (void)prec;
-  return kTiles[cfg];
+  return prec == Prec::kBF16x3 ? gemm_bf16_tile(cfg) : kTiles[cfg];
 }
 
 size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
+  if (prec == Prec::kBF16x3) return gemm_bf16_tile_lds_bytes(cfg);
   const TileCfg& t = kTiles[cfg];
   const size_t esz = prec == Prec::kF64 ? 8 : 4;
   const size_t pad = 16 / esz;
@@ -276,6 +275,7 @@ size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
 
 hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s) {
+  if (prec == Prec::kBF16x3) return launch_gemm_bf16x3(kind, cfg, g, w_is_f32, out_is_f32, s);
   if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   if (prec == Prec::kF64) {
     switch (kind) {

@@ -84,6 +84,11 @@ struct GemmArgs {
   int64_t sDi, sDj, oDz;
   int64_t M, N, L, Lchunk;
   int32_t nsplit, nbatch;   // gridDim.y = nbatch * nsplit
+  // BF16x3 kernel only: second (lo) plane of a pre-split operand, and bit 0 /
+  // bit 1 set when A / B rows allow 16-byte vector loads.
+  const void* A2;
+  const void* B2;
+  int32_t vec_ok;
 };
 
 // Derivatives of t^e (e in 0..3, wave-uniform) of order 0..3, given t, t^2,
@@ -117,6 +122,12 @@ TileCfg gemm_tile(Prec prec, int cfg);
 size_t gemm_tile_lds_bytes(Prec prec, int cfg);
 hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s);
+// BF16x3 kernel (gemm_bf16.hip); reached through launch_gemm_typed.
+int gemm_bf16_num_tiles();
+TileCfg gemm_bf16_tile(int cfg);
+size_t gemm_bf16_tile_lds_bytes(int cfg);
+hipError_t launch_gemm_bf16x3(GemmKind kind, int cfg, const GemmArgs& g, int w_is_f32,
+                              int out_is_f32, hipStream_t s);
 
 // Autotuner (tuner.cpp).
 struct GemmProblem {
