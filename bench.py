@@ -43,9 +43,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--walkers", type=int, default=512)
     ap.add_argument("--mode", default="fp64", choices=list(MODE_DTYPE))
-    ap.add_argument("--variants", default="", help="comma list of extra precision modes to time")
+    ap.add_argument("--variants", default="mixed_f32,mixed_bf16x3",
+                    help="comma list of extra precision modes to time and compare with FP64")
+    ap.add_argument("--mixed-bits", type=int, default=53,
+                    help="precision parameter B of the mixed variants (cutoff of the exponentials)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=12,
+    ap.add_argument("--cpu-walkers", type=int, default=96,
                     help="walkers in the oracle's timed sample")
     return ap.parse_args()
 
@@ -55,7 +58,7 @@ def make_workload(walkers: int):
     return synth.medium(walkers=walkers)
 
 
-def run_gpu(s, mode: str, steps: int, warmup: int, bits: int):
+def run_gpu(s, mode: str, steps: int, warmup: int, bits: int, keep_outputs: bool = False):
     import torch
     import paper_2512_16677_amd as qmk
 
@@ -92,8 +95,33 @@ def run_gpu(s, mode: str, steps: int, warmup: int, bits: int):
     timing = ctx.timing()
     ctx.set_timing(False)
     ms = (t1 - t0) * 1e3 / steps
+    outs = None
+    if keep_outputs:  # one more (untimed) step on the first coordinate set
+        ctx.set_point(r0)
+        ctx.get_mo_vgl(out=mo)
+        ctx.adjoint(w, out=grads)
+        torch.cuda.synchronize()
+        outs = {"mo": mo, **grads}
     ctx.close()
-    return ms, timing
+    return ms, timing, outs
+
+
+def errors_vs(ref, got):
+    """Mixed vs FP64 GPU results over the whole workload: row-normwise relative
+    error of mo_vgl per component (max over points of max_n|diff| / max_n|ref|)
+    and normwise error of each gradient (max|diff| / max|ref|)."""
+    import torch
+    e = {}
+    num = (got["mo"] - ref["mo"]).abs().amax(dim=-1)
+    den = ref["mo"].abs().amax(dim=-1).clamp_min(1e-300)
+    r = (num / den).reshape(-1, 5)
+    e["value"] = float(r[:, 0].max())
+    e["gradient"] = float(r[:, 1:4].max())
+    e["laplacian"] = float(r[:, 4].max())
+    e["laplacian_p999"] = float(torch.quantile(r[:, 4].float(), 0.999))
+    for k in ("d_coef", "d_elec", "d_nucl"):
+        e[k] = float((got[k] - ref[k]).abs().max() / ref[k].abs().max().clamp_min(1e-300))
+    return e
 
 
 def kernel_roofline(s, mode, timing):
@@ -150,8 +178,10 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     s = make_workload(a.walkers)
-    bits = 53 if a.mode == "fp64" else 24
-    ms, timing = run_gpu(s, a.mode, a.steps, a.warmup, bits)
+    bits = 53 if a.mode == "fp64" else a.mixed_bits
+    variants_list = [v for v in a.variants.split(",") if v and v != a.mode]
+    ms, timing, ref_out = run_gpu(s, a.mode, a.steps, a.warmup, bits,
+                                  keep_outputs=bool(variants_list) and a.mode == "fp64")
     value = s.point_num / (ms * 1e-3)
     kr = kernel_roofline(s, a.mode, timing)
     peak_key = {"fp64": "fp64_TFLOPs", "mixed_f32": "fp32_TFLOPs", "mixed_bf16x3": "bf16_TFLOPs"}[a.mode]
@@ -171,10 +201,19 @@ def main():
         "roofline": roof,
     }
     variants = {}
-    for m in [v for v in a.variants.split(",") if v]:
-        vms, vt = run_gpu(s, m, a.steps, a.warmup, 24)
-        variants[m] = {"value": s.point_num / (vms * 1e-3), "ms_per_step": vms,
-                       "per_kernel": kernel_roofline(s, m, vt)}
+    for m in variants_list:
+        vms, vt, vout = run_gpu(s, m, a.steps, a.warmup, a.mixed_bits, keep_outputs=ref_out is not None)
+        peak_v = PEAKS[{"mixed_f32": "fp32_TFLOPs", "mixed_bf16x3": "bf16_TFLOPs", "fp64": "fp64_TFLOPs"}[m]]
+        kv = kernel_roofline(s, m, vt)
+        variants[m] = {"value": s.point_num / (vms * 1e-3), "unit": "e-evals/s", "ms_per_step": vms,
+                       "speedup_vs_primary": ms / vms, "bits": a.mixed_bits,
+                       "mo_gemm_frac_of_peak": (kv["mo"]["TFLOPs"] * (3 if m == "mixed_bf16x3" else 1) / peak_v)
+                       if "mo" in kv else None,
+                       "per_kernel": kv}
+        if vout is not None:
+            variants[m]["error_vs_fp64_gpu"] = errors_vs(ref_out, vout)
+        del vout
+        torch.cuda.empty_cache()
     if variants:
         line["variants"] = variants
     if not a.no_cpu_baseline:

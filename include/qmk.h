@@ -195,23 +195,30 @@ qmk_status qmk_get_tile_count(qmk_ctx ctx, int32_t* count);
 qmk_status qmk_set_tile(qmk_ctx ctx, int32_t kernel_class, int32_t tile);
 
 /* ---------------------------------------------------------------------- */
-/* Batches: many independent contexts (Section 2.2) -- molecules of uneven
- * sizes, each with its own walkers -- evaluated together.  The contexts
- * must all be fully set (nuclei, basis, MO coefficients, points) on the
- * same device and the same precision mode; the batch reads them at each
- * run, so set_point between runs is allowed as long as no dimension
- * changes (a change makes qmk_batch_run return QMK_NOT_SET-free
- * re-planning automatically).  The batch does not own the contexts. */
+/* Batches: many independent contexts -- molecules of uneven sizes, each with
+ * its own walkers -- evaluated together (independent contexts: Section 2.2;
+ * parallelism over them: Section 2.4).  The batch does not own the contexts
+ * and reads their current inputs at every run, so set_point between runs is
+ * allowed.  All contexts must be fully set (nuclei, basis, MO coefficients,
+ * points), live on one device and use one precision mode.  A run whose
+ * dimensions differ from the previous run re-plans (and re-times the tile
+ * shapes) automatically.  Not thread-safe; contexts of a batch must not be
+ * used concurrently with its runs. */
 qmk_status qmk_batch_create(qmk_batch* out, const qmk_ctx* ctxs, int64_t n);
 qmk_status qmk_batch_destroy(qmk_batch batch);
+const char* qmk_batch_last_error(qmk_batch batch);
 
-/* Forward mo_vgl of every context into outs[i] (device, [walk][elec][5][mo]
- * of context i, type dtype), and, if ws != NULL, the adjoint with weights
- * ws[i] (type dtype) into d_coefs[i], d_elecs[i], d_nucls[i] (each array of
- * pointers may be NULL; entries may be NULL).  The whole batch runs as one
- * HIP graph launch, captured on the first run and replayed afterwards;
- * persistent kernels walk a longest-first work list of (molecule, tile)
- * items. */
+/* Forward mo_vgl of every context i into outs[i] (device buffer
+ * [walk][elec][5][mo] of context i, element type dtype), and, if ws != NULL,
+ * the adjoint of sum_i sum(ws[i] * mo_vgl_i) with weights ws[i] (device,
+ * same shape and element type as outs[i]) into d_coefs[i] [mo][ao],
+ * d_elecs[i] [walk][elec][3] and d_nucls[i] [nucl][3] (device FP64; any of
+ * the three pointer arrays, or any entry, may be NULL to skip that output).
+ * The first run of a batch shape times the tile shapes and captures the
+ * stage sequence -- persistent kernels walking longest-first work lists of
+ * (molecule, tile) items -- into a HIP graph on hip_stream; every run then
+ * rewrites the per-molecule argument tables and launches the graph once.
+ * hip_stream = NULL uses a stream of the batch and waits for completion. */
 qmk_status qmk_batch_run(qmk_batch batch, void* const* outs, int32_t dtype, const void* const* ws,
                          double* const* d_coefs, double* const* d_elecs, double* const* d_nucls,
                          void* hip_stream);

@@ -45,7 +45,7 @@ EXPORTED = [
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
     "qmk_get_tile_count", "qmk_set_tile",
-    "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_run",
+    "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
 KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce"]
@@ -88,8 +88,9 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_timing": ([P, I32, P, P], I32),
         "qmk_get_tile_count": ([P, P], I32),
         "qmk_set_tile": ([P, I32, I32], I32),
-        "qmk_batch_create": ([P, P, I64], I32),
+        "qmk_batch_create": ([ctypes.POINTER(P), P, I64], I32),
         "qmk_batch_destroy": ([P], I32),
+        "qmk_batch_last_error": ([P], ctypes.c_char_p),
         "qmk_batch_run": ([P, P, I32, P, P, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
@@ -299,6 +300,66 @@ class Context:
         else:
             c.set_point(s.elec_coord)
         return c
+
+
+class Batch:
+    """Several contexts evaluated together in one HIP-graph launch of
+    persistent kernels (see qmk_batch_run)."""
+
+    def __init__(self, contexts):
+        self._lib = load_library()
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c.handle.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        st = self._lib.qmk_batch_create(ctypes.byref(h), arr, len(self.contexts))
+        if st != QMK_OK:
+            raise QmkError(st, "qmk_batch_create failed")
+        self._h = h
+
+    def _check(self, st):
+        if st != QMK_OK:
+            raise QmkError(st, self._lib.qmk_batch_last_error(self._h).decode())
+
+    def run(self, outs=None, dtype=None, ws=None, grads=None, stream=None):
+        """outs: list of CUDA tensors [walk, elec, 5, mo] (allocated if None);
+        ws: optional list of weight tensors (same shapes and dtype);
+        grads: optional list of dicts with 'd_coef', 'd_elec', 'd_nucl'
+        tensors (allocated when ws is given and grads is None)."""
+        import torch
+        dtype = dtype or (outs[0].dtype if outs else torch.float64)
+        dims = [c.dims() for c in self.contexts]
+        if outs is None:
+            outs = [torch.empty((d["walk_num"], d["elec_num"], 5, d["mo_num"]), dtype=dtype,
+                                device=f"cuda:{c.device}") for d, c in zip(dims, self.contexts)]
+        n = len(self.contexts)
+        P = ctypes.c_void_p
+        o = (P * n)(*[t.data_ptr() for t in outs])
+        w_arr = dc = de = dn = None
+        if ws is not None:
+            if grads is None:
+                grads = [{"d_coef": torch.empty((d["mo_num"], d["ao_num"]), dtype=torch.float64, device=t.device),
+                          "d_elec": torch.empty((d["walk_num"], d["elec_num"], 3), dtype=torch.float64, device=t.device),
+                          "d_nucl": torch.empty((d["nucl_num"], 3), dtype=torch.float64, device=t.device)}
+                         for d, t in zip(dims, outs)]
+            w_arr = (P * n)(*[t.data_ptr() for t in ws])
+
+            def col(k):
+                return (P * n)(*[(g[k].data_ptr() if g.get(k) is not None else None) for g in grads])
+            dc, de, dn = col("d_coef"), col("d_elec"), col("d_nucl")
+        self._check(self._lib.qmk_batch_run(self._h, o, QMK_F32 if dtype == torch.float32 else QMK_F64,
+                                            w_arr, dc, de, dn, _stream(stream)))
+        return (outs, grads) if ws is not None else outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.qmk_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _autograd():

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libqmk.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["context.cpp", "tuner.cpp", "ao_kernels.hip", "gemm_kernels.hip", "gemm_bf16.hip",
+SOURCES = ["context.cpp", "batch.cpp", "tuner.cpp", "ao_kernels.hip", "gemm_kernels.hip", "gemm_bf16.hip",
            "adjoint_kernels.hip"]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -87,13 +87,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <typename GT>
-__global__ __launch_bounds__(256) void ao_adjoint_kernel(AoTables t, PointArgs pts,
-                                                         const GT* __restrict__ gbar, int64_t sK,
-                                                         int64_t sC, double* __restrict__ elec_out,
-                                                         int64_t elec_group_stride,
-                                                         double* __restrict__ nuc_partial) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const NucGroup g = t.group[blockIdx.y];
+__device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointArgs& pts,
+                                                const GT* __restrict__ gbar, int64_t sK,
+                                                int64_t sC, double* __restrict__ elec_out,
+                                                int64_t elec_group_stride,
+                                                double* __restrict__ nuc_partial, int bx, int gy,
+                                                unsigned char* smem) {
+  const NucGroup g = t.group[gy];
   const int np = g.p_end - g.p_begin, ns = g.sh_end - g.sh_begin, nn = g.nuc_end - g.nuc_begin;
   PrimDev* s_prim = reinterpret_cast<PrimDev*>(smem);
   ShellDev* s_shell = reinterpret_cast<ShellDev*>(s_prim + np);
@@ -103,8 +103,8 @@ __global__ __launch_bounds__(256) void ao_adjoint_kernel(AoTables t, PointArgs p
   for (int i = threadIdx.x; i < nn; i += blockDim.x) s_nuc[i] = t.nuc[g.nuc_begin + i];
   __syncthreads();
 
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t p = static_cast<int64_t>(bx) * blockDim.x + threadIdx.x;
+  const int64_t wave = p >> 6;
   const int lane = threadIdx.x & 63;
   const bool valid = p < pts.P;
   double rx = 0.0, ry = 0.0, rz = 0.0;
@@ -158,11 +158,87 @@ __global__ __launch_bounds__(256) void ao_adjoint_kernel(AoTables t, PointArgs p
     }
   }
   if (valid) {
-    double* o = elec_out + blockIdx.y * elec_group_stride + p * 3;
+    double* o = elec_out + gy * elec_group_stride + p * 3;
     o[0] = ex;
     o[1] = ey;
     o[2] = ez;
   }
+}
+
+template <typename GT>
+__global__ __launch_bounds__(256) void ao_adjoint_kernel(AoTables t, PointArgs pts,
+                                                         const GT* __restrict__ gbar, int64_t sK,
+                                                         int64_t sC, double* __restrict__ elec_out,
+                                                         int64_t elec_group_stride,
+                                                         double* __restrict__ nuc_partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  ao_adjoint_body<GT>(t, pts, gbar, sK, sC, elec_out, elec_group_stride, nuc_partial, blockIdx.x,
+                      blockIdx.y, smem);
+}
+
+template <typename GT>
+__global__ __launch_bounds__(256) void ao_adjoint_persist(const AdjJob* __restrict__ jobs,
+                                                          const WorkItem* __restrict__ items,
+                                                          int n_items) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const WorkItem it = items[i];
+    const AdjJob& j = jobs[it.job];
+    ao_adjoint_body<GT>(j.t, j.pts, static_cast<const GT*>(j.gbar), j.sK, j.sC, j.elec_out,
+                        j.elec_group_stride, j.nuc_partial, it.a, it.b, smem);
+    __syncthreads();
+  }
+}
+
+// Block-wide fixed-order sum of one value per thread (256 threads).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Largest j with prefix[j] <= e (prefix[0] = 0, increasing).
+__device__ __forceinline__ int find_job(const int64_t* prefix, int n_jobs, int64_t e) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void reduce_nuc_batch_kernel(const NucRedJob* __restrict__ jobs,
+                                                               const int64_t* __restrict__ prefix,
+                                                               int n_jobs) {
+  __shared__ double red[256];
+  const int64_t e = blockIdx.x;
+  const int jb = find_job(prefix, n_jobs, e);
+  const NucRedJob& j = jobs[jb];
+  const int64_t loc = e - prefix[jb];
+  const int A = static_cast<int>(loc / 3), i = static_cast<int>(loc - 3 * (loc / 3));
+  const int a = j.dev_of[A];
+  double acc = 0.0;
+  if (a >= 0)
+    for (int64_t w = threadIdx.x; w < j.n_waves; w += 256) acc += j.part[(w * j.nucl_dev + a) * 3 + i];
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) j.out[loc] = tot;
+}
+
+__global__ void reduce_batch_kernel(const RedJob* __restrict__ jobs,
+                                    const int64_t* __restrict__ prefix, int n_jobs, int64_t total) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int jb = find_job(prefix, n_jobs, e);
+  const RedJob& j = jobs[jb];
+  const int64_t loc = e - prefix[jb];
+  const int64_t r = loc / j.cols, c = loc - r * j.cols;
+  double acc = 0.0;
+  for (int64_t z = 0; z < j.nz; ++z) acc += j.ws[z * j.z_stride + r * j.ld_ws + c];
+  j.out[r * j.ld_out + c] = acc;
 }
 
 // One block per output entry: strided partial sums then a fixed-order tree
@@ -188,6 +264,39 @@ __global__ __launch_bounds__(256) void reduce_nuc_kernel(const double* __restric
 }
 
 }  // namespace
+
+hipError_t launch_ao_adjoint_persist(const AdjJob* jobs, const WorkItem* items, int n_items,
+                                     int grid, size_t smem, int gbar_is_f32, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (gbar_is_f32)
+    hipLaunchKernelGGL(ao_adjoint_persist<float>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
+  else
+    hipLaunchKernelGGL(ao_adjoint_persist<double>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
+  return hipGetLastError();
+}
+
+int adj_persist_blocks_per_cu(int f32, size_t smem) {
+  int n = 0;
+  hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_adjoint_persist<float>, 256, smem)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_adjoint_persist<double>, 256, smem);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_reduce_batch(const RedJob* jobs, const int64_t* prefix, int n_jobs, int64_t total,
+                               hipStream_t s) {
+  if (total <= 0 || n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_batch_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                     0, s, jobs, prefix, n_jobs, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_nuc_batch(const NucRedJob* jobs, const int64_t* prefix, int n_jobs,
+                                   int64_t total, hipStream_t s) {
+  if (total <= 0 || n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_nuc_batch_kernel, dim3(static_cast<unsigned>(total)), dim3(256), 0, s,
+                     jobs, prefix, n_jobs);
+  return hipGetLastError();
+}
 
 hipError_t launch_ao_adjoint(const AoTables& t, const PointArgs& pts, const void* gbar,
                              int gbar_is_f32, int64_t sK, int64_t sC, double* elec_out,

@@ -73,9 +73,10 @@ __device__ __forceinline__ void shell_zero(int l, OutT* __restrict__ o, int64_t 
 }
 
 template <typename OutT>
-__global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const NucGroup g = t.group[blockIdx.y];
+__device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& pts,
+                                            const AoOut& out, int bx, int gy,
+                                            unsigned char* smem) {
+  const NucGroup g = t.group[gy];
   const int np = g.p_end - g.p_begin, ns = g.sh_end - g.sh_begin, nn = g.nuc_end - g.nuc_begin;
   PrimDev* s_prim = reinterpret_cast<PrimDev*>(smem);
   ShellDev* s_shell = reinterpret_cast<ShellDev*>(s_prim + np);
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, 
   for (int i = threadIdx.x; i < nn; i += blockDim.x) s_nuc[i] = t.nuc[g.nuc_begin + i];
   __syncthreads();
 
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t p = static_cast<int64_t>(bx) * blockDim.x + threadIdx.x;
   const bool valid = p < pts.P;
   double rx = 0.0, ry = 0.0, rz = 0.0;
   if (valid) {
@@ -130,7 +131,44 @@ __global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, 
   }
 }
 
+template <typename OutT>
+__global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  ao_vgl_body<OutT>(t, pts, out, blockIdx.x, blockIdx.y, smem);
+}
+
+// Persistent form: the grid walks a list of (molecule, point block, group).
+template <typename OutT>
+__global__ __launch_bounds__(256) void ao_vgl_persist(const AoJob* __restrict__ jobs,
+                                                      const WorkItem* __restrict__ items,
+                                                      int n_items) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const WorkItem it = items[i];
+    const AoJob& j = jobs[it.job];
+    ao_vgl_body<OutT>(j.t, j.pts, j.out, it.a, it.b, smem);
+    __syncthreads();  // LDS is restaged by the next item
+  }
+}
+
 }  // namespace
+
+hipError_t launch_ao_vgl_persist(const AoJob* jobs, const WorkItem* items, int n_items, int grid,
+                                 size_t smem, int out_is_f32, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (out_is_f32)
+    hipLaunchKernelGGL(ao_vgl_persist<float>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
+  else
+    hipLaunchKernelGGL(ao_vgl_persist<double>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
+  return hipGetLastError();
+}
+
+int ao_persist_blocks_per_cu(int f32, size_t smem) {
+  int n = 0;
+  hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<float>, 256, smem)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<double>, 256, smem);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
 
 hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                          int fp32_compute, hipStream_t s) {

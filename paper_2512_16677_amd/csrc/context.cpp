@@ -18,56 +18,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/qmk.h"
-#include "qmk_internal.h"
+#include "ctx_internal.h"
 
 using namespace qmk;
 
 namespace {
 
-constexpr uint32_t kMagic = 0x514d4b43u;  // "QMKC"
 thread_local std::string g_create_error;
-
-int n_cart(int l) { return (l + 1) * (l + 2) / 2; }
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  hipError_t ensure(size_t n) {
-    if (n <= bytes && p) return hipSuccess;
-    release();
-    hipError_t e = hipMalloc(&p, n > 0 ? n : 16);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
-    }
-    bytes = n;
-    return hipSuccess;
-  }
-  template <typename T>
-  T* as() const { return static_cast<T*>(p); }
-};
-
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 // ---------------------------------------------------------------------------
 // Normalisation (QMCkl paper, Section 3.1: the factors f_ks, N_s and M_n),
@@ -87,84 +44,7 @@ double axis_norm2(int l, double alpha) {
 
 }  // namespace
 
-struct qmk_ctx_s {
-  uint32_t magic = kMagic;
-  int device = 0;
-  std::string err;
-
-  // time stamps: `date` moves with everything the AOs depend on
-  int64_t date = 1;
-  int32_t bits = 53;
-  int32_t mode = QMK_FP64;
-
-  int64_t nucl_num = 0;
-  std::vector<double> nucl;
-
-  bool has_basis = false;
-  int64_t shell_num = 0, prim_num = 0, ao_num = 0;
-  std::vector<int64_t> sh_nuc, sh_off;
-  std::vector<int32_t> sh_l;
-  std::vector<double> expo, coef, pf, sf, af;  // factors as used (given or computed)
-
-  bool has_coef = false;
-  int64_t mo_num = 0;
-  std::vector<double> C;  // [mo][ao]
-
-  bool has_points = false;
-  int64_t walk_num = 0, elec_num = 0;
-  char transp = 'N';
-  const double* pts = nullptr;
-  DevBuf own_pts;
-
-  // device tables
-  bool tables_dirty = true;
-  DevBuf d_nuc, d_shell, d_prim, d_aofac, d_group, d_devof;
-  AoTables tab{};
-  int32_t n_groups = 0, nucl_dev = 0;
-
-  // MO coefficient copies for the current mode
-  bool coef_dirty = true;
-  int coef_mode = -1;
-  int64_t Kp = 0, Np = 0;
-  DevBuf d_Ct, d_C;          // FP64 or FP32 copies: C^T [Kp][Np], C [Np][Kp]
-  DevBuf d_Cb_hi, d_Cb_lo;   // BF16x3: C [Np][Kp] split into bf16 hi / lo
-  DevBuf d_Ctb_hi, d_Ctb_lo; // BF16x3: C^T [Kp][Np] split
-
-  // AO array [Kp][5][Pp] (double or float), valid at ao_date
-  DevBuf ao;
-  int64_t ao_Pp = 0, ao_Kp = 0, ao_date = -1;
-  int ao_f32 = -1;
-
-  DevBuf gbar, ws_dc, ws_nuc, ws_elec;
-  int64_t gbar_Pp = 0, gbar_Kp = 0;
-  int gbar_f32 = -1;
-
-  int64_t launches = 0;
-  int forced_tile[3] = {-1, -1, -1};  // per GemmKind; -1 = autotuned
-
-  // tracing: events around launches, per kernel class
-  struct Pending {
-    int kind;
-    hipEvent_t a, b;
-  };
-  bool timing = false;
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> event_pool;
-  double t_ms[QMK_KERNEL_CLASSES] = {};
-  int64_t t_n[QMK_KERNEL_CLASSES] = {};
-  ~qmk_ctx_s() {
-    for (auto& p : pending) {
-      (void)hipEventDestroy(p.a);
-      (void)hipEventDestroy(p.b);
-    }
-    for (auto e : event_pool) (void)hipEventDestroy(e);
-  }
-
-  int64_t P() const { return walk_num * elec_num; }
-  bool f32_storage() const { return mode != QMK_FP64; }
-};
-
-namespace {
+namespace qmk {
 
 qmk_status fail(qmk_ctx ctx, qmk_status st, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -227,16 +107,6 @@ void collect_timing(qmk_ctx ctx) {
   }
   ctx->pending.clear();
 }
-
-#define QMK_CHECK_CTX(ctx) \
-  do {                     \
-    if (!valid_ctx(ctx)) return QMK_INVALID_CONTEXT; \
-  } while (0)
-#define QMK_HIP(ctx, expr, what)                      \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
-    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
-  } while (0)
 
 // Builds the device nucleus / shell / primitive tables and nucleus groups.
 qmk_status build_tables(qmk_ctx ctx) {
@@ -498,7 +368,7 @@ Prec gemm_prec(qmk_ctx ctx) {
   return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16x3);
 }
 
-}  // namespace
+}  // namespace qmk
 
 // ===========================================================================
 extern "C" {
@@ -1008,24 +878,6 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     QMK_HIP(ctx, enqueue(cfg), "dC product");
   }
   return QMK_OK;
-}
-
-qmk_status qmk_batch_create(qmk_batch* out, const qmk_ctx* ctxs, int64_t n) {
-  (void)out;
-  (void)ctxs;
-  (void)n;
-  return QMK_UNSUPPORTED;
-}
-qmk_status qmk_batch_destroy(qmk_batch batch) {
-  (void)batch;
-  return QMK_UNSUPPORTED;
-}
-qmk_status qmk_batch_run(qmk_batch batch, void* const* outs, int32_t dtype, const void* const* ws,
-                         double* const* d_coefs, double* const* d_elecs, double* const* d_nucls,
-                         void* hip_stream) {
-  (void)batch; (void)outs; (void)dtype; (void)ws; (void)d_coefs; (void)d_elecs; (void)d_nucls;
-  (void)hip_stream;
-  return QMK_UNSUPPORTED;
 }
 
 }  // extern "C"

@@ -244,25 +244,20 @@ struct TileLoader {
   }
 };
 
+template <int BM, int BN>
+struct BfSmem {
+  static constexpr int LDK = 32 + 8;
+  __bf16 A[2][2][BM * LDK];  // [buffer][hi, lo][row * LDK + k]
+  __bf16 B[2][2][BN * LDK];
+};
+
 template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(GemmArgs g, int nM, int nN) {
+__device__ __forceinline__ void bf16x3_body(const GemmArgs& g, int mt, int nt, int z,
+                                            BfSmem<16 * WGM * TM, 16 * WGN * TN>& sm) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, BK = 32, LDK = BK + 8;
-  __shared__ __align__(16) __bf16 sA[2][2][BM * LDK];
-  __shared__ __align__(16) __bf16 sB[2][2][BN * LDK];
-
-  const int bid = blockIdx.x;
-  int mt, nt;
-  if (nM >= 8) {
-    const int x = bid & 7, j = bid >> 3;
-    mt = (j / nN) * 8 + x;
-    nt = j % nN;
-  } else {
-    mt = bid / nN;
-    nt = bid % nN;
-  }
-  if (mt >= nM) return;
-  const int z = blockIdx.y;
+  auto& sA = sm.A;
+  auto& sB = sm.B;
   const int c = z / g.nsplit, s = z - c * g.nsplit;
   const TA* Ap = adv(static_cast<const TA*>(g.A), c * g.oAc + s * g.oAs);
   const TA* Ap2 = g.A2 ? adv(static_cast<const TA*>(g.A2), c * g.oAc + s * g.oAs) : Ap;
@@ -348,6 +343,34 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(GemmArgs g,
       }
 }
 
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(GemmArgs g, int nM, int nN) {
+  __shared__ __align__(16) BfSmem<16 * WGM * TM, 16 * WGN * TN> sm;
+  const int bid = blockIdx.x;
+  int mt, nt;
+  if (nM >= 8) {
+    const int x = bid & 7, j = bid >> 3;
+    mt = (j / nN) * 8 + x;
+    nt = j % nN;
+  } else {
+    mt = bid / nN;
+    nt = bid % nN;
+  }
+  if (mt >= nM) return;
+  bf16x3_body<TA, A_KC, TB, TD, WGM, WGN, TM, TN>(g, mt, nt, blockIdx.y, sm);
+}
+
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_persist(
+    const GemmArgs* __restrict__ jobs, const WorkItem* __restrict__ items, int n_items) {
+  __shared__ __align__(16) BfSmem<16 * WGM * TM, 16 * WGN * TN> sm;
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const WorkItem it = items[i];
+    bf16x3_body<TA, A_KC, TB, TD, WGM, WGN, TM, TN>(jobs[it.job], it.a, it.b, it.c, sm);
+    __syncthreads();
+  }
+}
+
 #define QMK_BF16_TILE_LIST(X) \
   X(0, 2, 2, 4, 4)            \
   X(1, 4, 1, 4, 5)            \
@@ -376,6 +399,40 @@ hipError_t run_bf_tile(const GemmArgs& g, hipStream_t s) {
   hipLaunchKernelGGL((gemm_bf16x3_kernel<TA, A_KC, TB, TD, WGM, WGN, TM, TN>), grid,
                      dim3(64 * WGM * WGN), 0, s, g, nM, nN);
   return hipGetLastError();
+}
+
+struct BfPersist {
+  const GemmArgs* jobs;
+  const WorkItem* items;
+  int n_items, grid;
+  int* occupancy;
+};
+
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+hipError_t run_bf_tile_persist(const BfPersist& pl, hipStream_t s) {
+  auto k = gemm_bf16x3_persist<TA, A_KC, TB, TD, WGM, WGN, TM, TN>;
+  if (pl.occupancy) {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * WGM * WGN, 0);
+    *pl.occupancy = (e == hipSuccess && n > 0) ? n : 1;
+    return e;
+  }
+  if (pl.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(pl.grid), dim3(64 * WGM * WGN), 0, s, pl.jobs, pl.items, pl.n_items);
+  return hipGetLastError();
+}
+
+template <typename TA, bool A_KC, typename TB, typename TD>
+hipError_t run_bf_persist(int cfg, const BfPersist& pl, hipStream_t s) {
+  switch (cfg) {
+#define QMK_BF_PCASE(id, wgm, wgn, tm, tn) \
+  case id:                                 \
+    return run_bf_tile_persist<TA, A_KC, TB, TD, wgm, wgn, tm, tn>(pl, s);
+    QMK_BF16_TILE_LIST(QMK_BF_PCASE)
+#undef QMK_BF_PCASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename TA, bool A_KC, typename TB, typename TD>
@@ -416,6 +473,25 @@ hipError_t launch_gemm_bf16x3(GemmKind kind, int cfg, const GemmArgs& g, int w_i
     case GemmKind::kDcoef:
       return w_is_f32 ? run_bf<float, false, float, double>(cfg, g, s)
                       : run_bf<double, false, float, double>(cfg, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_bf16x3_persist(GemmKind kind, int cfg, const GemmArgs* jobs,
+                                      const WorkItem* items, int n_items, int grid, int w_is_f32,
+                                      int out_is_f32, int* occupancy, hipStream_t s) {
+  if (cfg < 0 || cfg >= gemm_bf16_num_tiles()) return hipErrorInvalidValue;
+  const BfPersist pl{jobs, items, n_items, grid, occupancy};
+  switch (kind) {
+    case GemmKind::kForward:
+      return out_is_f32 ? run_bf_persist<float, false, PreSplit, float>(cfg, pl, s)
+                        : run_bf_persist<float, false, PreSplit, double>(cfg, pl, s);
+    case GemmKind::kGbar:
+      return w_is_f32 ? run_bf_persist<float, true, PreSplit, float>(cfg, pl, s)
+                      : run_bf_persist<double, true, PreSplit, float>(cfg, pl, s);
+    case GemmKind::kDcoef:
+      return w_is_f32 ? run_bf_persist<float, false, float, double>(cfg, pl, s)
+                      : run_bf_persist<double, false, float, double>(cfg, pl, s);
   }
   return hipErrorInvalidValue;
 }

@@ -63,20 +63,24 @@ __device__ __forceinline__ bool tile_of_block(int nM, int nN, int& mt, int& nt) 
 // Tile: WGM x WGN wavefronts, each owning TM x TN MFMA blocks of 16 x 16,
 // so the workgroup tile is BM = 16 WGM TM rows by BN = 16 WGN TN columns,
 // with a reduction step of BK.
+template <typename T, int BM, int BN, int BK>
+struct GemmSmem {
+  static constexpr int PAD = 16 / sizeof(T);
+  T A[2][BK][BM + PAD];
+  T B[2][BK][BN + PAD];
+};
+
+// One output tile (mt, nt) of batch index z.
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
           int BK, bool A_I, bool B_J>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmArgs g, int nM, int nN) {
+__device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int z,
+                                          GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK>& sm) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
-  constexpr int PAD = 16 / sizeof(T);
   constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
-
-  int mt, nt;
-  if (!tile_of_block(nM, nN, mt, nt)) return;
-  const int z = blockIdx.y;
+  auto& As = sm.A;
+  auto& Bs = sm.B;
   const int c = z / g.nsplit, s = z - c * g.nsplit;
   const TA* __restrict__ Ap = static_cast<const TA*>(g.A) + c * g.oAc + s * g.oAs;
   const TB* __restrict__ Bp = static_cast<const TB*>(g.B) + c * g.oBc + s * g.oBs;
@@ -197,6 +201,29 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmArgs g, int nM
       }
 }
 
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmArgs g, int nM, int nN) {
+  __shared__ GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK> sm;
+  int mt, nt;
+  if (!tile_of_block(nM, nN, mt, nt)) return;
+  gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>(g, mt, nt, blockIdx.y, sm);
+}
+
+// Persistent form: the grid walks a list of (job, M tile, N tile, z).
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_persist(const GemmArgs* __restrict__ jobs,
+                                                               const WorkItem* __restrict__ items,
+                                                               int n_items) {
+  __shared__ GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK> sm;
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const WorkItem it = items[i];
+    gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>(jobs[it.job], it.a, it.b, it.c, sm);
+    __syncthreads();
+  }
+}
+
 __global__ void reduce_splits_kernel(const double* __restrict__ ws, int64_t nz, int64_t rows,
                                      int64_t cols, int64_t ld_ws, int64_t z_stride,
                                      double* __restrict__ out, int64_t ld_out) {
@@ -239,6 +266,41 @@ hipError_t run_tile(const GemmArgs& g, hipStream_t s) {
   hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>), grid,
                      dim3(64 * WGM * WGN), 0, s, g, nM, nN);
   return hipGetLastError();
+}
+
+struct PersistLaunch {
+  const GemmArgs* jobs;
+  const WorkItem* items;
+  int n_items, grid;
+  int* occupancy;  // when non-NULL: report resident blocks per CU instead of launching
+};
+
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+hipError_t run_tile_persist(const PersistLaunch& pl, hipStream_t s) {
+  auto k = gemm_persist<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>;
+  if (pl.occupancy) {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * WGM * WGN, 0);
+    *pl.occupancy = (e == hipSuccess && n > 0) ? n : 1;
+    return e;
+  }
+  if (pl.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(pl.grid), dim3(64 * WGM * WGN), 0, s, pl.jobs, pl.items, pl.n_items);
+  return hipGetLastError();
+}
+
+template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
+hipError_t run_persist(int cfg, const PersistLaunch& pl, hipStream_t s) {
+  switch (cfg) {
+#define QMK_TILE_PCASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                       \
+    return run_tile_persist<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J>(pl, s);
+    QMK_TILE_LIST(QMK_TILE_PCASE)
+#undef QMK_TILE_PCASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
@@ -303,6 +365,59 @@ hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& 
     }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t gemm_persist_dispatch(GemmKind kind, Prec prec, int cfg, const PersistLaunch& pl,
+                                 int w_is_f32, int out_is_f32, hipStream_t s) {
+  if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
+  if (prec == Prec::kF64) {
+    switch (kind) {
+      case GemmKind::kForward:
+        return out_is_f32 ? run_persist<double, double, double, float, true, true>(cfg, pl, s)
+                          : run_persist<double, double, double, double, true, true>(cfg, pl, s);
+      case GemmKind::kGbar:
+        return w_is_f32 ? run_persist<double, float, double, double, false, true>(cfg, pl, s)
+                        : run_persist<double, double, double, double, false, true>(cfg, pl, s);
+      case GemmKind::kDcoef:
+        return w_is_f32 ? run_persist<double, float, double, double, true, false>(cfg, pl, s)
+                        : run_persist<double, double, double, double, true, false>(cfg, pl, s);
+    }
+  } else {
+    switch (kind) {
+      case GemmKind::kForward:
+        return out_is_f32 ? run_persist<float, float, float, float, true, true>(cfg, pl, s)
+                          : run_persist<float, float, float, double, true, true>(cfg, pl, s);
+      case GemmKind::kGbar:
+        return w_is_f32 ? run_persist<float, float, float, float, false, true>(cfg, pl, s)
+                        : run_persist<float, double, float, float, false, true>(cfg, pl, s);
+      case GemmKind::kDcoef:
+        return w_is_f32 ? run_persist<float, float, float, double, true, false>(cfg, pl, s)
+                        : run_persist<float, double, float, double, true, false>(cfg, pl, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_persist(GemmKind kind, Prec prec, int cfg, const GemmArgs* jobs,
+                               const WorkItem* items, int n_items, int grid, int w_is_f32,
+                               int out_is_f32, hipStream_t s) {
+  if (prec == Prec::kBF16x3)
+    return launch_gemm_bf16x3_persist(kind, cfg, jobs, items, n_items, grid, w_is_f32, out_is_f32,
+                                      nullptr, s);
+  PersistLaunch pl{jobs, items, n_items, grid, nullptr};
+  return gemm_persist_dispatch(kind, prec, cfg, pl, w_is_f32, out_is_f32, s);
+}
+
+int gemm_persist_blocks_per_cu(GemmKind kind, Prec prec, int cfg, int w_is_f32, int out_is_f32) {
+  int n = 1;
+  if (prec == Prec::kBF16x3) {
+    (void)launch_gemm_bf16x3_persist(kind, cfg, nullptr, nullptr, 0, 0, w_is_f32, out_is_f32, &n,
+                                     nullptr);
+    return n;
+  }
+  PersistLaunch pl{nullptr, nullptr, 0, 0, &n};
+  (void)gemm_persist_dispatch(kind, prec, cfg, pl, w_is_f32, out_is_f32, nullptr);
+  return n;
 }
 
 hipError_t launch_reduce_splits(const double* ws, int64_t nz, int64_t rows, int64_t cols,

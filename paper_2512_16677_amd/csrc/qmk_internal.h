@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <string>
 
 namespace qmk {
 
@@ -143,9 +144,70 @@ int default_tile(const GemmProblem& p);
 int choose_tile(const GemmProblem& p, int device, hipStream_t s,
                 const std::function<hipError_t(int)>& enqueue, hipError_t* err);
 void forget_tuning();
+// Raw access to the tile cache (batch executor): -1 if absent.
+int tune_cache_get(const std::string& key);
+void tune_cache_put(const std::string& key, int cfg);
+bool tuning_on();
+std::string device_arch(int device);
 hipError_t launch_reduce_splits(const double* ws, int64_t nz, int64_t rows, int64_t cols,
                                 int64_t ld_ws, int64_t z_stride, double* out, int64_t ld_out,
                                 hipStream_t s);
+// ---------------------------------------------------------------------------
+// Persistent (work-list) execution used by the batch executor: one launch
+// of a grid sized to the GPU walks a list of items, each item naming a job
+// (one molecule's arguments) and the block coordinates it stands for.
+struct WorkItem {
+  int32_t job, a, b, c;  // AO stages: a = point block, b = nucleus group;
+                         // products: a = M tile, b = N tile, c = batch index z
+};
+struct AoJob {
+  AoTables t;
+  PointArgs pts;
+  AoOut out;
+};
+struct AdjJob {
+  AoTables t;
+  PointArgs pts;
+  const void* gbar;
+  int64_t sK, sC;
+  double* elec_out;
+  int64_t elec_group_stride;
+  double* nuc_partial;
+};
+// out[r*ld_out + c] = sum_z ws[z*z_stride + r*ld_ws + c] for r < rows, c < cols
+struct RedJob {
+  const double* ws;
+  int64_t nz, rows, cols, ld_ws, z_stride;
+  double* out;
+  int64_t ld_out;
+};
+struct NucRedJob {
+  const double* part;
+  int64_t n_waves;
+  int32_t nucl_dev, nucl_num;
+  const int32_t* dev_of;
+  double* out;
+};
+
+hipError_t launch_ao_vgl_persist(const AoJob* jobs, const WorkItem* items, int n_items, int grid,
+                                 size_t smem, int out_is_f32, hipStream_t s);
+hipError_t launch_ao_adjoint_persist(const AdjJob* jobs, const WorkItem* items, int n_items,
+                                     int grid, size_t smem, int gbar_is_f32, hipStream_t s);
+hipError_t launch_gemm_persist(GemmKind kind, Prec prec, int cfg, const GemmArgs* jobs,
+                               const WorkItem* items, int n_items, int grid, int w_is_f32,
+                               int out_is_f32, hipStream_t s);
+hipError_t launch_reduce_batch(const RedJob* jobs, const int64_t* prefix, int n_jobs, int64_t total,
+                               hipStream_t s);
+hipError_t launch_reduce_nuc_batch(const NucRedJob* jobs, const int64_t* prefix, int n_jobs,
+                                   int64_t total, hipStream_t s);
+hipError_t launch_gemm_bf16x3_persist(GemmKind kind, int cfg, const GemmArgs* jobs,
+                                      const WorkItem* items, int n_items, int grid, int w_is_f32,
+                                      int out_is_f32, int* occupancy, hipStream_t s);
+// Resident blocks per compute unit of the persistent kernels.
+int ao_persist_blocks_per_cu(int f32, size_t smem);
+int adj_persist_blocks_per_cu(int f32, size_t smem);
+int gemm_persist_blocks_per_cu(GemmKind kind, Prec prec, int cfg, int w_is_f32, int out_is_f32);
+
 // Adjoint AO stage.  gbar: [ao][5][point] with strides (sK, sC, 1).
 // elec_out + blockIdx.y*elec_group_stride receives sum_k t[p][k][:] of the
 // group's nuclei as [point][3]; nuc_partial[(wave*nucl_dev + a)*3 + i]

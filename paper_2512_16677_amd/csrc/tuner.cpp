@@ -166,6 +166,30 @@ int choose_tile(const GemmProblem& p, int device, hipStream_t s,
   return best;
 }
 
+int tune_cache_get(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_cache_locked();
+  auto it = g_cache.find(key);
+  return it == g_cache.end() ? -1 : it->second;
+}
+
+void tune_cache_put(const std::string& key, int cfg) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_cache_locked();
+  g_cache[key] = cfg;
+  save_cache_locked();
+}
+
+bool tuning_on() { return tuning_enabled(); }
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx?";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  return colon == std::string::npos ? arch : arch.substr(0, colon);
+}
+
 void forget_tuning() {
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache.clear();
