@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--mixed-bits", type=int, default=53,
                     help="precision parameter B of the mixed variants (cutoff of the exponentials)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="medium", choices=["medium", "batch96"],
+                    help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes")
     ap.add_argument("--cpu-walkers", type=int, default=96,
                     help="walkers in the oracle's timed sample")
     return ap.parse_args()
@@ -166,8 +170,99 @@ def cpu_baseline(walkers: int):
                       f"system (forward + adjoint), {dt:.1f} s"}
 
 
+def run_batch(mols, mode, steps, warmup, bits, batched=True):
+    """Forward + adjoint of every molecule per step, as one batch (one graph
+    launch) or as a loop of single-context calls."""
+    import torch
+    import paper_2512_16677_amd as qmk
+    dev = torch.device("cuda:0")
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    ctxs = [qmk.Context.from_system(m, bits=bits, mode=mode) for m in mols]
+    r = [[torch.from_numpy(np.ascontiguousarray(m.elec_coord)).to(dev)] for m in mols]
+    for x in r:
+        x.append((x[0] + 1e-3).contiguous())
+    g = torch.Generator(device=dev)
+    g.manual_seed(99)
+    ws = [torch.randn((m.walk_num, m.elec_num, 5, m.mo_num), generator=g, device=dev, dtype=dt) for m in mols]
+    outs = [torch.empty_like(w) for w in ws]
+    grads = [{"d_coef": torch.empty((m.mo_num, m.ao_num), dtype=torch.float64, device=dev),
+              "d_elec": torch.empty((m.walk_num, m.elec_num, 3), dtype=torch.float64, device=dev),
+              "d_nucl": torch.empty((m.nucl_num, 3), dtype=torch.float64, device=dev)} for m in mols]
+    b = qmk.Batch(ctxs) if batched else None
+
+    def step(i):
+        for c, x in zip(ctxs, r):
+            c.set_point(x[i % 2])
+        if batched:
+            b.run(outs=outs, dtype=dt, ws=ws, grads=grads)
+        else:
+            for c, o, w, gr in zip(ctxs, outs, ws, grads):
+                c.get_mo_vgl(out=o)
+                c.adjoint(w, out=gr)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if b:
+        b.close()
+    for c in ctxs:
+        c.close()
+    return ms
+
+
+def main_batch(a):
+    import synth
+    mols = synth.molecule_batch(96, seed=0)
+    pts = sum(m.point_num for m in mols)
+    res = {}
+    for mode in ["fp64"] + [v for v in a.variants.split(",") if v]:
+        bits = 53 if mode == "fp64" else a.mixed_bits
+        ms_b = run_batch(mols, mode, a.steps, a.warmup, bits, batched=True)
+        ms_l = run_batch(mols, mode, max(2, a.steps // 2), 1, bits, batched=False)
+        res[mode] = {"value": pts / (ms_b * 1e-3), "ms_per_step": ms_b,
+                     "unbatched_ms_per_step": ms_l, "batching_speedup": ms_l / ms_b}
+    line = {"metric": METRIC, "value": res["fp64"]["value"], "unit": "e-evals/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["fp64"]["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "batch96: 96 C/H molecules, 4-60 atoms, 8-128 walkers each, "
+                                   "one persistent-kernel HIP graph per step; forward + adjoint",
+                       "points_per_step": pts, "molecules": len(mols),
+                       "ao_range": [min(m.ao_num for m in mols), max(m.ao_num for m in mols)]},
+            "modes": res}
+    print(json.dumps(line))
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size: under a hardware-counter
+    profile its FETCH_SIZE / WRITE_SIZE give the factor that turns those
+    counters into bytes."""
+    import torch
+    n = 1 << 27  # float64 elements: 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
+    if a.workload == "batch96":
+        if a.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        main_batch(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU "
                                    "sharding over walkers is described in the design notes, "

@@ -43,23 +43,46 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        I64 = ctypes.c_int64
-        lib.oracle_ao_num.argtypes = [I64, P]
-        lib.oracle_ao_num.restype = I64
-        lib.oracle_normalisation.argtypes = [I64, P, P, P, P, P, P, P]
-        lib.oracle_normalisation.restype = None
-        lib.oracle_ao_derivs.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, ctypes.c_double,
-                                         ctypes.c_int, P]
-        lib.oracle_ao_derivs.restype = ctypes.c_int
-        lib.oracle_mo_vgl.argtypes = [I64, I64, I64, P, P, P]
-        lib.oracle_mo_vgl.restype = ctypes.c_int
-        lib.oracle_adjoint.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, ctypes.c_double,
-                                       I64, P, P, P, P, P, P, P, P]
-        lib.oracle_adjoint.restype = ctypes.c_int
-        _lib = lib
+        _load_from(ctypes.CDLL(_LIB))
     return _lib
+
+
+def use_library(path: Optional[str]):
+    """Load the oracle's arithmetic from another build of oracle.c (the
+    mutation tests plant mistakes in copies); None restores the default."""
+    global _lib
+    _lib = None
+    if path is None:
+        return _load()
+    lib = ctypes.CDLL(path)
+    global _LIB
+    saved = _LIB
+    try:
+        _LIB = path
+        _lib = None
+        return _load_from(lib)
+    finally:
+        _LIB = saved
+
+
+def _load_from(lib):
+    global _lib
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    lib.oracle_ao_num.argtypes = [I64, P]
+    lib.oracle_ao_num.restype = I64
+    lib.oracle_normalisation.argtypes = [I64, P, P, P, P, P, P, P]
+    lib.oracle_normalisation.restype = None
+    lib.oracle_ao_derivs.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, ctypes.c_double,
+                                     ctypes.c_int, P]
+    lib.oracle_ao_derivs.restype = ctypes.c_int
+    lib.oracle_mo_vgl.argtypes = [I64, I64, I64, P, P, P]
+    lib.oracle_mo_vgl.restype = ctypes.c_int
+    lib.oracle_adjoint.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, ctypes.c_double,
+                                   I64, P, P, P, P, P, P, P, P]
+    lib.oracle_adjoint.restype = ctypes.c_int
+    _lib = lib
+    return lib
 
 
 def _c(a, dtype):

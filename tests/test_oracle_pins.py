@@ -378,3 +378,31 @@ def test_adjoint_finite_differences_and_sum_rule():
     tot = g["d_nucl"].sum(axis=0) + g["d_elec"].sum(axis=0)
     scale = g["d_nucl_abs"].sum(axis=0) + g["d_elec_abs"].sum(axis=0)
     assert np.all(np.abs(tot) <= 1e-11 * scale)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3])
+def test_contraction_weights_are_quadrature_normalised_primitives(l):
+    """A contracted shell is the unit-norm combination sum_k a_k phi_k of
+    primitives phi_k that are themselves unit-norm.  Each phi_k is normalised
+    here by numerical quadrature (no closed form), so the relative weights of
+    the primitives are fixed independently of the oracle's factors."""
+    gam = np.array([0.3, 1.7, 9.0])
+    a = np.array([0.8, 0.35, 0.6])
+    s = one_shell_system(l, gam, a)
+    x, w = _sinh_rule()
+    pts = np.random.default_rng(l).normal(scale=0.7, size=(25, 3))
+    got = oracle.ao_derivs(s, pts, B=0.0)[:, 0, 0]  # axis component x^l
+    # 1-D quadrature of x^(2l) exp(-2 g x^2) and exp(-2 g x^2) gives each primitive's norm
+    norms = np.array([np.sqrt(np.sum(w * x ** (2 * l) * np.exp(-2 * g * x * x)) *
+                              np.sum(w * np.exp(-2 * g * x * x)) ** 2) for g in gam])
+    prim = pts[:, 0:1] ** l * np.exp(-np.sum(pts ** 2, axis=1, keepdims=True) * gam[None, :]) / norms
+    combo = prim @ a
+    # normalise the combination by quadrature of its square (cross overlaps numerically)
+    ov = 0.0
+    for i in range(3):
+        for j in range(3):
+            gi, gj = gam[i], gam[j]
+            ov += a[i] * a[j] / (norms[i] * norms[j]) * (
+                np.sum(w * x ** (2 * l) * np.exp(-(gi + gj) * x * x)) *
+                np.sum(w * np.exp(-(gi + gj) * x * x)) ** 2)
+    np.testing.assert_allclose(got, combo / np.sqrt(ov), rtol=1e-9, atol=1e-14)
