@@ -25,6 +25,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmk.so")
+# tile shapes chosen by the library's autotuner on an MI355X for the shapes of
+# the shipped workloads (read-only; new shapes are timed on first use)
+TILE_TABLE = os.path.join(_HERE, "tiles_gfx950.json")
 
 QMK_OK = 0
 QMK_INVALID_CONTEXT = 1
@@ -67,6 +70,8 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libqmk.so not built at {path}: run paper_2512_16677_amd/build.py "
                           "(there is no CPU fallback)")
+    if "QMK_TUNE_TABLE" not in os.environ and os.path.exists(TILE_TABLE):
+        os.environ["QMK_TUNE_TABLE"] = TILE_TABLE
     lib = ctypes.CDLL(path)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {

@@ -19,17 +19,24 @@ OUT = os.path.join(HERE, "libqmk.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["context.cpp", "batch.cpp", "tuner.cpp", "ao_kernels.hip", "gemm_kernels.hip", "gemm_bf16.hip",
-           "adjoint_kernels.hip"]
+# (source, extra defines, object name): the MFMA product sources are compiled
+# once per (precision, product) unit so that their many tile instantiations
+# build in parallel.
+SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [], None),
+           ("ao_kernels.hip", [], None), ("adjoint_kernels.hip", [], None),
+           ("gemm_kernels.hip", [], None), ("gemm_bf16.hip", [], None)]
+SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_kernels_u{u}") for u in range(1, 7)]
+SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_bf16_u{u}") for u in range(1, 4)]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item) -> str:
+    src, defs, name = item
+    obj = os.path.join(BUILD_DIR, (name or os.path.basename(src)) + ".o")
+    cmd = [HIPCC] + COMMON + DEVICE_FLAGS + defs + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -38,7 +45,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4, 16)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp] + objs

@@ -863,6 +863,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ga.nsplit = static_cast<int32_t>(nsplit);
       ga.nbatch = 5;
       ga.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
+      ga.map_slab = 1;
       hipError_t e;
       {
         LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);

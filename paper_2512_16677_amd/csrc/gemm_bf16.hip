@@ -23,6 +23,14 @@
 #include "qmk_internal.h"
 
 namespace qmk {
+
+struct BfPersist {
+  const GemmArgs* jobs;
+  const WorkItem* items;
+  int n_items, grid;
+  int* occupancy;
+};
+
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -128,9 +136,9 @@ __device__ __forceinline__ void pair_load(const TS* p, TS& a, TS& b) {
 //   KC: reduction index contiguous (runs of 8 along k), else rows
 //   contiguous (2-row x 8-k micro-tiles, transposed in registers).
 // Element (row, l) of the operand is at base[row * s_row + l * s_l].
-template <typename TS, bool KC, int ROWS, int NT>
+template <typename TS, bool KC, int ROWS, int NT, int BK>
 struct TileLoader {
-  static constexpr int BK = 32, LDK = BK + 8;
+  static constexpr int LDK = BK + 8;
   static constexpr int UNITS = KC ? ROWS * (BK / 8) : (ROWS / 2) * (BK / 8);
   static constexpr int PER = (UNITS + NT - 1) / NT;
   static constexpr bool PRE = std::is_same<TS, PreSplit>::value;
@@ -244,18 +252,19 @@ struct TileLoader {
   }
 };
 
-template <int BM, int BN>
+template <int BM, int BN, int BK>
 struct BfSmem {
-  static constexpr int LDK = 32 + 8;
+  static constexpr int LDK = BK + 8;
   __bf16 A[2][2][BM * LDK];  // [buffer][hi, lo][row * LDK + k]
   __bf16 B[2][2][BN * LDK];
 };
 
-template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK>
 __device__ __forceinline__ void bf16x3_body(const GemmArgs& g, int mt, int nt, int z,
-                                            BfSmem<16 * WGM * TM, 16 * WGN * TN>& sm) {
+                                            BfSmem<16 * WGM * TM, 16 * WGN * TN, BK>& sm) {
   constexpr int NT = 64 * WGM * WGN;
-  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, BK = 32, LDK = BK + 8;
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, LDK = BK + 8;
   auto& sA = sm.A;
   auto& sB = sm.B;
   const int c = z / g.nsplit, s = z - c * g.nsplit;
@@ -271,8 +280,8 @@ __device__ __forceinline__ void bf16x3_body(const GemmArgs& g, int mt, int nt, i
 
   // A rows are i (stride sAi), reduction l (stride sAl); B rows are j
   // (stride sBj), reduction l (stride sBl = 1).
-  TileLoader<TA, A_KC, BM, NT> la;
-  TileLoader<TB, true, BN, NT> lb;
+  TileLoader<TA, A_KC, BM, NT, BK> la;
+  TileLoader<TB, true, BN, NT, BK> lb;
   auto load = [&](int64_t l0) {
     const int64_t rows_a = g.M - i0, rows_b = g.N - j0, lleft = Ls - l0;
     const bool a_fast = a_vec && rows_a >= BM && lleft >= BK;
@@ -302,27 +311,30 @@ __device__ __forceinline__ void bf16x3_body(const GemmArgs& g, int mt, int nt, i
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = static_cast<int>(kt & 1);
     if (kt + 1 < nk) load((kt + 1) * BK);
-    bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-    for (int a = 0; a < TM; ++a) {
-      const int off = ((wm * TM + a) * 16 + ri) * LDK + kq;
-      ah[a] = *reinterpret_cast<const bf16x8*>(&sA[buf][0][off]);
-      al[a] = *reinterpret_cast<const bf16x8*>(&sA[buf][1][off]);
-    }
+    for (int kk = 0; kk < BK / 32; ++kk) {
+      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-    for (int b = 0; b < TN; ++b) {
-      const int off = ((wn * TN + b) * 16 + ri) * LDK + kq;
-      bh[b] = *reinterpret_cast<const bf16x8*>(&sB[buf][0][off]);
-      bl[b] = *reinterpret_cast<const bf16x8*>(&sB[buf][1][off]);
-    }
-#pragma unroll
-    for (int a = 0; a < TM; ++a)
+      for (int a = 0; a < TM; ++a) {
+        const int off = ((wm * TM + a) * 16 + ri) * LDK + kk * 32 + kq;
+        ah[a] = *reinterpret_cast<const bf16x8*>(&sA[buf][0][off]);
+        al[a] = *reinterpret_cast<const bf16x8*>(&sA[buf][1][off]);
+      }
 #pragma unroll
       for (int b = 0; b < TN; ++b) {
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        const int off = ((wn * TN + b) * 16 + ri) * LDK + kk * 32 + kq;
+        bh[b] = *reinterpret_cast<const bf16x8*>(&sB[buf][0][off]);
+        bl[b] = *reinterpret_cast<const bf16x8*>(&sB[buf][1][off]);
       }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
     if (kt + 1 < nk) {
       la.stash(sA[buf ^ 1][0], sA[buf ^ 1][1], tid);
       lb.stash(sB[buf ^ 1][0], sB[buf ^ 1][1], tid);
@@ -343,74 +355,67 @@ __device__ __forceinline__ void bf16x3_body(const GemmArgs& g, int mt, int nt, i
       }
 }
 
-template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_kernel(GemmArgs g, int nM, int nN) {
-  __shared__ __align__(16) BfSmem<16 * WGM * TM, 16 * WGN * TN> sm;
-  const int bid = blockIdx.x;
-  int mt, nt;
-  if (nM >= 8) {
-    const int x = bid & 7, j = bid >> 3;
-    mt = (j / nN) * 8 + x;
-    nt = j % nN;
-  } else {
-    mt = bid / nN;
-    nt = bid % nN;
-  }
-  if (mt >= nM) return;
-  bf16x3_body<TA, A_KC, TB, TD, WGM, WGN, TM, TN>(g, mt, nt, blockIdx.y, sm);
+  __shared__ __align__(16) BfSmem<16 * WGM * TM, 16 * WGN * TN, BK> sm;
+  int mt, nt, z;
+  if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
+  bf16x3_body<TA, A_KC, TB, TD, WGM, WGN, TM, TN, BK>(g, mt, nt, z, sm);
 }
 
-template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16x3_persist(
     const GemmArgs* __restrict__ jobs, const WorkItem* __restrict__ items, int n_items) {
-  __shared__ __align__(16) BfSmem<16 * WGM * TM, 16 * WGN * TN> sm;
+  __shared__ __align__(16) BfSmem<16 * WGM * TM, 16 * WGN * TN, BK> sm;
   for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
     const WorkItem it = items[i];
-    bf16x3_body<TA, A_KC, TB, TD, WGM, WGN, TM, TN>(jobs[it.job], it.a, it.b, it.c, sm);
+    bf16x3_body<TA, A_KC, TB, TD, WGM, WGN, TM, TN, BK>(jobs[it.job], it.a, it.b, it.c, sm);
     __syncthreads();
   }
 }
 
+// {WGM, WGN, TM, TN, BK}
 #define QMK_BF16_TILE_LIST(X) \
-  X(0, 2, 2, 4, 4)            \
-  X(1, 4, 1, 4, 5)            \
-  X(2, 2, 2, 4, 5)            \
-  X(3, 2, 2, 2, 4)            \
-  X(4, 1, 2, 5, 5)            \
-  X(5, 2, 2, 2, 5)            \
-  X(6, 2, 2, 4, 2)            \
-  X(7, 2, 2, 4, 3)            \
-  X(8, 2, 1, 5, 5)            \
-  X(9, 4, 1, 2, 5)
+  X(0, 2, 2, 4, 4, 32)        \
+  X(1, 4, 1, 4, 5, 32)        \
+  X(2, 2, 2, 4, 5, 32)        \
+  X(3, 2, 2, 2, 4, 32)        \
+  X(4, 1, 2, 5, 5, 32)        \
+  X(5, 2, 2, 2, 5, 32)        \
+  X(6, 2, 2, 4, 2, 32)        \
+  X(7, 2, 2, 4, 3, 32)        \
+  X(8, 2, 1, 5, 5, 32)        \
+  X(9, 4, 1, 2, 5, 32)        \
+  X(10, 2, 2, 4, 4, 64)       \
+  X(11, 4, 1, 2, 5, 64)       \
+  X(12, 2, 2, 2, 4, 64)       \
+  X(13, 2, 1, 4, 5, 64)       \
+  X(14, 2, 2, 4, 2, 64)
 
 constexpr TileCfg kBfTiles[] = {
-#define QMK_BF_ENTRY(id, wgm, wgn, tm, tn) {wgm, wgn, tm, tn, 32},
+#define QMK_BF_ENTRY(id, wgm, wgn, tm, tn, bk) {wgm, wgn, tm, tn, bk},
     QMK_BF16_TILE_LIST(QMK_BF_ENTRY)
 #undef QMK_BF_ENTRY
 };
 
-template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK>
 hipError_t run_bf_tile(const GemmArgs& g, hipStream_t s) {
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
   if (nM <= 0 || nN <= 0) return hipSuccess;
-  const int gx = nM >= 8 ? 8 * nN * ((nM + 7) / 8) : nM * nN;
-  dim3 grid(gx, g.nbatch * g.nsplit);
-  hipLaunchKernelGGL((gemm_bf16x3_kernel<TA, A_KC, TB, TD, WGM, WGN, TM, TN>), grid,
+  const dim3 grid = grid_of(g, nM, nN);
+  hipLaunchKernelGGL((gemm_bf16x3_kernel<TA, A_KC, TB, TD, WGM, WGN, TM, TN, BK>), grid,
                      dim3(64 * WGM * WGN), 0, s, g, nM, nN);
   return hipGetLastError();
 }
 
-struct BfPersist {
-  const GemmArgs* jobs;
-  const WorkItem* items;
-  int n_items, grid;
-  int* occupancy;
-};
-
-template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN>
+template <typename TA, bool A_KC, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK>
 hipError_t run_bf_tile_persist(const BfPersist& pl, hipStream_t s) {
-  auto k = gemm_bf16x3_persist<TA, A_KC, TB, TD, WGM, WGN, TM, TN>;
+  auto k = gemm_bf16x3_persist<TA, A_KC, TB, TD, WGM, WGN, TM, TN, BK>;
   if (pl.occupancy) {
     int n = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * WGM * WGN, 0);
@@ -425,9 +430,9 @@ hipError_t run_bf_tile_persist(const BfPersist& pl, hipStream_t s) {
 template <typename TA, bool A_KC, typename TB, typename TD>
 hipError_t run_bf_persist(int cfg, const BfPersist& pl, hipStream_t s) {
   switch (cfg) {
-#define QMK_BF_PCASE(id, wgm, wgn, tm, tn) \
-  case id:                                 \
-    return run_bf_tile_persist<TA, A_KC, TB, TD, wgm, wgn, tm, tn>(pl, s);
+#define QMK_BF_PCASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                     \
+    return run_bf_tile_persist<TA, A_KC, TB, TD, wgm, wgn, tm, tn, bk>(pl, s);
     QMK_BF16_TILE_LIST(QMK_BF_PCASE)
 #undef QMK_BF_PCASE
     default:
@@ -438,9 +443,9 @@ hipError_t run_bf_persist(int cfg, const BfPersist& pl, hipStream_t s) {
 template <typename TA, bool A_KC, typename TB, typename TD>
 hipError_t run_bf(int cfg, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
-#define QMK_BF_CASE(id, wgm, wgn, tm, tn) \
-  case id:                                \
-    return run_bf_tile<TA, A_KC, TB, TD, wgm, wgn, tm, tn>(g, s);
+#define QMK_BF_CASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                    \
+    return run_bf_tile<TA, A_KC, TB, TD, wgm, wgn, tm, tn, bk>(g, s);
     QMK_BF16_TILE_LIST(QMK_BF_CASE)
 #undef QMK_BF_CASE
     default:
@@ -450,50 +455,77 @@ hipError_t run_bf(int cfg, const GemmArgs& g, hipStream_t s) {
 
 }  // namespace
 
+#ifdef QMK_GEMM_UNIT
+#if QMK_GEMM_UNIT == 1
+hipError_t bf16_unit_fwd(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
+                          hipStream_t s) {
+  const bool alt = o32 != 0;
+  if (pl) return alt ? run_bf_persist<float, false, PreSplit, float>(cfg, *pl, s) : run_bf_persist<float, false, PreSplit, double>(cfg, *pl, s);
+  return alt ? run_bf<float, false, PreSplit, float>(cfg, *g, s) : run_bf<float, false, PreSplit, double>(cfg, *g, s);
+}
+#endif
+#if QMK_GEMM_UNIT == 2
+hipError_t bf16_unit_gbar(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
+                          hipStream_t s) {
+  const bool alt = w32 != 0;
+  if (pl) return alt ? run_bf_persist<float, true, PreSplit, float>(cfg, *pl, s) : run_bf_persist<double, true, PreSplit, float>(cfg, *pl, s);
+  return alt ? run_bf<float, true, PreSplit, float>(cfg, *g, s) : run_bf<double, true, PreSplit, float>(cfg, *g, s);
+}
+#endif
+#if QMK_GEMM_UNIT == 3
+hipError_t bf16_unit_dc(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
+                          hipStream_t s) {
+  const bool alt = w32 != 0;
+  if (pl) return alt ? run_bf_persist<float, false, float, double>(cfg, *pl, s) : run_bf_persist<double, false, float, double>(cfg, *pl, s);
+  return alt ? run_bf<float, false, float, double>(cfg, *g, s) : run_bf<double, false, float, double>(cfg, *g, s);
+}
+#endif
+#else
+// The three products are instantiated in their own translation units (this
+// file compiled with QMK_GEMM_UNIT = 1..3); the unit without it holds the
+// tile table and the dispatch.
+hipError_t bf16_unit_fwd(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
+                          hipStream_t s);
+hipError_t bf16_unit_gbar(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
+                          hipStream_t s);
+hipError_t bf16_unit_dc(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
+                          hipStream_t s);
+
 int gemm_bf16_num_tiles() { return sizeof(kBfTiles) / sizeof(kBfTiles[0]); }
 TileCfg gemm_bf16_tile(int cfg) { return kBfTiles[cfg]; }
 size_t gemm_bf16_tile_lds_bytes(int cfg) {
   const TileCfg& t = kBfTiles[cfg];
-  return 2 * 2 * static_cast<size_t>(16 * t.wgm * t.tm + 16 * t.wgn * t.tn) * (32 + 8) * 2;
+  return 2 * 2 * static_cast<size_t>(16 * t.wgm * t.tm + 16 * t.wgn * t.tn) * (t.bk + 8) * 2;
 }
 
 // forward: A = AO array (FP32, rows contiguous), B = C split (k contiguous)
 // Gbar:    A = W (k contiguous),                 B = C^T split (k contiguous)
 // dC:      A = W^T (rows contiguous),            B = AO array (k contiguous)
-hipError_t launch_gemm_bf16x3(GemmKind kind, int cfg, const GemmArgs& g, int w_is_f32,
-                              int out_is_f32, hipStream_t s) {
+namespace {
+hipError_t bf16_dispatch(GemmKind kind, int cfg, const GemmArgs* g, const BfPersist* pl, int w32,
+                         int o32, hipStream_t s) {
   if (cfg < 0 || cfg >= gemm_bf16_num_tiles()) return hipErrorInvalidValue;
   switch (kind) {
-    case GemmKind::kForward:
-      return out_is_f32 ? run_bf<float, false, PreSplit, float>(cfg, g, s)
-                        : run_bf<float, false, PreSplit, double>(cfg, g, s);
-    case GemmKind::kGbar:
-      return w_is_f32 ? run_bf<float, true, PreSplit, float>(cfg, g, s)
-                      : run_bf<double, true, PreSplit, float>(cfg, g, s);
-    case GemmKind::kDcoef:
-      return w_is_f32 ? run_bf<float, false, float, double>(cfg, g, s)
-                      : run_bf<double, false, float, double>(cfg, g, s);
+    case GemmKind::kForward: return bf16_unit_fwd(cfg, g, pl, w32, o32, s);
+    case GemmKind::kGbar: return bf16_unit_gbar(cfg, g, pl, w32, o32, s);
+    case GemmKind::kDcoef: return bf16_unit_dc(cfg, g, pl, w32, o32, s);
   }
   return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_gemm_bf16x3(GemmKind kind, int cfg, const GemmArgs& g, int w_is_f32,
+                              int out_is_f32, hipStream_t s) {
+  return bf16_dispatch(kind, cfg, &g, nullptr, w_is_f32, out_is_f32, s);
 }
 
 hipError_t launch_gemm_bf16x3_persist(GemmKind kind, int cfg, const GemmArgs* jobs,
                                       const WorkItem* items, int n_items, int grid, int w_is_f32,
                                       int out_is_f32, int* occupancy, hipStream_t s) {
-  if (cfg < 0 || cfg >= gemm_bf16_num_tiles()) return hipErrorInvalidValue;
   const BfPersist pl{jobs, items, n_items, grid, occupancy};
-  switch (kind) {
-    case GemmKind::kForward:
-      return out_is_f32 ? run_bf_persist<float, false, PreSplit, float>(cfg, pl, s)
-                        : run_bf_persist<float, false, PreSplit, double>(cfg, pl, s);
-    case GemmKind::kGbar:
-      return w_is_f32 ? run_bf_persist<float, true, PreSplit, float>(cfg, pl, s)
-                      : run_bf_persist<double, true, PreSplit, float>(cfg, pl, s);
-    case GemmKind::kDcoef:
-      return w_is_f32 ? run_bf_persist<float, false, float, double>(cfg, pl, s)
-                      : run_bf_persist<double, false, float, double>(cfg, pl, s);
-  }
-  return hipErrorInvalidValue;
+  return bf16_dispatch(kind, cfg, nullptr, &pl, w_is_f32, out_is_f32, s);
 }
+
+#endif  // QMK_GEMM_UNIT
 
 }  // namespace qmk

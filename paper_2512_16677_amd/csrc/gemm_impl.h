@@ -1,0 +1,293 @@
+// Templates of the FP64 / FP32 MFMA product (shared by the translation units
+// that instantiate them; see gemm_kernels.hip).
+#pragma once
+
+#include "qmk_internal.h"
+
+namespace qmk {
+
+struct PersistLaunch {
+  const GemmArgs* jobs;
+  const WorkItem* items;
+  int n_items, grid;
+  int* occupancy;  // when non-NULL: report resident blocks per CU instead of launching
+};
+
+namespace {
+
+
+template <typename T>
+struct Mfma;
+
+// Accumulator element r of lane l sits in column l % 16 and in row
+//   FP64 16x16x4:  l / 16 + 4 r
+//   FP32 16x16x4:  4 (l / 16) + r
+// (measured lane layouts on gfx950).
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Tile: WGM x WGN wavefronts, each owning TM x TN MFMA blocks of 16 x 16,
+// so the workgroup tile is BM = 16 WGM TM rows by BN = 16 WGN TN columns,
+// with a reduction step of BK.
+template <typename T, int BM, int BN, int BK>
+struct GemmSmem {
+  static constexpr int PAD = 16 / sizeof(T);
+  T A[2][BK][BM + PAD];
+  T B[2][BK][BN + PAD];
+};
+
+// One output tile (mt, nt) of batch index z.
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+__device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int z,
+                                          GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK>& sm) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+  constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
+  typedef typename Mfma<T>::v4 v4;
+  auto& As = sm.A;
+  auto& Bs = sm.B;
+  const int c = z / g.nsplit, s = z - c * g.nsplit;
+  const TA* __restrict__ Ap = static_cast<const TA*>(g.A) + c * g.oAc + s * g.oAs;
+  const TB* __restrict__ Bp = static_cast<const TB*>(g.B) + c * g.oBc + s * g.oBs;
+  TD* __restrict__ Dp = static_cast<TD*>(g.D) + z * g.oDz;
+  const int64_t Ls = min(g.Lchunk, g.L - s * g.Lchunk);
+  const int64_t i0 = static_cast<int64_t>(mt) * BM, j0 = static_cast<int64_t>(nt) * BN;
+  const int tid = threadIdx.x;
+
+  T ra[EA], rb[EB];
+  // Operand tiles fully inside the matrices take an unguarded path (uniform
+  // branch per K step); only edge tiles test every element.
+  const bool a_rows_in = i0 + BM <= g.M, b_cols_in = j0 + BN <= g.N;
+  auto load = [&](int64_t l0) {
+    const bool l_in = l0 + BK <= Ls;
+    if (a_rows_in && l_in && BM * BK % NT == 0) {
+      const TA* base = Ap + i0 * g.sAi + l0 * g.sAl;
+#pragma unroll
+      for (int r = 0; r < EA; ++r) {
+        const int e = tid + NT * r;
+        const int i = A_I ? e % BM : e / BK;
+        const int l = A_I ? e / BM : e % BK;
+        ra[r] = static_cast<T>(base[i * g.sAi + l * g.sAl]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < EA; ++r) {
+        const int e = tid + NT * r;
+        const int i = A_I ? e % BM : e / BK;
+        const int l = A_I ? e / BM : e % BK;
+        const int64_t gi = i0 + i, gl = l0 + l;
+        const bool in = (BM * BK % NT == 0 || e < BM * BK) && gi < g.M && gl < Ls;
+        ra[r] = in ? static_cast<T>(Ap[gi * g.sAi + gl * g.sAl]) : T(0);
+      }
+    }
+    if (b_cols_in && l_in && BK * BN % NT == 0) {
+      const TB* base = Bp + l0 * g.sBl + j0 * g.sBj;
+#pragma unroll
+      for (int r = 0; r < EB; ++r) {
+        const int e = tid + NT * r;
+        const int j = B_J ? e % BN : e / BK;
+        const int l = B_J ? e / BN : e % BK;
+        rb[r] = static_cast<T>(base[l * g.sBl + j * g.sBj]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < EB; ++r) {
+        const int e = tid + NT * r;
+        const int j = B_J ? e % BN : e / BK;
+        const int l = B_J ? e / BN : e % BK;
+        const int64_t gj = j0 + j, gl = l0 + l;
+        const bool in = (BK * BN % NT == 0 || e < BK * BN) && gj < g.N && gl < Ls;
+        rb[r] = in ? static_cast<T>(Bp[gl * g.sBl + gj * g.sBj]) : T(0);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < EA; ++r) {
+      const int e = tid + NT * r;
+      if (BM * BK % NT != 0 && e >= BM * BK) continue;
+      const int i = A_I ? e % BM : e / BK;
+      const int l = A_I ? e / BM : e % BK;
+      As[buf][l][i] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < EB; ++r) {
+      const int e = tid + NT * r;
+      if (BK * BN % NT != 0 && e >= BK * BN) continue;
+      const int j = B_J ? e % BN : e / BK;
+      const int l = B_J ? e / BN : e % BK;
+      Bs[buf][l][j] = rb[r];
+    }
+  };
+
+  const int lane = tid & 63, w = tid >> 6;
+  const int wm = w / WGN, wn = w % WGN;
+  v4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4{0, 0, 0, 0};
+
+  const int64_t nk = (Ls + BK - 1) / BK;
+  if (nk > 0) {
+    load(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = static_cast<int>(kt & 1);
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4), ci = lane & 15;
+      T fa[TM], fb[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) fa[a] = As[buf][kr][(wm * TM + a) * 16 + ci];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) fb[b] = Bs[buf][kr][(wn * TN + b) * 16 + ci];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::op(fa[a], fb[b], acc[a][b]);
+    }
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+        if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+      }
+}
+
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmArgs g, int nM, int nN) {
+  __shared__ GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK> sm;
+  int mt, nt, z;
+  if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
+  gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>(g, mt, nt, z, sm);
+}
+
+// Persistent form: the grid walks a list of (job, M tile, N tile, z).
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_persist(const GemmArgs* __restrict__ jobs,
+                                                               const WorkItem* __restrict__ items,
+                                                               int n_items) {
+  __shared__ GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK> sm;
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const WorkItem it = items[i];
+    gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>(jobs[it.job], it.a, it.b, it.c, sm);
+    __syncthreads();
+  }
+}
+
+__global__ void reduce_splits_kernel(const double* __restrict__ ws, int64_t nz, int64_t rows,
+                                     int64_t cols, int64_t ld_ws, int64_t z_stride,
+                                     double* __restrict__ out, int64_t ld_out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e / cols, c = e - r * cols;
+  double acc = 0.0;
+  for (int64_t z = 0; z < nz; ++z) acc += ws[z * z_stride + r * ld_ws + c];
+  out[r * ld_out + c] = acc;
+}
+
+// Tile configurations offered to the autotuner: {WGM, WGN, TM, TN, BK}.
+#define QMK_TILE_LIST(X) \
+  X(0, 2, 2, 4, 4, 16)   \
+  X(1, 4, 1, 4, 5, 16)   \
+  X(2, 2, 2, 4, 5, 16)   \
+  X(3, 2, 2, 5, 4, 16)   \
+  X(4, 1, 2, 5, 5, 16)   \
+  X(5, 2, 2, 2, 5, 16)   \
+  X(6, 2, 2, 4, 4, 32)   \
+  X(7, 2, 2, 4, 3, 16)   \
+  X(8, 2, 1, 5, 5, 16)   \
+  X(9, 4, 1, 2, 5, 32)
+
+constexpr TileCfg kTiles[] = {
+#define QMK_TILE_ENTRY(id, wgm, wgn, tm, tn, bk) {wgm, wgn, tm, tn, bk},
+    QMK_TILE_LIST(QMK_TILE_ENTRY)
+#undef QMK_TILE_ENTRY
+};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+hipError_t run_tile(const GemmArgs& g, hipStream_t s) {
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+  const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
+  if (nM <= 0 || nN <= 0) return hipSuccess;
+  const dim3 grid = grid_of(g, nM, nN);
+  hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>), grid,
+                     dim3(64 * WGM * WGN), 0, s, g, nM, nN);
+  return hipGetLastError();
+}
+
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK, bool A_I, bool B_J>
+hipError_t run_tile_persist(const PersistLaunch& pl, hipStream_t s) {
+  auto k = gemm_persist<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>;
+  if (pl.occupancy) {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * WGM * WGN, 0);
+    *pl.occupancy = (e == hipSuccess && n > 0) ? n : 1;
+    return e;
+  }
+  if (pl.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(pl.grid), dim3(64 * WGM * WGN), 0, s, pl.jobs, pl.items, pl.n_items);
+  return hipGetLastError();
+}
+
+template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
+hipError_t run_persist(int cfg, const PersistLaunch& pl, hipStream_t s) {
+  switch (cfg) {
+#define QMK_TILE_PCASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                       \
+    return run_tile_persist<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J>(pl, s);
+    QMK_TILE_LIST(QMK_TILE_PCASE)
+#undef QMK_TILE_PCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
+hipError_t run(int cfg, const GemmArgs& g, hipStream_t s) {
+  switch (cfg) {
+#define QMK_TILE_CASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                      \
+    return run_tile<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J>(g, s);
+    QMK_TILE_LIST(QMK_TILE_CASE)
+#undef QMK_TILE_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+}  // namespace qmk

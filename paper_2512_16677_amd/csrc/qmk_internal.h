@@ -90,7 +90,44 @@ struct GemmArgs {
   const void* A2;
   const void* B2;
   int32_t vec_ok;
+  // Workgroup -> tile order of the grid launch.  0: the N tiles of one M tile
+  // run back to back on one XCD (A tile reused from that XCD's L2).  1: all
+  // tiles of one batch index z run together on one XCD (split products,
+  // whose z slab of both operands is shared by every tile of that z).
+  int32_t map_slab;
 };
+
+// Tile of workgroup `bid` of a grid launch; false if it has none.  The
+// eight consecutive workgroup ids land on the eight XCDs of the MI355X.
+__device__ __forceinline__ bool grid_tile(const GemmArgs& g, int nM, int nN, int bid, int& mt,
+                                          int& nt, int& z) {
+  const int x = bid & 7, j = bid >> 3;
+  if (g.map_slab) {
+    const int tiles = nM * nN, nz = g.nbatch * g.nsplit;
+    z = (j / tiles) * 8 + x;
+    const int t = j % tiles;
+    mt = t / nN;
+    nt = t % nN;
+    return z < nz;
+  }
+  z = blockIdx.y;
+  if (nM >= 8) {
+    mt = (j / nN) * 8 + x;
+    nt = j % nN;
+    return mt < nM;
+  }
+  mt = bid / nN;
+  nt = bid % nN;
+  return mt < nM;
+}
+
+// Grid of a launch for GemmArgs g and tile counts nM x nN.
+inline dim3 grid_of(const GemmArgs& g, int nM, int nN) {
+  const int nz = g.nbatch * g.nsplit;
+  if (g.map_slab) return dim3(8 * nM * nN * ((nz + 7) / 8), 1);
+  const int gx = nM >= 8 ? 8 * nN * ((nM + 7) / 8) : nM * nN;
+  return dim3(gx, nz);
+}
 
 // Derivatives of t^e (e in 0..3, wave-uniform) of order 0..3, given t, t^2,
 // t^3: v0 = t^e, v1 = e t^(e-1), v2 = e(e-1) t^(e-2), v3 = e(e-1)(e-2) t^(e-3).

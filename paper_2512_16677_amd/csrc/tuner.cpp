@@ -7,6 +7,9 @@
 // including calls from other contexts -- reuse the choice.  The table of
 // choices can be persisted: QMK_TUNE_CACHE=<file> loads it at first use and
 // rewrites it after each new decision (a flat JSON object key -> tile id).
+// QMK_TUNE_TABLE=<file> names a read-only table of earlier decisions loaded
+// first (the Python binding points it at the table shipped with the
+// package), so that runs of known shapes use the same tiles every time.
 // QMK_TUNE=0 disables timing and picks the tile with the least padded work.
 #include <hip/hip_runtime.h>
 
@@ -33,11 +36,8 @@ const char* cache_path() {
   return (p && *p) ? p : nullptr;
 }
 
-void load_cache_locked() {
-  if (g_loaded) return;
-  g_loaded = true;
-  const char* path = cache_path();
-  if (!path) return;
+void load_file_locked(const char* path) {
+  if (!path || !*path) return;
   std::ifstream f(path);
   if (!f) return;
   std::stringstream ss;
@@ -54,6 +54,13 @@ void load_cache_locked() {
     i = s.find_first_of(",}", c);
     if (i == std::string::npos) break;
   }
+}
+
+void load_cache_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  load_file_locked(std::getenv("QMK_TUNE_TABLE"));
+  load_file_locked(cache_path());
 }
 
 void save_cache_locked() {
