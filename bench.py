@@ -128,9 +128,51 @@ def errors_vs(ref, got):
     return e
 
 
+KERNEL_SOURCES = {  # files whose change invalidates a kernel class's counter figures
+    "mo": ["gemm_impl.h", "gemm_kernels.hip", "gemm_bf16.hip", "qmk_internal.h", "context.cpp",
+           "tiles_gfx950.json"],
+    "ao": ["ao_kernels.hip", "qmk_internal.h", "context.cpp"],
+    "ao_adjoint": ["adjoint_kernels.hip", "qmk_internal.h", "context.cpp"],
+}
+KERNEL_SOURCES["gbar"] = KERNEL_SOURCES["dcoef"] = KERNEL_SOURCES["mo"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_ch80_800ao.txt")
+
+
+def sources_digest(name: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_2512_16677_amd")
+    for f in KERNEL_SOURCES[name]:
+        path = os.path.join(pkg, "csrc", f)
+        if not os.path.exists(path):
+            path = os.path.join(pkg, f)
+        with open(path, "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(mode: str, name: str):
+    """HBM bytes per launch of kernel class `name`, from the committed
+    hardware-counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the counter reads for a plain copy of known size).  None when the summary
+    has no entry or the kernel's sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = sources_digest(name)
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("mode") == mode and kv.get("class") == name:
+                return float(kv["bytes"]) if kv.get("sources") == want else None
+    return None
+
+
 def kernel_roofline(s, mode, timing):
     """Per-kernel algorithmic rates.  Contractions: 2*5*P*K*N flop per launch.
-    AO stage: 5*K*P*bytes(element) written + 24*P read per launch."""
+    AO stage: 5*K*P*bytes(element) written + 24*P read per launch; its adjoint
+    reads the AO-sized G-bar and writes 24 B per point."""
     P, K, N = s.point_num, s.ao_num, s.mo_num
     flop = 2.0 * 5 * P * K * N
     esz = 8 if mode == "fp64" else 4
@@ -139,19 +181,39 @@ def kernel_roofline(s, mode, timing):
         t = timing[name]
         if t["launches"]:
             avg = t["ms"] / t["launches"]
-            out[name] = {"avg_ms": avg, "TFLOPs": flop / (avg * 1e-3) / 1e12}
-    t = timing["ao"]
-    if t["launches"]:
-        avg = t["ms"] / t["launches"]
-        out["ao"] = {"avg_ms": avg, "GBps": (5.0 * K * P * esz + 24.0 * P) / (avg * 1e-3) / 1e9}
-    t = timing["ao_adjoint"]
-    if t["launches"]:
-        avg = t["ms"] / t["launches"]
-        out["ao_adjoint"] = {"avg_ms": avg,
-                             "GBps": (5.0 * K * P * esz + 48.0 * P) / (avg * 1e-3) / 1e9}
+            out[name] = {"avg_ms": avg, "launches": t["launches"], "flop": flop,
+                         "TFLOPs": flop / (avg * 1e-3) / 1e12}
+    for name, nbytes in (("ao", 5.0 * K * P * esz + 24.0 * P),
+                         ("ao_adjoint", 5.0 * K * P * esz + 48.0 * P)):
+        t = timing[name]
+        if t["launches"]:
+            avg = t["ms"] / t["launches"]
+            out[name] = {"avg_ms": avg, "launches": t["launches"], "bytes": nbytes,
+                         "GBps": nbytes / (avg * 1e-3) / 1e9}
     if timing["reduce"]["launches"]:
-        out["reduce"] = {"avg_ms": timing["reduce"]["ms"] / timing["reduce"]["launches"]}
+        out["reduce"] = {"avg_ms": timing["reduce"]["ms"] / timing["reduce"]["launches"],
+                         "launches": timing["reduce"]["launches"]}
     return out
+
+
+def dominant_roofline(mode, kr):
+    """Roofline entry for the kernel class with the largest share of step time."""
+    peak_key = {"fp64": "fp64_TFLOPs", "mixed_f32": "fp32_TFLOPs", "mixed_bf16x3": "bf16_TFLOPs"}[mode]
+    cands = {k: v for k, v in kr.items() if k != "reduce"}
+    name = max(cands, key=lambda k: cands[k]["avg_ms"] * cands[k]["launches"])
+    d = cands[name]
+    traffic = measured_traffic(mode, name)
+    if "TFLOPs" in d:
+        # BF16x3 issues three products per element; the algorithmic rate counts one
+        roof = {"bound": "mfma", "achieved": d["TFLOPs"], "peak": PEAKS[peak_key], "unit": "TFLOP/s",
+                "frac": d["TFLOPs"] / PEAKS[peak_key]}
+    else:
+        roof = {"bound": "hbm", "achieved": d["GBps"], "peak": PEAKS["hbm_GBps"], "unit": "GB/s",
+                "frac": d["GBps"] / PEAKS["hbm_GBps"]}
+    roof.update({"traffic": traffic, "kernel": name, "avg_ms": d["avg_ms"],
+                 "traffic_unit": "bytes per launch (FETCH_SIZE, WRITE_SIZE scaled by a copy kernel)",
+                 "per_kernel": kr})
+    return roof
 
 
 def cpu_baseline(walkers: int):
@@ -279,12 +341,7 @@ def main():
                                   keep_outputs=bool(variants_list) and a.mode == "fp64")
     value = s.point_num / (ms * 1e-3)
     kr = kernel_roofline(s, a.mode, timing)
-    peak_key = {"fp64": "fp64_TFLOPs", "mixed_f32": "fp32_TFLOPs", "mixed_bf16x3": "bf16_TFLOPs"}[a.mode]
-    dom = kr.get("mo", {})
-    roof = {"bound": "mfma", "kernel": "mo contraction (forward GEMM)",
-            "achieved": dom.get("TFLOPs"), "peak": PEAKS[peak_key], "unit": "TFLOP/s",
-            "frac": (dom.get("TFLOPs") / PEAKS[peak_key]) if dom else None, "traffic": None,
-            "per_kernel": kr}
+    roof = dominant_roofline(a.mode, kr)
     line = {
         "metric": METRIC, "value": value, "unit": "e-evals/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -304,7 +361,7 @@ def main():
                        "speedup_vs_primary": ms / vms, "bits": a.mixed_bits,
                        "mo_gemm_frac_of_peak": (kv["mo"]["TFLOPs"] * (3 if m == "mixed_bf16x3" else 1) / peak_v)
                        if "mo" in kv else None,
-                       "per_kernel": kv}
+                       "roofline": dominant_roofline(m, kv)}
         if vout is not None:
             variants[m]["error_vs_fp64_gpu"] = errors_vs(ref_out, vout)
         del vout
