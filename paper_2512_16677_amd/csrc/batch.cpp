@@ -134,7 +134,8 @@ std::vector<WorkItem> gemm_items(qmk_batch b, GemmKind kind, int cfg) {
     if (kind == GemmKind::kForward) {
       M = mp.P; N = mp.N; L = mp.K; nz = 5;
     } else if (kind == GemmKind::kGbar) {
-      M = mp.P; N = mp.K; L = mp.N; nz = 5;
+      const bool rows_k = b->prec != Prec::kBF16x3;  // see gbar_args
+      M = rows_k ? mp.K : mp.P; N = rows_k ? mp.P : mp.K; L = mp.N; nz = 5;
     } else {
       M = mp.N; N = mp.K; L = mp.chunk; nz = 5 * mp.nsplit;
     }
@@ -248,28 +249,8 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.N = mp.N;
     g.L = g.Lchunk = mp.K;
   } else if (kind == GemmKind::kGbar) {
-    g.A = w;
-    g.sAi = 5 * mp.N;
-    g.sAl = 1;
-    g.oAc = mp.N;
-    if (bf) {
-      g.B = c->d_Ctb_hi.p;
-      g.B2 = c->d_Ctb_lo.p;
-      g.sBl = 1;
-      g.sBj = mp.Np;
-      g.vec_ok = (w_vec_ok(w, mp.N, b->tile_w32) ? 1 : 0) | 2;
-    } else {
-      g.B = c->d_C.p;
-      g.sBl = mp.Kp;
-      g.sBj = 1;
-    }
-    g.D = gbp;
-    g.sDi = 1;
-    g.sDj = 5 * mp.Pp;
-    g.oDz = mp.Pp;
-    g.M = mp.P;
-    g.N = mp.K;
-    g.L = g.Lchunk = mp.N;
+    g = gbar_args(b->prec, w, b->tile_w32, c->d_C.p, c->d_Ctb_hi.p, c->d_Ctb_lo.p, gbp, mp.P,
+                  mp.Pp, mp.K, mp.Kp, mp.N, mp.Np);
   } else {
     g.A = w;
     g.sAi = 1;

@@ -138,13 +138,16 @@ qmk_status build_tables(qmk_ctx ctx) {
     int64_t np = 0;
     for (int64_t s : shells_of[A]) np += ctx->sh_off[s + 1] - ctx->sh_off[s];
     const int64_t nsh = static_cast<int64_t>(shells_of[A].size());
+    int64_t nao = 0;
+    for (int64_t s : shells_of[A]) nao += n_cart(ctx->sh_l[s]);
     if (np > kGroupMaxPrim || nsh > kGroupMaxShell)
       return fail(ctx, QMK_UNSUPPORTED, "nucleus " + std::to_string(A) + " has more than " +
                                             std::to_string(kGroupMaxPrim) + " primitives or " +
                                             std::to_string(kGroupMaxShell) + " shells");
     if ((cur.p_end - cur.p_begin) + np > kGroupMaxPrim ||
         (cur.sh_end - cur.sh_begin) + nsh > kGroupMaxShell ||
-        (cur.nuc_end - cur.nuc_begin) + 1 > kGroupMaxNuc)
+        (cur.nuc_end - cur.nuc_begin) + 1 > kGroupMaxNuc ||
+        (cur.n_ao > 0 && cur.n_ao + nao > kGroupMaxAo))
       close_group();
     NucDev nd{};
     nd.x = ctx->nucl[3 * A];
@@ -177,6 +180,7 @@ qmk_status build_tables(qmk_ctx ctx) {
     cur.nuc_end = static_cast<int32_t>(nuc.size());
     cur.sh_end = static_cast<int32_t>(shell.size());
     cur.p_end = static_cast<int32_t>(prim.size());
+    cur.n_ao += static_cast<int32_t>(nao);
   }
   close_group();
   if (group.empty()) return fail(ctx, QMK_NOT_SET, "basis has no shells");
@@ -366,6 +370,52 @@ bool w_vec_ok(const void* w, int64_t N, int w32) {
 
 Prec gemm_prec(qmk_ctx ctx) {
   return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16x3);
+}
+
+GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void* Ct_hi,
+                   const void* Ct_lo, void* gbar, int64_t P, int64_t Pp, int64_t K, int64_t Kp,
+                   int64_t N, int64_t Np) {
+  GemmArgs g{};
+  g.L = g.Lchunk = N;
+  g.nsplit = 1;
+  g.nbatch = 5;
+  if (prec == Prec::kBF16x3) {
+    // rows (p, c), columns k: both operands read along the reduction index n
+    g.A = w;
+    g.sAi = 5 * N;
+    g.sAl = 1;
+    g.oAc = N;
+    g.B = Ct_hi;  // C^T [k][n], split into bf16 hi + lo
+    g.B2 = Ct_lo;
+    g.sBl = 1;
+    g.sBj = Np;
+    g.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
+    g.D = gbar;
+    g.sDi = 1;
+    g.sDj = 5 * Pp;
+    g.oDz = Pp;
+    g.M = P;
+    g.N = K;
+    return g;
+  }
+  // rows k, columns p: consecutive accumulator lanes own consecutive points,
+  // so Gbar (point index contiguous) is stored in full lines; the N tiles of
+  // W run on one XCD together with every M tile that reads them
+  g.A = C;  // C [n][k]
+  g.sAi = 1;
+  g.sAl = Kp;
+  g.B = w;  // W [p][c][n]
+  g.sBl = 1;
+  g.sBj = 5 * N;
+  g.oBc = N;
+  g.D = gbar;
+  g.sDi = 5 * Pp;
+  g.sDj = 1;
+  g.oDz = Pp;
+  g.M = K;
+  g.N = P;
+  g.map_slab = 2;
+  return g;
 }
 
 }  // namespace qmk
@@ -753,33 +803,9 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ctx->gbar_Kp = Kp;
       ctx->gbar_f32 = f32;
     }
-    GemmArgs ga{};
-    ga.A = w;
-    ga.sAi = 5 * N;
-    ga.sAl = 1;
-    ga.oAc = N;
-    if (prec == Prec::kBF16x3) {
-      ga.B = ctx->d_Ctb_hi.p;  // C^T [k][n]: reduction index contiguous
-      ga.B2 = ctx->d_Ctb_lo.p;
-      ga.sBl = 1;
-      ga.sBj = Np;
-      ga.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
-    } else {
-      ga.B = ctx->d_C.p;
-      ga.sBl = Kp;
-      ga.sBj = 1;
-    }
-    ga.D = ctx->gbar.p;
-    ga.sDi = 1;
-    ga.sDj = 5 * Pp;
-    ga.oDz = Pp;
-    ga.M = P;
-    ga.N = K;
-    ga.L = N;
-    ga.Lchunk = N;
-    ga.nsplit = 1;
-    ga.nbatch = 5;
-    const GemmProblem pb{GemmKind::kGbar, prec, w32, f32, P, K, N};
+    const GemmArgs ga = gbar_args(prec, w, w32, ctx->d_C.p, ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p,
+                                  ctx->gbar.p, P, Pp, K, Kp, N, Np);
+    const GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
     int cfg = 0;
     if ((st = pick_tile(ctx, pb, s, [&](int c) {
            return launch_gemm_typed(GemmKind::kGbar, prec, c, ga, w32, f32, s);

@@ -4,7 +4,9 @@
 //
 // One strided, batched kernel serves the three products of the path:
 //   forward   mo[p][c][n]   = sum_k ao[k][c][p] Ct[k][n]        (batch c)
-//   Gbar      Gb[k][c][p]   = sum_n W[p][c][n]  C[n][k]         (batch c)
+//   Gbar      Gb[k][c][p]   = sum_n C[n][k] W[p][c][n]          (batch c)
+//             (rows k, columns p: a 16-lane group of the accumulator stores
+//             16 consecutive points, so the output is written in full lines)
 //   dC        ws[c,s][n][k] = sum_{p in split s} W[p][c][n] ao[k][c][p]
 // (see GemmArgs for the index algebra).  A tile is WGM x WGN wavefronts,
 // each owning TM x TN MFMA 16x16x4 blocks (FP64 or FP32); the shapes on
@@ -33,8 +35,8 @@ hipError_t gemm_unit_f64_fwd(int cfg, const GemmArgs* g, const PersistLaunch* pl
 hipError_t gemm_unit_f64_gbar(int cfg, const GemmArgs* g, const PersistLaunch* pl, int w32, int o32,
                          hipStream_t s) {
   const bool alt = w32 != 0;
-  if (pl) return alt ? run_persist<double, float, double, double, false, true>(cfg, *pl, s) : run_persist<double, double, double, double, false, true>(cfg, *pl, s);
-  return alt ? run<double, float, double, double, false, true>(cfg, *g, s) : run<double, double, double, double, false, true>(cfg, *g, s);
+  if (pl) return alt ? run_persist<double, double, float, double, true, false>(cfg, *pl, s) : run_persist<double, double, double, double, true, false>(cfg, *pl, s);
+  return alt ? run<double, double, float, double, true, false>(cfg, *g, s) : run<double, double, double, double, true, false>(cfg, *g, s);
 }
 #endif
 #if QMK_GEMM_UNIT == 3
@@ -57,8 +59,8 @@ hipError_t gemm_unit_f32_fwd(int cfg, const GemmArgs* g, const PersistLaunch* pl
 hipError_t gemm_unit_f32_gbar(int cfg, const GemmArgs* g, const PersistLaunch* pl, int w32, int o32,
                          hipStream_t s) {
   const bool alt = w32 != 0;
-  if (pl) return alt ? run_persist<float, float, float, float, false, true>(cfg, *pl, s) : run_persist<float, double, float, float, false, true>(cfg, *pl, s);
-  return alt ? run<float, float, float, float, false, true>(cfg, *g, s) : run<float, double, float, float, false, true>(cfg, *g, s);
+  if (pl) return alt ? run_persist<float, float, float, float, true, false>(cfg, *pl, s) : run_persist<float, float, double, float, true, false>(cfg, *pl, s);
+  return alt ? run<float, float, float, float, true, false>(cfg, *g, s) : run<float, float, double, float, true, false>(cfg, *g, s);
 }
 #endif
 #if QMK_GEMM_UNIT == 6

@@ -14,6 +14,11 @@ constexpr int kMaxL = 3;            // highest angular momentum supported (f)
 constexpr int kGroupMaxPrim = 2048; // primitives staged in LDS per nucleus group
 constexpr int kGroupMaxShell = 512;
 constexpr int kGroupMaxNuc = 128;
+// AOs per nucleus group.  The AO kernels launch one workgroup per (256
+// points, group), so the cap also sets how finely the AO axis is split over
+// workgroups: at 120 an 800-AO system runs 7 workgroups per point block
+// instead of 1, which removes the tail of a grid of only ~2 workgroups per CU.
+constexpr int kGroupMaxAo = 120;
 constexpr int kPointPad = 256;      // points are padded to a multiple of this
 constexpr int kAoPad = 128;         // AOs (K) padded to a multiple of this
 constexpr int kMoPad = 128;         // MOs (N) padded to a multiple of this
@@ -36,7 +41,7 @@ struct ShellDev {
 
 // Contiguous range of nuclei whose shells and primitives fit in LDS.
 struct NucGroup {
-  int32_t nuc_begin, nuc_end, sh_begin, sh_end, p_begin, p_end, pad0, pad1;
+  int32_t nuc_begin, nuc_end, sh_begin, sh_end, p_begin, p_end, n_ao, pad1;
 };
 
 // Primitive table entry: exponent gamma and folded coefficient a*f*N_s.
@@ -94,6 +99,8 @@ struct GemmArgs {
   // run back to back on one XCD (A tile reused from that XCD's L2).  1: all
   // tiles of one batch index z run together on one XCD (split products,
   // whose z slab of both operands is shared by every tile of that z).
+  // 2: the M tiles of one N tile run back to back on one XCD (B tile reused;
+  // for products with few M tiles and a long N axis).
   int32_t map_slab;
 };
 
@@ -102,7 +109,7 @@ struct GemmArgs {
 __device__ __forceinline__ bool grid_tile(const GemmArgs& g, int nM, int nN, int bid, int& mt,
                                           int& nt, int& z) {
   const int x = bid & 7, j = bid >> 3;
-  if (g.map_slab) {
+  if (g.map_slab == 1) {
     const int tiles = nM * nN, nz = g.nbatch * g.nsplit;
     z = (j / tiles) * 8 + x;
     const int t = j % tiles;
@@ -111,6 +118,11 @@ __device__ __forceinline__ bool grid_tile(const GemmArgs& g, int nM, int nN, int
     return z < nz;
   }
   z = blockIdx.y;
+  if (g.map_slab == 2) {
+    nt = (j / nM) * 8 + x;
+    mt = j % nM;
+    return nt < nN;
+  }
   if (nM >= 8) {
     mt = (j / nN) * 8 + x;
     nt = j % nN;
@@ -124,7 +136,8 @@ __device__ __forceinline__ bool grid_tile(const GemmArgs& g, int nM, int nN, int
 // Grid of a launch for GemmArgs g and tile counts nM x nN.
 inline dim3 grid_of(const GemmArgs& g, int nM, int nN) {
   const int nz = g.nbatch * g.nsplit;
-  if (g.map_slab) return dim3(8 * nM * nN * ((nz + 7) / 8), 1);
+  if (g.map_slab == 1) return dim3(8 * nM * nN * ((nz + 7) / 8), 1);
+  if (g.map_slab == 2) return dim3(8 * nM * ((nN + 7) / 8), nz);
   const int gx = nM >= 8 ? 8 * nN * ((nM + 7) / 8) : nM * nN;
   return dim3(gx, nz);
 }
