@@ -846,13 +846,20 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     }
   }
   if (d_coef) {
-    // dC[n][k] = sum_{c, p} W[p][c][n] ao[k][c][p], split over (c, point chunk);
-    // the number of point chunks follows from the tile so that the grid holds
-    // about 2048 workgroups.
+    // dC[n][k] = sum_{c, p} W[p][c][n] ao[k][c][p], split over (c, point chunk).
+    // Every workgroup of this grid does the same work, so the number of point
+    // chunks is chosen for a whole number of rounds of resident workgroups:
+    // the largest count that fills at most four rounds (a fifth, nearly
+    // empty round would cost up to a fifth of the launch).
+    int ncu = 0;
+    QMK_HIP(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device),
+            "query CU count");
     auto split_of = [&](int cfg, int64_t* chunk_out) {
       const TileCfg t = gemm_tile(prec, cfg);
       const int64_t tiles = ((N + t.bm() - 1) / t.bm()) * ((K + t.bn() - 1) / t.bn());
-      int64_t ns = std::max<int64_t>(1, (2048 + tiles * 5 - 1) / (tiles * 5));
+      const int64_t resident = static_cast<int64_t>(std::max(1, ncu)) *
+                               gemm_persist_blocks_per_cu(GemmKind::kDcoef, prec, cfg, w32, 0);
+      int64_t ns = std::max<int64_t>(1, 4 * resident / (tiles * 5));
       ns = std::min<int64_t>(ns, std::max<int64_t>(1, (P + 255) / 256));
       int64_t chunk = round_up((P + ns - 1) / ns, 32);
       *chunk_out = chunk;
