@@ -50,10 +50,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="medium", choices=["medium", "batch96"],
-                    help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes")
+    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density"],
+                    help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes; "
+                         "density: electron density of a 1114-AO molecule on a 100^3 grid")
     ap.add_argument("--cpu-walkers", type=int, default=96,
                     help="walkers in the oracle's timed sample")
+    ap.add_argument("--cpu-points", type=int, default=1000000,
+                    help="grid points in the oracle's timed sample (density workload)")
     return ap.parse_args()
 
 
@@ -300,6 +303,86 @@ def main_batch(a):
     print(json.dumps(line))
 
 
+def run_density(s, occ, mode, steps, warmup, bits):
+    """get_density on fresh grid coordinates every step (so the AO stage runs)."""
+    import torch
+    import paper_2512_16677_amd as qmk
+    dev = torch.device("cuda:0")
+    ctx = qmk.Context.from_system(s, bits=bits, mode=mode)
+    r0 = torch.from_numpy(np.ascontiguousarray(s.elec_coord)).to(dev)
+    r1 = (r0 + 1e-3).contiguous()
+    rho = torch.empty((s.walk_num, s.elec_num), dtype=torch.float64, device=dev)
+
+    def step(i):
+        ctx.set_point(r0 if i % 2 == 0 else r1)
+        ctx.get_density(occ, out=rho)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    timing = ctx.timing()
+    ctx.close()
+    return ms, timing
+
+
+def main_density(a):
+    import synth
+    s = synth.peptide_like()
+    occ = s.meta["occ"]
+    P, K, No = s.point_num, s.ao_num, int(np.count_nonzero(occ))
+    flop = 2.0 * P * K * No
+    res = {}
+    for mode in ["fp64"] + [v for v in a.variants.split(",") if v == "mixed_f32"]:
+        bits = 53 if mode == "fp64" else a.mixed_bits
+        ms, t = run_density(s, occ, mode, a.steps, a.warmup, bits)
+        esz = 8 if mode == "fp64" else 4
+        per = {}
+        for name in ("ao", "density", "reduce"):
+            if t[name]["launches"]:
+                per[name] = {"avg_ms": t[name]["ms"] / t[name]["launches"], "launches": t[name]["launches"]}
+        per["ao"]["GBps"] = (K * P * esz + 24.0 * P) / (per["ao"]["avg_ms"] * 1e-3) / 1e9
+        per["density"]["TFLOPs"] = flop / (per["density"]["avg_ms"] * 1e-3) / 1e12
+        res[mode] = {"value": P / (ms * 1e-3), "ms_per_step": ms, "per_kernel": per}
+    d = res["fp64"]["per_kernel"]
+    dom = "density" if d["density"]["avg_ms"] >= d["ao"]["avg_ms"] else "ao"
+    roof = ({"bound": "mfma", "achieved": d["density"]["TFLOPs"], "peak": PEAKS["fp64_TFLOPs"],
+             "unit": "TFLOP/s", "frac": d["density"]["TFLOPs"] / PEAKS["fp64_TFLOPs"]} if dom == "density" else
+            {"bound": "hbm", "achieved": d["ao"]["GBps"], "peak": PEAKS["hbm_GBps"], "unit": "GB/s",
+             "frac": d["ao"]["GBps"] / PEAKS["hbm_GBps"]})
+    roof.update({"kernel": dom, "traffic": None})
+    line = {"metric": "density grid points/s (value-only AOs, MO product with fused sum of squares)",
+            "value": res["fp64"]["value"], "unit": "points/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": res["fp64"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"peptide_like: 104 atoms (C34 N11 O10 H48 Cu), {K} AOs, "
+                                   f"{No} doubly occupied of {s.mo_num} MOs, 100^3 grid",
+                       "points_per_step": P},
+            "roofline": roof, "modes": res,
+            "paper_context": "Section 4: density of a 1114-AO, 218-occupied-MO molecule on a 100^3 "
+                             "grid in 5.0 s (FP64) / 3.7 s (FP32) on 18 cores of an i7-13850HX, "
+                             "including file input and cube output"}
+    if not a.no_cpu_baseline:
+        import oracle
+        n = a.cpu_points
+        pts = s.points()[:: max(1, P // n)][:n]
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.density(s, occ, points=pts)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": len(pts) / dt, "unit": "points/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": (f"the whole {len(pts)}-point grid" if len(pts) == P else
+                                           f"{len(pts)} evenly strided grid points of the same system")
+                                          + f", FP64, {dt:.1f} s"}
+    print(json.dumps(line))
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: under a hardware-counter
     profile its FETCH_SIZE / WRITE_SIZE give the factor that turns those
@@ -318,6 +401,12 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "density":
+        if a.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        main_density(a)
         return
     if a.workload == "batch96":
         if a.gpus != 1:

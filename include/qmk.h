@@ -149,6 +149,32 @@ qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
 qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                           void* hip_stream);
 
+/* MO values only (the value rows of Section 3.2's product; the orbital
+ * evaluation on grids of Section 4): mo_value[walk][elec][mo] =
+ * sum_k C[mo][k] chi_k(r), into a device buffer of size_max >=
+ * walk*elec*mo elements of type dtype (QMK_F64 or QMK_F32).  If the full AO
+ * array is current for these points its value plane is read; otherwise a
+ * value-only AO kernel runs (no derivatives).  Precision follows the mode:
+ * FP64, or FP32 MFMA in both mixed modes (the value product has no BF16x3
+ * form). */
+qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                            void* hip_stream);
+
+/* Electron density of a determinant at every point (Section 4, density of a
+ * Kohn-Sham determinant as a sum of squared MOs):
+ *   rho[walk][elec] = sum_n occ[n] * phi_n(r)^2
+ * occ: host array of mo_num finite occupation numbers (for a closed-shell
+ * determinant, 2 for each occupied MO and 0 otherwise); MOs with occ = 0 are
+ * left out of the product.  rho: device FP64 buffer of size_max >=
+ * walk*elec entries, overwritten.  The squares and the occupation-weighted
+ * sum are taken in the epilogue of the MO product (MO values are never
+ * stored); per-tile partial sums are added in a fixed order, so the result
+ * is deterministic.  Precision as for qmk_get_mo_value; partial sums are
+ * FP64.  Errors: QMK_INVALID_ARG_BASE + k (NULL, occ_num != mo_num), QMK_NONFINITE
+ * (an occupation is not finite), QMK_SIZE. */
+qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, double* rho,
+                           int64_t size_max, void* hip_stream);
+
 /* Adjoint of L = sum(W * mo_vgl) for the current points (Section 3.6 and
  * Section 3.5 motivate these derivatives; the nuclei carry their shells
  * rigidly, basis parameters are fixed):
@@ -178,13 +204,14 @@ enum {
   QMK_KERNEL_AO_ADJOINT = 3, /* adjoint: AO derivatives contracted     */
   QMK_KERNEL_DCOEF = 4,      /* adjoint: W^T ao split-K product        */
   QMK_KERNEL_REDUCE = 5,     /* deterministic reductions               */
-  QMK_KERNEL_CLASSES = 6
+  QMK_KERNEL_DENSITY = 6,    /* MO values squared and summed (density) */
+  QMK_KERNEL_CLASSES = 7
 };
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
 
 /* Tile shapes of the MFMA products (QMK_KERNEL_MO, QMK_KERNEL_GBAR,
- * QMK_KERNEL_DCOEF).  By default the library's autotuner times every tile
+ * QMK_KERNEL_DCOEF, QMK_KERNEL_DENSITY).  By default the library's autotuner times every tile
  * shape on the first call of each distinct product size and keeps the
  * fastest (process-wide; QMK_TUNE_CACHE=<file> persists the choices,
  * QMK_TUNE=0 picks by least padded work without timing).  qmk_set_tile

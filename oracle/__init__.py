@@ -9,7 +9,8 @@ and marshals numpy arrays through ctypes.
 Layouts (C order): AO and MO results are ``[point][component][function]`` with
 components (value, d/dx, d/dy, d/dz, Laplacian); with ``nq=14`` the AO result
 also carries the Hessian (xx xy xz yy yz zz) and the gradient of the
-Laplacian (components 5..13).
+Laplacian (components 5..13).  MO values alone and the electron density of a
+determinant (Section 4, orbital visualisation) are taken from the value rows.
 """
 from __future__ import annotations
 
@@ -184,3 +185,34 @@ def adjoint(sys_, w: np.ndarray, points: Optional[np.ndarray] = None, B: float =
     if rc:
         raise RuntimeError(f"oracle_adjoint failed ({rc})")
     return out
+
+
+def mo_value(sys_, points: Optional[np.ndarray] = None, B: float = 53.0,
+             coef: Optional[np.ndarray] = None) -> np.ndarray:
+    """MO values [P, mo] (the value rows of mo_vgl)."""
+    return mo_vgl(sys_, points, B, coef)[:, 0, :]
+
+
+def density(sys_, occ: np.ndarray, points: Optional[np.ndarray] = None, B: float = 53.0,
+            coef: Optional[np.ndarray] = None, with_abs: bool = False):
+    """Electron density of a determinant, rho(r) = sum_n occ[n] phi_n(r)^2
+    (Section 4: density as a sum of squared MOs), at `points` (default: all
+    walkers).  With with_abs, also returns sum_n |occ[n]| (sum_k |C_nk chi_k|)^2,
+    an upper scale of the rounding error of any evaluation of rho."""
+    C = np.asarray(sys_.mo_coef if coef is None else coef, dtype=np.float64)
+    occ = np.asarray(occ, dtype=np.float64).reshape(-1)
+    assert occ.shape[0] == C.shape[0]
+    keep = occ != 0.0
+    pts = np.asarray(sys_.points() if points is None else points, dtype=np.float64).reshape(-1, 3)
+    rho = np.zeros(pts.shape[0])
+    rho_abs = np.zeros(pts.shape[0])
+    if keep.any():
+        for a in range(0, pts.shape[0], 16384):  # bounded memory: points in chunks
+            b = min(a + 16384, pts.shape[0])
+            ao = ao_vgl(sys_, pts[a:b], B)[:, 0, :]       # [chunk, ao]
+            phi = ao @ C[keep].T                          # [chunk, n_occ]
+            rho[a:b] = (phi * phi) @ occ[keep]
+            if with_abs:
+                phi_abs = np.abs(ao) @ np.abs(C[keep]).T
+                rho_abs[a:b] = (phi_abs * phi_abs) @ np.abs(occ[keep])
+    return (rho, rho_abs) if with_abs else rho

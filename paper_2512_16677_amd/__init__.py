@@ -46,12 +46,13 @@ EXPORTED = [
     "qmk_status_string", "qmk_last_error", "qmk_ctx_create", "qmk_ctx_destroy",
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
+    "qmk_get_mo_value", "qmk_get_density",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
     "qmk_get_tile_count", "qmk_set_tile",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
-KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce"]
+KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density"]
 
 _lib = None
 
@@ -87,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_dims": ([P, P, P, P, P, P], I32),
         "qmk_get_ao_vgl": ([P, P, I64, I32, P], I32),
         "qmk_get_mo_vgl": ([P, P, I64, I32, P], I32),
+        "qmk_get_mo_value": ([P, P, I64, I32, P], I32),
+        "qmk_get_density": ([P, P, I64, P, I64, P], I32),
         "qmk_mo_vgl_adjoint": ([P, P, I32, P, P, P, P], I32),
         "qmk_get_launch_count": ([P, P], I32),
         "qmk_set_timing": ([P, I32], I32),
@@ -241,7 +244,7 @@ class Context:
         return v.value
 
     def set_tile(self, kernel: str, tile: int):
-        """Force MFMA tile `tile` for kernel class 'mo', 'gbar' or 'dcoef' (-1: autotune)."""
+        """Force MFMA tile `tile` for kernel class 'mo', 'gbar', 'dcoef' or 'density' (-1: autotune)."""
         self._check(self._lib.qmk_set_tile(self._h, KERNEL_CLASSES.index(kernel), int(tile)))
 
     def _out(self, out, shape, dtype):
@@ -264,6 +267,29 @@ class Context:
         d = self.dims()
         out, dt = self._out(out, (d["walk_num"], d["elec_num"], 5, d["mo_num"]), dtype or torch.float64)
         self._check(self._lib.qmk_get_mo_vgl(self._h, _ptr(out), out.numel(), dt, _stream(stream)))
+        return out
+
+    def get_mo_value(self, out=None, dtype=None, stream=None):
+        """MO values only: CUDA tensor [walk, elec, mo]."""
+        import torch
+        d = self.dims()
+        out, dt = self._out(out, (d["walk_num"], d["elec_num"], d["mo_num"]), dtype or torch.float64)
+        self._check(self._lib.qmk_get_mo_value(self._h, _ptr(out), out.numel(), dt, _stream(stream)))
+        return out
+
+    def get_density(self, occ, out=None, stream=None):
+        """rho = sum_n occ[n] phi_n^2 at every point: CUDA float64 tensor
+        [walk, elec].  occ: mo_num occupation numbers (host)."""
+        import torch
+        d = self.dims()
+        o = _np(occ, np.float64).reshape(-1)
+        if out is None:
+            out = torch.empty((d["walk_num"], d["elec_num"]), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        if not (out.is_cuda and out.is_contiguous() and out.dtype == torch.float64):
+            raise ValueError("out must be a contiguous CUDA float64 tensor")
+        self._check(self._lib.qmk_get_density(self._h, _ptr(o), o.shape[0], _ptr(out), out.numel(),
+                                              _stream(stream)))
         return out
 
     def adjoint(self, w, d_coef=True, d_elec=True, d_nucl=True, out=None, stream=None):

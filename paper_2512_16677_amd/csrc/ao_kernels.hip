@@ -13,6 +13,10 @@
 // primitive).  Radial sums g0 = R, g1 = dR/du, g2 = d2R/du2 live in
 // registers; powers of the displacement are built by repeated
 // multiplication (Section 3.1, angular part) and never stored.
+//
+// The value-only form (VAL = true) serves the MO values and the density on a
+// grid (Section 4, orbital visualisation): it accumulates only g0 and stores
+// one [ao][point] plane.
 #include "qmk_internal.h"
 
 namespace qmk {
@@ -60,7 +64,28 @@ __device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz
   }
 }
 
+// Values only: chi = M P g0.
 template <typename OutT>
+__device__ __forceinline__ void shell_value(int l, double dx, double dy, double dz, double g0,
+                                            const double* __restrict__ M, OutT* __restrict__ o,
+                                            int64_t sK) {
+  const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
+  const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
+  int idx = 0;
+#pragma unroll 1
+  for (int a = l; a >= 0; --a) {
+#pragma unroll 1
+    for (int b = l - a; b >= 0; --b, ++idx) {
+      const int c = l - a - b;
+      const double px = a == 0 ? 1.0 : (a == 1 ? dx : (a == 2 ? dx2 : dx3));
+      const double py = b == 0 ? 1.0 : (b == 1 ? dy : (b == 2 ? dy2 : dy3));
+      const double pz = c == 0 ? 1.0 : (c == 1 ? dz : (c == 2 ? dz2 : dz3));
+      st(o + idx * sK, M[idx] * (px * py * pz) * g0);
+    }
+  }
+}
+
+template <typename OutT, bool VAL>
 __device__ __forceinline__ void shell_zero(int l, OutT* __restrict__ o, int64_t sK, int64_t sC,
                                            bool store) {
   if (!store) return;
@@ -68,11 +93,11 @@ __device__ __forceinline__ void shell_zero(int l, OutT* __restrict__ o, int64_t 
   for (int i = 0; i < n; ++i) {
     OutT* q = o + i * sK;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) q[c * sC] = OutT(0);
+    for (int c = 0; c < (VAL ? 1 : 5); ++c) q[c * sC] = OutT(0);
   }
 }
 
-template <typename OutT>
+template <typename OutT, bool VAL>
 __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& pts,
                                             const AoOut& out, int bx, int gy,
                                             unsigned char* smem) {
@@ -105,7 +130,7 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
     if (!__any(near)) {
       for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
         const ShellDev sh = s_shell[s];
-        shell_zero(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, valid);
+        shell_zero<OutT, VAL>(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, valid);
       }
       continue;
     }
@@ -124,17 +149,22 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
           g2 += pr.gamma * pr.gamma * e;
         }
       }
-      if (valid)
-        shell_vgl(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2,
-                  t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK, out.sC);
+      if (valid) {
+        if (VAL)
+          shell_value(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, g0,
+                      t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK);
+        else
+          shell_vgl(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2,
+                    t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK, out.sC);
+      }
     }
   }
 }
 
-template <typename OutT>
+template <typename OutT, bool VAL>
 __global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  ao_vgl_body<OutT>(t, pts, out, blockIdx.x, blockIdx.y, smem);
+  ao_vgl_body<OutT, VAL>(t, pts, out, blockIdx.x, blockIdx.y, smem);
 }
 
 // Persistent form: the grid walks a list of (molecule, point block, group).
@@ -146,7 +176,7 @@ __global__ __launch_bounds__(256) void ao_vgl_persist(const AoJob* __restrict__ 
   for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
     const WorkItem it = items[i];
     const AoJob& j = jobs[it.job];
-    ao_vgl_body<OutT>(j.t, j.pts, j.out, it.a, it.b, smem);
+    ao_vgl_body<OutT, false>(j.t, j.pts, j.out, it.a, it.b, smem);
     __syncthreads();  // LDS is restaged by the next item
   }
 }
@@ -177,9 +207,21 @@ hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& o
   const size_t smem = static_cast<size_t>(t.smem_bytes);
   dim3 grid(static_cast<unsigned>((pts.P + 255) / 256), static_cast<unsigned>(t.n_groups));
   if (out_is_f32)
-    hipLaunchKernelGGL(ao_vgl_kernel<float>, grid, dim3(256), smem, s, t, pts, out);
+    hipLaunchKernelGGL((ao_vgl_kernel<float, false>), grid, dim3(256), smem, s, t, pts, out);
   else
-    hipLaunchKernelGGL(ao_vgl_kernel<double>, grid, dim3(256), smem, s, t, pts, out);
+    hipLaunchKernelGGL((ao_vgl_kernel<double, false>), grid, dim3(256), smem, s, t, pts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ao_value(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
+                           hipStream_t s) {
+  if (pts.P <= 0 || t.n_groups <= 0) return hipSuccess;
+  const size_t smem = static_cast<size_t>(t.smem_bytes);
+  dim3 grid(static_cast<unsigned>((pts.P + 255) / 256), static_cast<unsigned>(t.n_groups));
+  if (out_is_f32)
+    hipLaunchKernelGGL((ao_vgl_kernel<float, true>), grid, dim3(256), smem, s, t, pts, out);
+  else
+    hipLaunchKernelGGL((ao_vgl_kernel<double, true>), grid, dim3(256), smem, s, t, pts, out);
   return hipGetLastError();
 }
 

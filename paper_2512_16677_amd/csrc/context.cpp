@@ -265,9 +265,8 @@ qmk_status ensure_coef(qmk_ctx ctx) {
       QMK_HIP(ctx, bufs[i]->ensure(bytes), "alloc split C");
       QMK_HIP(ctx, hipMemcpy(bufs[i]->p, src[i]->data(), bytes, hipMemcpyHostToDevice), "upload split C");
     }
-    ctx->coef_dirty = false;
-    ctx->coef_mode = want;
-    return QMK_OK;
+    // the FP32 copies below serve the value-only products, which have no
+    // BF16x3 form
   }
   const int64_t K = ctx->ao_num, N = ctx->mo_num;
   ctx->Kp = round_up(K, kAoPad);
@@ -349,6 +348,44 @@ qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
 }
 
 // Tile for one product: forced by qmk_set_tile, else the autotuner's choice.
+// AO values for the current points: the value plane of the full AO array
+// when that is current, else the value-only kernel into its own plane.
+// Returns the plane and its AO-row stride.
+qmk_status provide_ao_value(qmk_ctx ctx, hipStream_t s, const void** plane, int64_t* row_stride) {
+  qmk_status st = ensure_tables(ctx);
+  if (st != QMK_OK) return st;
+  const int f32 = ctx->f32_storage() ? 1 : 0;
+  const int64_t Pp = round_up(ctx->P(), kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
+  if (ctx->ao_date == ctx->date && ctx->ao_f32 == f32 && ctx->ao_Pp == Pp && ctx->ao_Kp == Kp) {
+    *plane = ctx->ao.p;
+    *row_stride = 5 * Pp;
+    return QMK_OK;
+  }
+  *plane = nullptr;
+  *row_stride = Pp;
+  if (ctx->aov_date == ctx->date && ctx->aov_f32 == f32 && ctx->aov_Pp == Pp && ctx->aov_Kp == Kp) {
+    *plane = ctx->aov.p;
+    return QMK_OK;
+  }
+  if (ctx->aov_Pp != Pp || ctx->aov_Kp != Kp || ctx->aov_f32 != f32 || !ctx->aov.p) {
+    const size_t bytes = static_cast<size_t>(Kp * Pp) * (f32 ? 4 : 8);
+    ctx->aov.release();
+    QMK_HIP(ctx, ctx->aov.ensure(bytes), "alloc AO value plane");
+    QMK_HIP(ctx, hipMemsetAsync(ctx->aov.p, 0, bytes, s), "clear AO value plane");
+    ctx->aov_Pp = Pp;
+    ctx->aov_Kp = Kp;
+    ctx->aov_f32 = f32;
+  }
+  AoOut o{ctx->aov.p, Pp, 0, 1};
+  {
+    LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
+    QMK_HIP(ctx, launch_ao_value(ctx->tab, point_args(ctx), o, f32, s), "AO value kernel");
+  }
+  ctx->aov_date = ctx->date;
+  *plane = ctx->aov.p;
+  return QMK_OK;
+}
+
 qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
                      const std::function<hipError_t(int)>& enqueue, int* cfg) {
   const int forced = ctx->forced_tile[static_cast<int>(pb.kind)];
@@ -606,6 +643,7 @@ qmk_status qmk_set_mo_coef(qmk_ctx ctx, int64_t mo_num, int64_t ao_num, const do
   ctx->mo_num = mo_num;
   ctx->has_coef = true;
   ctx->coef_dirty = true;
+  ++ctx->coef_version;
   return QMK_OK;
 }
 
@@ -662,6 +700,7 @@ qmk_status qmk_set_tile(qmk_ctx ctx, int32_t kernel_class, int32_t tile) {
   if (kernel_class == QMK_KERNEL_MO) kind = static_cast<int>(GemmKind::kForward);
   if (kernel_class == QMK_KERNEL_GBAR) kind = static_cast<int>(GemmKind::kGbar);
   if (kernel_class == QMK_KERNEL_DCOEF) kind = static_cast<int>(GemmKind::kDcoef);
+  if (kernel_class == QMK_KERNEL_DENSITY) kind = static_cast<int>(GemmKind::kDensity);
   if (kind < 0) return bad_arg(ctx, 2, "kernel class has no tile choice");
   if (tile < -1 || tile >= gemm_num_tiles(Prec::kF64)) return bad_arg(ctx, 3, "unknown tile");
   if (tile >= 0 && !tile_feasible(Prec::kF64, tile) && ctx->mode == QMK_FP64)
@@ -774,6 +813,156 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
     return st;
   LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
   QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, prec, cfg, ga, 0, o32, s), "MO contraction");
+  return QMK_OK;
+}
+
+qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                            void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (!out) return bad_arg(ctx, 2, "NULL");
+  if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
+  qmk_status st = check_ready(ctx, true);
+  if (st != QMK_OK) return st;
+  const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
+  if (size_max < P * N)
+    return fail(ctx, QMK_SIZE, "size_max " + std::to_string(size_max) + " < " + std::to_string(P * N));
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const Prec prec = ctx->mode == QMK_FP64 ? Prec::kF64 : Prec::kF32;
+  if ((st = ensure_coef(ctx)) != QMK_OK) return st;
+  const void* plane = nullptr;
+  int64_t row = 0;
+  if ((st = provide_ao_value(ctx, s, &plane, &row)) != QMK_OK) return st;
+  GemmArgs ga{};
+  ga.A = plane;
+  ga.sAi = 1;
+  ga.sAl = row;
+  ga.B = ctx->d_Ct.p;
+  ga.sBl = ctx->Np;
+  ga.sBj = 1;
+  ga.D = out;
+  ga.sDi = N;
+  ga.sDj = 1;
+  ga.M = P;
+  ga.N = N;
+  ga.L = ga.Lchunk = K;
+  ga.nsplit = 1;
+  ga.nbatch = 1;
+  const int o32 = dtype == QMK_F32;
+  GemmProblem pb{GemmKind::kForward, prec, 0, o32, P, N, K};
+  pb.nbatch = 1;
+  int cfg = 0;
+  if ((st = pick_tile(ctx, pb, s, [&](int c) {
+         return launch_gemm_typed(GemmKind::kForward, prec, c, ga, 0, o32, s);
+       }, &cfg)) != QMK_OK)
+    return st;
+  LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
+  QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, prec, cfg, ga, 0, o32, s), "MO value product");
+  return QMK_OK;
+}
+
+qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, double* rho,
+                           int64_t size_max, void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (!occ) return bad_arg(ctx, 2, "NULL");
+  if (!rho) return bad_arg(ctx, 4, "NULL");
+  qmk_status st = check_ready(ctx, true);
+  if (st != QMK_OK) return st;
+  const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
+  if (occ_num != N) return bad_arg(ctx, 3, "occ_num must equal mo_num");
+  for (int64_t n = 0; n < N; ++n)
+    if (!std::isfinite(occ[n])) return fail(ctx, QMK_NONFINITE, "non-finite occupation number");
+  if (size_max < P)
+    return fail(ctx, QMK_SIZE, "size_max " + std::to_string(size_max) + " < " + std::to_string(P));
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const Prec prec = ctx->mode == QMK_FP64 ? Prec::kF64 : Prec::kF32;
+  const int f32 = prec == Prec::kF32 ? 1 : 0;
+
+  // occupied MOs, compacted once per (occupations, coefficients, precision)
+  std::vector<double> key(occ, occ + N);
+  if (key != ctx->occ_key || ctx->occ_coef_version != ctx->coef_version || ctx->occ_f32 != f32) {
+    std::vector<int64_t> rows;
+    for (int64_t n = 0; n < N; ++n)
+      if (occ[n] != 0.0) rows.push_back(n);
+    const int64_t no = static_cast<int64_t>(rows.size());
+    const int64_t Kp = round_up(K, kAoPad), Nop = std::max<int64_t>(round_up(no, kMoPad), kMoPad);
+    std::vector<double> w(Nop, 0.0);
+    std::vector<double> ct64;
+    std::vector<float> ct32;
+    if (f32) ct32.assign(static_cast<size_t>(Kp * Nop), 0.0f);
+    else ct64.assign(static_cast<size_t>(Kp * Nop), 0.0);
+    for (int64_t j = 0; j < no; ++j) {
+      w[j] = occ[rows[j]];
+      for (int64_t k = 0; k < K; ++k) {
+        const double c = ctx->C[rows[j] * K + k];
+        if (f32) ct32[k * Nop + j] = static_cast<float>(c);
+        else ct64[k * Nop + j] = c;
+      }
+    }
+    const size_t cb = static_cast<size_t>(Kp * Nop) * (f32 ? 4 : 8);
+    QMK_HIP(ctx, ctx->d_Cocc_t.ensure(cb), "alloc occupied coefficients");
+    QMK_HIP(ctx, hipMemcpy(ctx->d_Cocc_t.p, f32 ? static_cast<const void*>(ct32.data())
+                                                 : static_cast<const void*>(ct64.data()),
+                           cb, hipMemcpyHostToDevice),
+            "upload occupied coefficients");
+    QMK_HIP(ctx, ctx->d_occ.ensure(static_cast<size_t>(Nop) * 8), "alloc occupations");
+    QMK_HIP(ctx, hipMemcpy(ctx->d_occ.p, w.data(), static_cast<size_t>(Nop) * 8, hipMemcpyHostToDevice),
+            "upload occupations");
+    ctx->occ_key = key;
+    ctx->occ_coef_version = ctx->coef_version;
+    ctx->occ_f32 = f32;
+    ctx->n_occ = no;
+    ctx->Nop = Nop;
+  }
+  if (ctx->n_occ == 0) {
+    QMK_HIP(ctx, hipMemsetAsync(rho, 0, static_cast<size_t>(P) * 8, s), "clear density");
+    return QMK_OK;
+  }
+  const void* plane = nullptr;
+  int64_t row = 0;
+  if ((st = provide_ao_value(ctx, s, &plane, &row)) != QMK_OK) return st;
+  const int64_t Pp = round_up(P, kPointPad);
+  // one partial row per (N tile, wave) of the widest tile on offer
+  int64_t slots_max = 0;
+  for (int c = 0; c < gemm_num_tiles(prec); ++c) {
+    const TileCfg t = gemm_tile(prec, c);
+    slots_max = std::max<int64_t>(slots_max, (ctx->n_occ + t.bn() - 1) / t.bn() * t.wgn);
+  }
+  QMK_HIP(ctx, ctx->ws_den.ensure(static_cast<size_t>(slots_max * Pp) * 8), "alloc density partials");
+  GemmArgs ga{};
+  ga.A = plane;
+  ga.sAi = 1;
+  ga.sAl = row;
+  ga.B = ctx->d_Cocc_t.p;
+  ga.sBl = ctx->Nop;
+  ga.sBj = 1;
+  ga.D = ctx->ws_den.p;
+  ga.sDi = 1;
+  ga.sDj = Pp;
+  ga.M = P;
+  ga.N = ctx->n_occ;
+  ga.L = ga.Lchunk = K;
+  ga.nsplit = 1;
+  ga.nbatch = 1;
+  ga.occ = ctx->d_occ.as<double>();
+  auto enqueue = [&](int c) -> hipError_t {
+    hipError_t e;
+    {
+      LaunchTimer lt(ctx, QMK_KERNEL_DENSITY, s);
+      e = launch_gemm_density(prec, c, ga, s);
+    }
+    if (e != hipSuccess) return e;
+    const TileCfg t = gemm_tile(prec, c);
+    const int64_t slots = (ctx->n_occ + t.bn() - 1) / t.bn() * t.wgn;
+    LaunchTimer lt(ctx, QMK_KERNEL_REDUCE, s);
+    return launch_reduce_splits(ctx->ws_den.as<double>(), slots, 1, P, 0, Pp, rho, 0, s);
+  };
+  GemmProblem pb{GemmKind::kDensity, prec, 0, 0, P, ctx->n_occ, K};
+  pb.nbatch = 1;
+  int cfg = 0;
+  if ((st = pick_tile(ctx, pb, s, enqueue, &cfg)) != QMK_OK) return st;
+  QMK_HIP(ctx, enqueue(cfg), "density product");
   return QMK_OK;
 }
 

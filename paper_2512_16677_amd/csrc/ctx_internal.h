@@ -107,12 +107,25 @@ struct qmk_ctx_s {
   int64_t ao_Pp = 0, ao_Kp = 0, ao_date = -1;
   int ao_f32 = -1;
 
+  // AO values only [Kp][Pp], valid at aov_date (used when the full AO array
+  // is stale for the current points)
+  DevBuf aov;
+  int64_t aov_Pp = 0, aov_Kp = 0, aov_date = -1;
+  int aov_f32 = -1;
+
+  // density: occupied MOs compacted into Cocc^T [Kp][No_p] and occ [No_p]
+  DevBuf d_Cocc_t, d_occ, ws_den;
+  std::vector<double> occ_key;
+  int64_t occ_coef_version = -1, n_occ = 0, Nop = 0;
+  int occ_f32 = -1;
+  int64_t coef_version = 0;
+
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
   int64_t gbar_Pp = 0, gbar_Kp = 0;
   int gbar_f32 = -1;
 
   int64_t launches = 0;
-  int forced_tile[3] = {-1, -1, -1};  // per GemmKind; -1 = autotuned
+  int forced_tile[4] = {-1, -1, -1, -1};  // per GemmKind; -1 = autotuned
 
   // tracing: events around launches, per kernel class
   struct Pending {

@@ -51,9 +51,12 @@ struct GemmSmem {
   T B[2][BK][BN + PAD];
 };
 
-// One output tile (mt, nt) of batch index z.
+// One output tile (mt, nt) of batch index z.  EPI = 0 stores D; EPI = 1 is
+// the density epilogue: each wave reduces occ[j] * D(i, j)^2 over its own
+// columns and stores the partial sum of row i in slot nt * WGN + wn, at
+// D[i*sDi + slot*sDj] (FP64).
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
-          int BK, bool A_I, bool B_J>
+          int BK, bool A_I, bool B_J, int EPI = 0>
 __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int z,
                                           GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK>& sm) {
   constexpr int NT = 64 * WGM * WGN;
@@ -170,16 +173,52 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     __syncthreads();
   }
 
+  if constexpr (EPI == 1) {
+    // the 16 lanes sharing lane / 16 hold the 16 columns of one row: sum
+    // them with butterfly shuffles inside each 16-lane group
+    double* const part = reinterpret_cast<double*>(g.D) + z * g.oDz +
+                         static_cast<int64_t>(nt * WGN + wn) * g.sDj;
 #pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b)
+    for (int a = 0; a < TM; ++a) {
+      // one block row at a time keeps the accumulators in place
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+          const double x = static_cast<double>(acc[a][b][r]);
+          v += (gj < g.N ? g.occ[gj] : 0.0) * x * x;
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
-        const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
-        if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+        if ((lane & 15) == 0 && gi < g.M) part[gi * g.sDi] = v;
       }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+          const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+          if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+        }
+  }
+}
+
+// Density product: partial sums over columns of occ[j] (sum_l A(i,l) B(l,j))^2
+// (see gemm_body, EPI = 1).
+template <typename T, int WGM, int WGN, int TM, int TN, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_density_kernel(GemmArgs g, int nM, int nN) {
+  __shared__ GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK> sm;
+  int mt, nt, z;
+  if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
+  gemm_body<T, T, T, double, WGM, WGN, TM, TN, BK, true, true, 1>(g, mt, nt, z, sm);
 }
 
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
@@ -284,6 +323,29 @@ hipError_t run(int cfg, const GemmArgs& g, hipStream_t s) {
     return run_tile<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J>(g, s);
     QMK_TILE_LIST(QMK_TILE_CASE)
 #undef QMK_TILE_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int WGM, int WGN, int TM, int TN, int BK>
+hipError_t run_density_tile(const GemmArgs& g, hipStream_t s) {
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+  const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
+  if (nM <= 0 || nN <= 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_density_kernel<T, WGM, WGN, TM, TN, BK>), grid_of(g, nM, nN),
+                     dim3(64 * WGM * WGN), 0, s, g, nM, nN);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_density(int cfg, const GemmArgs& g, hipStream_t s) {
+  switch (cfg) {
+#define QMK_TILE_DCASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                       \
+    return run_density_tile<T, wgm, wgn, tm, tn, bk>(g, s);
+    QMK_TILE_LIST(QMK_TILE_DCASE)
+#undef QMK_TILE_DCASE
     default:
       return hipErrorInvalidValue;
   }

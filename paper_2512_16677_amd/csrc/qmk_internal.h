@@ -102,6 +102,8 @@ struct GemmArgs {
   // 2: the M tiles of one N tile run back to back on one XCD (B tile reused;
   // for products with few M tiles and a long N axis).
   int32_t map_slab;
+  // Density epilogue only: occupation of column j (device, N entries).
+  const double* occ;
 };
 
 // Tile of workgroup `bid` of a grid launch; false if it has none.  The
@@ -156,12 +158,15 @@ __device__ __forceinline__ AxisD axis_derivs(int e, double t, double t2, double 
   return r;
 }
 
-enum class GemmKind { kForward, kGbar, kDcoef };
+enum class GemmKind { kForward, kGbar, kDcoef, kDensity };
 enum class Prec { kF64, kF32, kBF16x3 };
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                          int fp32_compute, hipStream_t s);
+// Values only, one plane: element (k, p) at out.out[k*out.sK + p*out.sP].
+hipError_t launch_ao_value(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
+                           hipStream_t s);
 // GEMM tile shape: WGM x WGN wavefronts of TM x TN 16x16 MFMA blocks, K step BK.
 struct TileCfg {
   int wgm, wgn, tm, tn, bk;
@@ -171,6 +176,9 @@ struct TileCfg {
 int gemm_num_tiles(Prec prec);
 TileCfg gemm_tile(Prec prec, int cfg);
 size_t gemm_tile_lds_bytes(Prec prec, int cfg);
+// Density product (FP64 or FP32 tile cfg): partial row sums of
+// occ[j] D(i, j)^2 per (N tile, wave) slot; see gemm_body.
+hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s);
 // BF16x3 kernel (gemm_bf16.hip); reached through launch_gemm_typed.
@@ -186,6 +194,7 @@ struct GemmProblem {
   Prec prec;
   int w32, o32;
   int64_t M, N, L;
+  int nbatch = 5;  // components per product (1: values only)
 };
 bool tile_feasible(Prec prec, int cfg);
 int default_tile(const GemmProblem& p);

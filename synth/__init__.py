@@ -34,6 +34,7 @@ RECIPE_HEAVY_SMALL = (0, 0, 0, 1, 1, 2)                    # 3s2p1d -> 15 AOs
 RECIPE_H_SMALL = (0, 0, 1)                                 # 2s1p   ->  5 AOs
 RECIPE_HEAVY_LARGE = (0, 0, 0, 0, 1, 1, 1, 2, 2, 3)        # 4s3p2d1f -> 35 AOs
 RECIPE_H_LARGE = (0, 0, 0, 1, 1, 2)                        # 3s2p1d -> 15 AOs
+RECIPE_TM_DZ = (0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 3)  # 6s5p3d1f -> 49 AOs
 
 
 @dataclass
@@ -214,6 +215,40 @@ def large(walkers: int = 64, seed: int = 0) -> System:
                       light=RECIPE_H_LARGE, n_mo=1050, name="ch300_7500ao")
 
 
+def peptide_like(grid_n: int = 100, seed: int = 0, margin: float = 4.0) -> System:
+    """Stand-in for the density benchmark of Section 4 (a Cu(II)-peptide
+    complex, C34 H48 Cu N11 O10, in cc-pVDZ: 1114 AOs, 218 occupied MOs, on a
+    100^3 grid).  34 C, 11 N, 10 O (3s2p1d each), 48 H (2s1p) and one Cu
+    (6s5p3d1f), each element with its own drawn basis -> 1114 Cartesian AOs;
+    atoms uniform in a cube at the medium system's atom density (80 atoms per
+    20^3 bohr^3) with 1.5-bohr minimum separation; 1053 MOs with
+    C ~ N(0, 1/1114), of which the first 218 are doubly occupied
+    (meta["occ"]).  The points are a grid_n^3 Cartesian grid over the atoms'
+    cube plus `margin` bohr on every side (z fastest, as in a cube file),
+    held as one walker of grid_n^3 "electrons"."""
+    rg, rb, rc, re, _ = _streams(seed)
+    elems = ["C"] * 34 + ["N"] * 11 + ["O"] * 10 + ["H"] * 48 + ["Cu"]
+    charges = {"C": 6, "N": 7, "O": 8, "H": 1, "Cu": 29}
+    n_at = len(elems)
+    box = 20.0 * (n_at / 80.0) ** (1.0 / 3.0)
+    coords = _pack_atoms(rg, n_at, box, 1.5)
+    bases = {"C": _draw_element_basis(rb, RECIPE_HEAVY_SMALL),
+             "N": _draw_element_basis(rb, RECIPE_HEAVY_SMALL),
+             "O": _draw_element_basis(rb, RECIPE_HEAVY_SMALL),
+             "H": _draw_element_basis(rb, RECIPE_H_SMALL),
+             "Cu": _draw_element_basis(rb, RECIPE_TM_DZ)}
+    s = _assemble("peptide_like", coords, [charges[e] for e in elems], elems, bases, rc, re,
+                  1053, 1, seed, {"box": box})
+    ax = np.linspace(-margin, box + margin, grid_n)
+    gx, gy, gz = np.meshgrid(ax, ax, ax, indexing="ij")
+    grid = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+    s.elec_coord = np.ascontiguousarray(grid.reshape(1, -1, 3))
+    occ = np.zeros(s.mo_num)
+    occ[:218] = 2.0
+    s.meta = dict(s.meta, occ=occ, grid_n=grid_n, spacing=float(ax[1] - ax[0]))
+    return s
+
+
 def molecule_batch(n_mol: int = 96, seed: int = 0) -> List[System]:
     """`n_mol` molecules with atom count uniform in 4..60 (ceil(n/2) C,
     floor(n/2) H) and walkers uniform in 8..128; molecule m uses child seed m
@@ -260,4 +295,5 @@ CONFIGS = {
     "water_like": water_like,
     "medium": medium,
     "large": large,
+    "peptide_like": peptide_like,
 }
