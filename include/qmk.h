@@ -175,6 +175,26 @@ qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dt
 qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, double* rho,
                            int64_t size_max, void* hip_stream);
 
+/* MO cusp correction (Section 3.3).  Inside the sphere of radius r_cusp[A]
+ * around nucleus A every MO is replaced by
+ *   phi_i - phi_i^{s_A} + sum_{k=0..3} f_{k,i,A} |r - R_A|^k
+ * (phi_i^{s_A}: the part of MO i carried by the s-type AOs on A).  The four
+ * f_k per (MO, nucleus) make the value and the first and second radial
+ * derivatives continuous at r_cusp[A] and satisfy the electron-nucleus cusp
+ * condition (1/phi) dphi/dr = -charge[A] at the nucleus (spherical average);
+ * they are computed in FP64 when first needed after the nuclei, basis,
+ * precision, MO coefficients or these arrays change.
+ *   charge  host [nucl_num]: nuclear charges Z_A (finite, >= 0)
+ *   r_cusp  host [nucl_num]: radii (finite, >= 0; 0 = no correction at A),
+ *           or NULL to switch the correction off
+ * The spheres must not overlap (r_A + r_B < |R_A - R_B|).  While the
+ * correction is on, qmk_get_mo_vgl applies it; qmk_get_mo_value,
+ * qmk_get_density, qmk_mo_vgl_adjoint and batches return QMK_UNSUPPORTED.
+ * At a point exactly on a nucleus with a sphere the corrected gradient and
+ * Laplacian are not finite (the cusp). */
+qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
+                           const double* r_cusp);
+
 /* Adjoint of L = sum(W * mo_vgl) for the current points (Section 3.6 and
  * Section 3.5 motivate these derivatives; the nuclei carry their shells
  * rigidly, basis parameters are fixed):
@@ -205,7 +225,8 @@ enum {
   QMK_KERNEL_DCOEF = 4,      /* adjoint: W^T ao split-K product        */
   QMK_KERNEL_REDUCE = 5,     /* deterministic reductions               */
   QMK_KERNEL_DENSITY = 6,    /* MO values squared and summed (density) */
-  QMK_KERNEL_CLASSES = 7
+  QMK_KERNEL_CUSP = 7,       /* MO cusp correction                     */
+  QMK_KERNEL_CLASSES = 8
 };
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);

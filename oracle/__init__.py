@@ -216,3 +216,82 @@ def density(sys_, occ: np.ndarray, points: Optional[np.ndarray] = None, B: float
                 phi_abs = np.abs(ao) @ np.abs(C[keep]).T
                 rho_abs[a:b] = (phi_abs * phi_abs) @ np.abs(occ[keep])
     return (rho, rho_abs) if with_abs else rho
+
+
+def _s_ao_columns(sys_, nucleus: int) -> np.ndarray:
+    """AO indices of the s-type shells on `nucleus` (AOs numbered shell by
+    shell, (l+1)(l+2)/2 Cartesian functions each)."""
+    cols, k = [], 0
+    for sh, (A, l) in enumerate(zip(sys_.shell_nucleus, sys_.shell_ang_mom)):
+        if int(A) == nucleus and int(l) == 0:
+            cols.append(k)
+        k += (int(l) + 1) * (int(l) + 2) // 2
+    return np.asarray(cols, dtype=np.int64)
+
+
+def cusp_coefficients(sys_, charge, r_cusp, B: float = 53.0, coef: Optional[np.ndarray] = None):
+    """Coefficients f[A] of shape [mo, 4] of the cusp polynomial of every
+    nucleus with r_cusp[A] > 0 (Section 3.3), as a dict A -> f.
+
+    With r = |r - R_A|, R = r_cusp[A], Z = charge[A] and phi^s the part of MO i
+    carried by the s-type AOs on A, p(r) = sum_k f_k r^k satisfies
+      p(R) = phi^s(R),  p'(R) = phi^s'(R),  p''(R) = phi^s''(R)  (continuity
+      of the value and of the first two radial derivatives at R), and
+      p'(0) = -Z (phi(R_A) - phi^s(R_A) + p(0))  (the electron-nucleus cusp of
+      the corrected orbital).
+    The radial derivatives of phi^s at R are read off the oracle's gradient
+    and Laplacian at R_A + R e_x: phi^s' = d/dx, phi^s'' = lap - 2 phi^s' / R."""
+    C = np.asarray(sys_.mo_coef if coef is None else coef, dtype=np.float64)
+    out = {}
+    for A in range(sys_.nucl_num):
+        R = float(r_cusp[A])
+        if R <= 0.0:
+            continue
+        Z = float(charge[A])
+        cols = _s_ao_columns(sys_, A)
+        Cs = C[:, cols]
+        centre = sys_.nucl_coord[A]
+        at_nuc = ao_vgl(sys_, centre[None, :], B)[0]                  # [5, ao]
+        delta = C @ at_nuc[0] - Cs @ at_nuc[0, cols]                  # phi(R_A) - phi^s(R_A)
+        on_sphere = ao_vgl(sys_, (centre + np.array([R, 0.0, 0.0]))[None, :], B)[0]
+        v = Cs @ on_sphere[0, cols]
+        v1 = Cs @ on_sphere[1, cols]
+        v2 = Cs @ on_sphere[4, cols] - 2.0 * v1 / R
+        M = np.array([[1.0, R, R * R, R ** 3],
+                      [0.0, 1.0, 2.0 * R, 3.0 * R * R],
+                      [0.0, 0.0, 2.0, 6.0 * R],
+                      [Z, 1.0, 0.0, 0.0]])
+        rhs = np.stack([v, v1, v2, -Z * delta])                       # [4, mo]
+        out[A] = np.linalg.solve(M, rhs).T                            # [mo, 4]
+    return out
+
+
+def mo_vgl_cusp(sys_, charge, r_cusp, points: Optional[np.ndarray] = None, B: float = 53.0,
+                coef: Optional[np.ndarray] = None) -> np.ndarray:
+    """Cusp-corrected mo_vgl [P, 5, mo] (Section 3.3): inside the sphere of
+    radius r_cusp[A] around nucleus A, phi_i - phi_i^{s_A} + sum_k f_k r^k,
+    with value, gradient and Laplacian of the radial polynomial
+    (p, p'(r) d/r, p'' + 2 p'/r) and of phi^{s_A} from the oracle's AOs."""
+    C = np.asarray(sys_.mo_coef if coef is None else coef, dtype=np.float64)
+    pts = np.asarray(sys_.points() if points is None else points, dtype=np.float64).reshape(-1, 3)
+    ao = ao_vgl(sys_, pts, B)                                         # [P, 5, ao]
+    mo = np.einsum("pck,nk->pcn", ao, C)
+    for A, f in cusp_coefficients(sys_, charge, r_cusp, B, C).items():
+        d = pts - sys_.nucl_coord[A]
+        r = np.sqrt(np.sum(d * d, axis=1))
+        inside = np.nonzero(r < float(r_cusp[A]))[0]
+        if inside.size == 0:
+            continue
+        cols = _s_ao_columns(sys_, A)
+        phis = np.einsum("pck,nk->pcn", ao[inside][:, :, cols], C[:, cols])
+        ri = r[inside][:, None]
+        p0 = f[:, 0] + ri * (f[:, 1] + ri * (f[:, 2] + ri * f[:, 3]))
+        p1 = f[:, 1] + ri * (2.0 * f[:, 2] + 3.0 * ri * f[:, 3])
+        p2 = 2.0 * f[:, 2] + 6.0 * ri * f[:, 3]
+        poly = np.empty_like(phis)
+        poly[:, 0] = p0
+        with np.errstate(divide="ignore", invalid="ignore"):  # r = 0: the cusp diverges
+            poly[:, 1:4] = (p1 / ri)[:, None, :] * d[inside][:, :, None]
+            poly[:, 4] = p2 + 2.0 * p1 / ri
+        mo[inside] += poly - phis
+    return mo

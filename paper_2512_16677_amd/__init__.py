@@ -46,13 +46,13 @@ EXPORTED = [
     "qmk_status_string", "qmk_last_error", "qmk_ctx_create", "qmk_ctx_destroy",
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
-    "qmk_get_mo_value", "qmk_get_density",
+    "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
     "qmk_get_tile_count", "qmk_set_tile",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
-KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density"]
+KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp"]
 
 _lib = None
 
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_mo_vgl": ([P, P, I64, I32, P], I32),
         "qmk_get_mo_value": ([P, P, I64, I32, P], I32),
         "qmk_get_density": ([P, P, I64, P, I64, P], I32),
+        "qmk_set_mo_cusp": ([P, I64, P, P], I32),
         "qmk_mo_vgl_adjoint": ([P, P, I32, P, P, P, P], I32),
         "qmk_get_launch_count": ([P, P], I32),
         "qmk_set_timing": ([P, I32], I32),
@@ -268,6 +269,16 @@ class Context:
         out, dt = self._out(out, (d["walk_num"], d["elec_num"], 5, d["mo_num"]), dtype or torch.float64)
         self._check(self._lib.qmk_get_mo_vgl(self._h, _ptr(out), out.numel(), dt, _stream(stream)))
         return out
+
+    def set_mo_cusp(self, charge=None, r_cusp=None):
+        """Switch the MO cusp correction on (charges and radii per nucleus) or
+        off (r_cusp None)."""
+        if r_cusp is None:
+            self._check(self._lib.qmk_set_mo_cusp(self._h, 0, None, None))
+            return
+        z = _np(charge, np.float64).reshape(-1)
+        r = _np(r_cusp, np.float64).reshape(-1)
+        self._check(self._lib.qmk_set_mo_cusp(self._h, r.shape[0], _ptr(z), _ptr(r)))
 
     def get_mo_value(self, out=None, dtype=None, stream=None):
         """MO values only: CUDA tensor [walk, elec, mo]."""

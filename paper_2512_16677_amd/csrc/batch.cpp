@@ -442,6 +442,8 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
     if (c->mode != mode) return bfail(b, QMK_INVALID_ARG_BASE + 1, "contexts use different precision modes");
     qmk_status st = check_ready(c, true);
     if (st != QMK_OK) return bfail(b, st, "context " + std::to_string(i) + ": " + c->err);
+    if (c->cusp_on)
+      return bfail(b, QMK_UNSUPPORTED, "context " + std::to_string(i) + " has the cusp correction on");
     if ((st = ensure_tables(c)) != QMK_OK) return bfail(b, st, c->err);
     if ((st = ensure_coef(c)) != QMK_OK) return bfail(b, st, c->err);
     key.insert(key.end(), {c->P(), c->ao_num, c->mo_num, c->nucl_num, c->n_groups, c->nucl_dev,

@@ -386,6 +386,165 @@ qmk_status provide_ao_value(qmk_ctx ctx, hipStream_t s, const void** plane, int6
   return QMK_OK;
 }
 
+// Solves the 4x4 system a f = b (Gaussian elimination, partial pivoting);
+// false if it is singular.
+bool solve4(double a[4][4], double b[4], double f[4]) {
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+    if (a[piv][c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < 4; ++k) std::swap(a[c][k], a[piv][k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < 4; ++r) {
+      const double m = a[r][c] / a[c][c];
+      for (int k = c; k < 4; ++k) a[r][k] -= m * a[c][k];
+      b[r] -= m * b[c];
+    }
+  }
+  for (int c = 3; c >= 0; --c) {
+    double v = b[c];
+    for (int k = c + 1; k < 4; ++k) v -= a[c][k] * f[k];
+    f[c] = v / a[c][c];
+  }
+  return true;
+}
+
+// Cusp tables for the current nuclei, basis, precision and coefficients
+// (Section 3.3).  With r = |r - R_A|, R = r_A, Z = charge of A and
+// phi^s the radial s part of MO i on A, the coefficients solve
+//   p(R) = phi^s(R),  p'(R) = phi^s'(R),  p''(R) = phi^s''(R),
+//   p'(0) = -Z (phi(R_A) - phi^s(R_A) + p(0))
+// with p(r) = f0 + f1 r + f2 r^2 + f3 r^3.  phi(R_A) comes from the AO values
+// at the nuclei computed by the value-only AO kernel; phi^s and its radial
+// derivatives at R from the folded primitives, with the AO stage's cutoff.
+qmk_status ensure_cusp(qmk_ctx ctx, hipStream_t s) {
+  const int64_t key[4] = {ctx->geom_version, ctx->coef_version, ctx->cusp_version, ctx->mode};
+  if (std::equal(key, key + 4, ctx->cusp_key)) return QMK_OK;
+  qmk_status st = ensure_tables(ctx);
+  if (st != QMK_OK) return st;
+  const int64_t nn = ctx->nucl_num, K = ctx->ao_num, N = ctx->mo_num;
+  const double* R = ctx->nucl.data();
+  for (int64_t a = 0; a < nn; ++a)
+    for (int64_t b = a + 1; b < nn; ++b) {
+      if (ctx->cusp_rc[a] <= 0.0 || ctx->cusp_rc[b] <= 0.0) continue;
+      const double dx = R[3 * a] - R[3 * b], dy = R[3 * a + 1] - R[3 * b + 1], dz = R[3 * a + 2] - R[3 * b + 2];
+      if (ctx->cusp_rc[a] + ctx->cusp_rc[b] >= std::sqrt(dx * dx + dy * dy + dz * dz))
+        return fail(ctx, QMK_INVALID_ARG_BASE + 4,
+                    "cusp spheres of nuclei " + std::to_string(a) + " and " + std::to_string(b) + " overlap");
+    }
+  // AO offsets and s shells per nucleus
+  std::vector<int64_t> ao_off(ctx->shell_num + 1, 0);
+  for (int64_t sh = 0; sh < ctx->shell_num; ++sh) ao_off[sh + 1] = ao_off[sh] + n_cart(ctx->sh_l[sh]);
+  std::vector<std::vector<int64_t>> s_shells(nn);
+  for (int64_t sh = 0; sh < ctx->shell_num; ++sh)
+    if (ctx->sh_l[sh] == 0) s_shells[ctx->sh_nuc[sh]].push_back(sh);
+
+  // AO values at every nucleus (value-only kernel, FP64)
+  const int64_t Kp = round_up(K, kAoPad);
+  QMK_HIP(ctx, ctx->d_cusp_pts.ensure(static_cast<size_t>(3 * nn) * 8), "alloc cusp points");
+  QMK_HIP(ctx, hipMemcpyAsync(ctx->d_cusp_pts.p, R, static_cast<size_t>(3 * nn) * 8, hipMemcpyHostToDevice, s),
+          "upload cusp points");
+  QMK_HIP(ctx, ctx->d_cusp_ao.ensure(static_cast<size_t>(Kp * nn) * 8), "alloc cusp AO values");
+  PointArgs pa{};
+  pa.coord = ctx->d_cusp_pts.as<double>();
+  pa.s_pt = 3;
+  pa.s_ax = 1;
+  pa.P = nn;
+  AoOut o{ctx->d_cusp_ao.p, nn, 0, 1};
+  QMK_HIP(ctx, launch_ao_value(ctx->tab, pa, o, 0, s), "AO values at the nuclei");
+  std::vector<double> chi(static_cast<size_t>(K * nn));
+  QMK_HIP(ctx, hipMemcpyAsync(chi.data(), ctx->d_cusp_ao.p, chi.size() * 8, hipMemcpyDeviceToHost, s),
+          "download AO values at the nuclei");
+  QMK_HIP(ctx, hipStreamSynchronize(s), "wait for AO values at the nuclei");
+
+  std::vector<CuspNuc> cn;
+  std::vector<CuspS> cs;
+  std::vector<PrimDev> cp;
+  std::vector<double> ccs, cf;
+  const double T = (ctx->bits - 1) * std::log(2.0);
+  for (int64_t a = 0; a < nn; ++a) {
+    const double rc = ctx->cusp_rc[a];
+    if (rc <= 0.0) continue;
+    CuspNuc nu{R[3 * a], R[3 * a + 1], R[3 * a + 2], rc, static_cast<int32_t>(cs.size()), 0, 0, 0};
+    const double u = rc * rc;
+    std::vector<double> v(N, 0.0), v1(N, 0.0), v2(N, 0.0), phiA(N, 0.0), phisA(N, 0.0);
+    for (int64_t sh : s_shells[a]) {
+      const int64_t k = ao_off[sh];
+      CuspS sd{ctx->af[k], static_cast<int32_t>(cp.size()), 0};
+      std::vector<int64_t> order(ctx->sh_off[sh + 1] - ctx->sh_off[sh]);
+      std::iota(order.begin(), order.end(), ctx->sh_off[sh]);
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int64_t x, int64_t y) { return ctx->expo[x] < ctx->expo[y]; });
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+      for (int64_t q : order) {
+        const PrimDev pd{ctx->expo[q], ctx->coef[q] * ctx->pf[q] * ctx->sf[sh]};
+        cp.push_back(pd);
+        const double x = pd.gamma * u;
+        if (x >= T) continue;
+        const double e = pd.coef * std::exp(-x);
+        g0 += e;
+        g1 -= pd.gamma * e;
+        g2 += pd.gamma * pd.gamma * e;
+      }
+      sd.p_end = static_cast<int32_t>(cp.size());
+      cs.push_back(sd);
+      const double c0 = sd.m * g0, c1 = sd.m * 2.0 * rc * g1, c2 = sd.m * (2.0 * g1 + 4.0 * u * g2);
+      for (int64_t i = 0; i < N; ++i) {
+        const double cik = ctx->C[i * K + k];
+        ccs.push_back(cik);
+        v[i] += cik * c0;
+        v1[i] += cik * c1;
+        v2[i] += cik * c2;
+        phisA[i] += cik * chi[k * nn + a];
+      }
+    }
+    nu.s_end = static_cast<int32_t>(cs.size());
+    for (int64_t i = 0; i < N; ++i) {
+      double acc = 0.0;
+      for (int64_t k = 0; k < K; ++k) acc += ctx->C[i * K + k] * chi[k * nn + a];
+      phiA[i] = acc;
+    }
+    const double Z = ctx->cusp_charge[a];
+    const size_t base = cf.size();
+    cf.resize(base + 4 * N);
+    for (int64_t i = 0; i < N; ++i) {
+      double m[4][4] = {{1.0, rc, rc * rc, rc * rc * rc},
+                        {0.0, 1.0, 2.0 * rc, 3.0 * rc * rc},
+                        {0.0, 0.0, 2.0, 6.0 * rc},
+                        {Z, 1.0, 0.0, 0.0}};
+      double b[4] = {v[i], v1[i], v2[i], -Z * (phiA[i] - phisA[i])};
+      double f[4];
+      if (!solve4(m, b, f))
+        return fail(ctx, QMK_INVALID_ARG_BASE + 4, "cusp conditions are singular at nucleus " + std::to_string(a));
+      for (int q = 0; q < 4; ++q) cf[base + q * N + i] = f[q];
+    }
+    cn.push_back(nu);
+  }
+  auto up = [&](DevBuf& b, const void* src, size_t n) -> hipError_t {
+    hipError_t e = b.ensure(std::max<size_t>(n, 16));
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpy(b.p, src, n, hipMemcpyHostToDevice);
+  };
+  QMK_HIP(ctx, up(ctx->d_cusp_nuc, cn.data(), cn.size() * sizeof(CuspNuc)), "upload cusp nuclei");
+  QMK_HIP(ctx, up(ctx->d_cusp_s, cs.data(), cs.size() * sizeof(CuspS)), "upload cusp s AOs");
+  QMK_HIP(ctx, up(ctx->d_cusp_prim, cp.data(), cp.size() * sizeof(PrimDev)), "upload cusp primitives");
+  QMK_HIP(ctx, up(ctx->d_cusp_cs, ccs.data(), ccs.size() * 8), "upload cusp coefficients");
+  QMK_HIP(ctx, up(ctx->d_cusp_f, cf.data(), cf.size() * 8), "upload cusp polynomials");
+  CuspArgs& c = ctx->cusp;
+  c.nuc = ctx->d_cusp_nuc.as<CuspNuc>();
+  c.s = ctx->d_cusp_s.as<CuspS>();
+  c.prim = ctx->d_cusp_prim.as<PrimDev>();
+  c.cs = ctx->d_cusp_cs.as<double>();
+  c.f = ctx->d_cusp_f.as<double>();
+  c.T = T;
+  c.n_nuc = static_cast<int32_t>(cn.size());
+  std::copy(key, key + 4, ctx->cusp_key);
+  return QMK_OK;
+}
+
 qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
                      const std::function<hipError_t(int)>& enqueue, int* cfg) {
   const int forced = ctx->forced_tile[static_cast<int>(pb.kind)];
@@ -523,6 +682,7 @@ qmk_status qmk_set_precision(qmk_ctx ctx, int32_t bits, int32_t mode) {
   ctx->bits = bits;
   ctx->mode = mode;
   ++ctx->date;
+  ++ctx->geom_version;
   return QMK_OK;
 }
 
@@ -538,6 +698,7 @@ qmk_status qmk_set_nucleus(qmk_ctx ctx, int64_t nucl_num, const double* coord) {
   ctx->nucl_num = nucl_num;
   ctx->tables_dirty = true;
   ++ctx->date;
+  ++ctx->geom_version;
   return QMK_OK;
 }
 
@@ -628,6 +789,7 @@ qmk_status qmk_set_basis(qmk_ctx ctx, int64_t shell_num, int64_t prim_num,
   ctx->tables_dirty = true;
   ctx->coef_dirty = true;
   ++ctx->date;
+  ++ctx->geom_version;
   return QMK_OK;
 }
 
@@ -644,6 +806,27 @@ qmk_status qmk_set_mo_coef(qmk_ctx ctx, int64_t mo_num, int64_t ao_num, const do
   ctx->has_coef = true;
   ctx->coef_dirty = true;
   ++ctx->coef_version;
+  return QMK_OK;
+}
+
+qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
+                           const double* r_cusp) {
+  QMK_CHECK_CTX(ctx);
+  if (!r_cusp) {
+    ctx->cusp_on = false;
+    return QMK_OK;
+  }
+  if (ctx->nucl_num <= 0) return fail(ctx, QMK_NOT_SET, "set the nuclei before the cusp radii");
+  if (nucl_num != ctx->nucl_num) return bad_arg(ctx, 2, "nucl_num does not match the nuclei");
+  if (!charge) return bad_arg(ctx, 3, "NULL");
+  for (int64_t a = 0; a < nucl_num; ++a) {
+    if (!std::isfinite(charge[a]) || charge[a] < 0.0) return bad_arg(ctx, 3, "charges must be finite and >= 0");
+    if (!std::isfinite(r_cusp[a]) || r_cusp[a] < 0.0) return bad_arg(ctx, 4, "radii must be finite and >= 0");
+  }
+  ctx->cusp_charge.assign(charge, charge + nucl_num);
+  ctx->cusp_rc.assign(r_cusp, r_cusp + nucl_num);
+  ctx->cusp_on = true;
+  ++ctx->cusp_version;
   return QMK_OK;
 }
 
@@ -811,8 +994,15 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
          return launch_gemm_typed(GemmKind::kForward, prec, c, ga, 0, o32, s);
        }, &cfg)) != QMK_OK)
     return st;
-  LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
-  QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, prec, cfg, ga, 0, o32, s), "MO contraction");
+  {
+    LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
+    QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, prec, cfg, ga, 0, o32, s), "MO contraction");
+  }
+  if (ctx->cusp_on) {
+    if ((st = ensure_cusp(ctx, s)) != QMK_OK) return st;
+    LaunchTimer lt(ctx, QMK_KERNEL_CUSP, s);
+    QMK_HIP(ctx, launch_cusp(ctx->cusp, point_args(ctx), out, o32, N, s), "cusp correction");
+  }
   return QMK_OK;
 }
 
@@ -823,6 +1013,7 @@ qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dt
   if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
+  if (ctx->cusp_on) return fail(ctx, QMK_UNSUPPORTED, "MO values alone with the cusp correction on is not implemented");
   const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
   if (size_max < P * N)
     return fail(ctx, QMK_SIZE, "size_max " + std::to_string(size_max) + " < " + std::to_string(P * N));
@@ -868,6 +1059,7 @@ qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, doub
   if (!rho) return bad_arg(ctx, 4, "NULL");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
+  if (ctx->cusp_on) return fail(ctx, QMK_UNSUPPORTED, "the density with the cusp correction on is not implemented");
   const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
   if (occ_num != N) return bad_arg(ctx, 3, "occ_num must equal mo_num");
   for (int64_t n = 0; n < N; ++n)
@@ -973,6 +1165,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   if (w_dtype != QMK_F64 && w_dtype != QMK_F32) return bad_arg(ctx, 3, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
+  if (ctx->cusp_on) return fail(ctx, QMK_UNSUPPORTED, "the adjoint with the cusp correction on is not implemented");
   DeviceGuard g(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;

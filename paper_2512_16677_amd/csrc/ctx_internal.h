@@ -120,6 +120,14 @@ struct qmk_ctx_s {
   int occ_f32 = -1;
   int64_t coef_version = 0;
 
+  // MO cusp correction: inputs, and device tables valid for cusp_key
+  bool cusp_on = false;
+  std::vector<double> cusp_charge, cusp_rc;
+  int64_t cusp_version = 0, geom_version = 0;
+  int64_t cusp_key[4] = {-1, -1, -1, -1};  // geom, coef, cusp versions, mode
+  DevBuf d_cusp_nuc, d_cusp_s, d_cusp_prim, d_cusp_cs, d_cusp_f, d_cusp_pts, d_cusp_ao;
+  qmk::CuspArgs cusp{};
+
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
   int64_t gbar_Pp = 0, gbar_Kp = 0;
   int gbar_f32 = -1;

@@ -1,0 +1,101 @@
+// MO cusp correction (QMCkl paper, Section 3.3).
+//
+// Inside the sphere of radius r_A around nucleus A, MO i becomes
+//   phi_i - phi_i^{s_A} + sum_{k=0..3} f_{k,i,A} |r - R_A|^k,
+// where phi_i^{s_A} is the part of MO i carried by the s-type AOs on A.  Both
+// the removed part and the polynomial are radial functions h(r) of
+// r = |r - R_A|, so the correction adds to the five components of mo_vgl
+//   value h,  gradient h'(r) d / r,  Laplacian h''(r) + 2 h'(r) / r.
+//
+// One lane per point finds the sphere (if any; the spheres do not overlap)
+// that contains its point.  Such points are rare, so the wave then serves
+// them one at a time: every lane evaluates the same radial s functions of
+// that point and updates 64 MOs per pass of the point's mo_vgl row.
+#include "qmk_internal.h"
+
+namespace qmk {
+namespace {
+
+template <typename TD>
+__global__ __launch_bounds__(256) void cusp_kernel(CuspArgs c, PointArgs pts, TD* __restrict__ mo,
+                                                   int64_t N) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  double rx = 0.0, ry = 0.0, rz = 0.0;
+  int hit = -1;
+  if (p < pts.P) {
+    rx = pts.coord[p * pts.s_pt];
+    ry = pts.coord[p * pts.s_pt + pts.s_ax];
+    rz = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
+    for (int a = 0; a < c.n_nuc; ++a) {
+      const CuspNuc nu = c.nuc[a];
+      const double dx = rx - nu.x, dy = ry - nu.y, dz = rz - nu.z;
+      if (dx * dx + dy * dy + dz * dz < nu.rc * nu.rc) {
+        hit = a;
+        break;
+      }
+    }
+  }
+  uint64_t mask = __ballot(hit >= 0);
+  while (mask) {
+    const int src = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const int64_t q = __shfl(p, src, 64);
+    const int a = __shfl(hit, src, 64);
+    const CuspNuc nu = c.nuc[a];
+    const double dx = __shfl(rx, src, 64) - nu.x;
+    const double dy = __shfl(ry, src, 64) - nu.y;
+    const double dz = __shfl(rz, src, 64) - nu.z;
+    const double u = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(u);
+    const double ir = 1.0 / r;  // a point exactly on the nucleus: the cusp diverges
+    TD* row = mo + q * 5 * N;
+    for (int64_t i = lane; i < N; i += 64) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;  // phi^s and its first two radial derivatives
+      for (int j = nu.s_begin; j < nu.s_end; ++j) {
+        const CuspS sj = c.s[j];
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+        for (int k = sj.p_begin; k < sj.p_end; ++k) {
+          const PrimDev pr = c.prim[k];
+          const double x = pr.gamma * u;
+          if (x >= c.T) break;  // ascending exponents, as in the AO stage
+          const double e = pr.coef * exp(-x);
+          g0 += e;
+          g1 -= pr.gamma * e;
+          g2 += pr.gamma * pr.gamma * e;
+        }
+        // chi = M g0(u), chi' = 2 r M g1, chi'' = M (2 g1 + 4 u g2)
+        const double w = c.cs[static_cast<int64_t>(j) * N + i] * sj.m;
+        s0 += w * g0;
+        s1 += w * 2.0 * r * g1;
+        s2 += w * (2.0 * g1 + 4.0 * u * g2);
+      }
+      const double* f = c.f + static_cast<int64_t>(a) * 4 * N;
+      const double f0 = f[i], f1 = f[N + i], f2 = f[2 * N + i], f3 = f[3 * N + i];
+      const double h0 = f0 + r * (f1 + r * (f2 + r * f3)) - s0;
+      const double h1 = f1 + r * (2.0 * f2 + 3.0 * r * f3) - s1;
+      const double h2 = 2.0 * f2 + 6.0 * r * f3 - s2;
+      const double g = h1 * ir;
+      row[i] = static_cast<TD>(static_cast<double>(row[i]) + h0);
+      row[N + i] = static_cast<TD>(static_cast<double>(row[N + i]) + g * dx);
+      row[2 * N + i] = static_cast<TD>(static_cast<double>(row[2 * N + i]) + g * dy);
+      row[3 * N + i] = static_cast<TD>(static_cast<double>(row[3 * N + i]) + g * dz);
+      row[4 * N + i] = static_cast<TD>(static_cast<double>(row[4 * N + i]) + h2 + 2.0 * g);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cusp(const CuspArgs& c, const PointArgs& pts, void* mo, int out_is_f32, int64_t N,
+                       hipStream_t s) {
+  if (pts.P <= 0 || c.n_nuc <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>((pts.P + 255) / 256));
+  if (out_is_f32)
+    hipLaunchKernelGGL(cusp_kernel<float>, grid, dim3(256), 0, s, c, pts, static_cast<float*>(mo), N);
+  else
+    hipLaunchKernelGGL(cusp_kernel<double>, grid, dim3(256), 0, s, c, pts, static_cast<double*>(mo), N);
+  return hipGetLastError();
+}
+
+}  // namespace qmk

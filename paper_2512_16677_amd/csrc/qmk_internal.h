@@ -74,6 +74,28 @@ struct AoOut {
   int64_t sK, sC, sP;
 };
 
+// Cusp correction tables (see cusp_kernels.hip).  One entry per nucleus
+// with a cusp sphere: centre, radius, its s-type AOs s_begin .. s_end-1.
+struct CuspNuc {
+  double x, y, z, rc;
+  int32_t s_begin, s_end, pad0, pad1;
+};
+// One s-type AO: normalisation factor M and its primitives (folded
+// coefficients, ascending exponents) p_begin .. p_end-1 of CuspArgs::prim.
+struct CuspS {
+  double m;
+  int32_t p_begin, p_end;
+};
+struct CuspArgs {
+  const CuspNuc* nuc;
+  const CuspS* s;
+  const PrimDev* prim;
+  const double* cs;  // [s-AO j][mo i]: C[i][AO of j]
+  const double* f;   // [nucleus a][k][mo i]: polynomial coefficients f_k
+  double T;          // exponent cutoff of the AO stage
+  int32_t n_nuc;
+};
+
 // Generic strided batched GEMM  D(i,j) = sum_l A(i,l) B(l,j)  for a batch
 // index z = c*nsplit + s:
 //   A(i,l) = A[c*oAc + s*oAs + i*sAi + l*sAl]     (l restricted to split s)
@@ -167,6 +189,9 @@ hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& o
 // Values only, one plane: element (k, p) at out.out[k*out.sK + p*out.sP].
 hipError_t launch_ao_value(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                            hipStream_t s);
+// Adds the cusp correction to mo_vgl[P][5][N] (FP64 or FP32) in place.
+hipError_t launch_cusp(const CuspArgs& c, const PointArgs& pts, void* mo, int out_is_f32, int64_t N,
+                       hipStream_t s);
 // GEMM tile shape: WGM x WGN wavefronts of TM x TN 16x16 MFMA blocks, K step BK.
 struct TileCfg {
   int wgm, wgn, tm, tn, bk;
