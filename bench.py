@@ -364,7 +364,7 @@ def main_density(a):
                                    f"{No} doubly occupied of {s.mo_num} MOs, 100^3 grid",
                        "points_per_step": P},
             "roofline": roof, "modes": res,
-            "paper_context": "Section 4: density of a 1114-AO, 218-occupied-MO molecule on a 100^3 "
+            "paper_context": "Section 5.4: density of a 1114-AO, 218-occupied-MO molecule on a 100^3 "
                              "grid in 5.0 s (FP64) / 3.7 s (FP32) on 18 cores of an i7-13850HX, "
                              "including file input and cube output"}
     if not a.no_cpu_baseline:

@@ -150,7 +150,7 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
                           void* hip_stream);
 
 /* MO values only (the value rows of Section 3.2's product; the orbital
- * evaluation on grids of Section 4): mo_value[walk][elec][mo] =
+ * evaluation on grids of Section 5.4): mo_value[walk][elec][mo] =
  * sum_k C[mo][k] chi_k(r), into a device buffer of size_max >=
  * walk*elec*mo elements of type dtype (QMK_F64 or QMK_F32).  If the full AO
  * array is current for these points its value plane is read; otherwise a
@@ -160,7 +160,7 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
 qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                             void* hip_stream);
 
-/* Electron density of a determinant at every point (Section 4, density of a
+/* Electron density of a determinant at every point (Section 5.4, density of a
  * Kohn-Sham determinant as a sum of squared MOs):
  *   rho[walk][elec] = sum_n occ[n] * phi_n(r)^2
  * occ: host array of mo_num finite occupation numbers (for a closed-shell

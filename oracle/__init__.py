@@ -10,7 +10,7 @@ Layouts (C order): AO and MO results are ``[point][component][function]`` with
 components (value, d/dx, d/dy, d/dz, Laplacian); with ``nq=14`` the AO result
 also carries the Hessian (xx xy xz yy yz zz) and the gradient of the
 Laplacian (components 5..13).  MO values alone and the electron density of a
-determinant (Section 4, orbital visualisation) are taken from the value rows.
+determinant (Section 5.4, orbital visualisation) are taken from the value rows.
 """
 from __future__ import annotations
 
@@ -196,7 +196,7 @@ def mo_value(sys_, points: Optional[np.ndarray] = None, B: float = 53.0,
 def density(sys_, occ: np.ndarray, points: Optional[np.ndarray] = None, B: float = 53.0,
             coef: Optional[np.ndarray] = None, with_abs: bool = False):
     """Electron density of a determinant, rho(r) = sum_n occ[n] phi_n(r)^2
-    (Section 4: density as a sum of squared MOs), at `points` (default: all
+    (Section 5.4: density as a sum of squared MOs), at `points` (default: all
     walkers).  With with_abs, also returns sum_n |occ[n]| (sum_k |C_nk chi_k|)^2,
     an upper scale of the rounding error of any evaluation of rho."""
     C = np.asarray(sys_.mo_coef if coef is None else coef, dtype=np.float64)

@@ -15,7 +15,7 @@
 // multiplication (Section 3.1, angular part) and never stored.
 //
 // The value-only form (VAL = true) serves the MO values and the density on a
-// grid (Section 4, orbital visualisation): it accumulates only g0 and stores
+// grid (Section 5.4, orbital visualisation): it accumulates only g0 and stores
 // one [ao][point] plane.
 #include "qmk_internal.h"
 

@@ -216,7 +216,7 @@ def large(walkers: int = 64, seed: int = 0) -> System:
 
 
 def peptide_like(grid_n: int = 100, seed: int = 0, margin: float = 4.0) -> System:
-    """Stand-in for the density benchmark of Section 4 (a Cu(II)-peptide
+    """Stand-in for the density benchmark of Section 5.4 (a Cu(II)-peptide
     complex, C34 H48 Cu N11 O10, in cc-pVDZ: 1114 AOs, 218 occupied MOs, on a
     100^3 grid).  34 C, 11 N, 10 O (3s2p1d each), 48 H (2s1p) and one Cu
     (6s5p3d1f), each element with its own drawn basis -> 1114 Cartesian AOs;

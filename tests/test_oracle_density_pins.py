@@ -1,4 +1,4 @@
-"""Pins of the oracle's MO values and electron density (Section 4, density of
+"""Pins of the oracle's MO values and electron density (Section 5.4, density of
 a determinant as a sum of squared orbitals) against what the mathematics
 fixes: a closed form, the electron count by quadrature, and invariance under
 orthogonal mixing of equally occupied orbitals."""
