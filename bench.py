@@ -50,9 +50,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density"],
+    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large"],
                     help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes; "
-                         "density: electron density of a 1114-AO molecule on a 100^3 grid")
+                         "density: electron density of a 1114-AO molecule on a 100^3 grid; "
+                         "large: 7500-AO system, dense vs screened contraction")
     ap.add_argument("--cpu-walkers", type=int, default=96,
                     help="walkers in the oracle's timed sample")
     ap.add_argument("--cpu-points", type=int, default=1000000,
@@ -383,6 +384,66 @@ def main_density(a):
     print(json.dumps(line))
 
 
+def main_large(a):
+    """The 7500-AO / 1050-MO system at 64 walkers: forward (dense and screened
+    contraction) and forward + adjoint, per precision mode."""
+    import torch
+    import synth
+    import paper_2512_16677_amd as qmk
+    s = synth.large(walkers=64)
+    P, K, N = s.point_num, s.ao_num, s.mo_num
+    dev = torch.device("cuda:0")
+    r0 = torch.from_numpy(np.ascontiguousarray(s.elec_coord)).to(dev)
+    r1 = (r0 + 1e-3).contiguous()
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    res = {}
+    for mode, bits in (("fp64", 53), ("mixed_f32", 24), ("mixed_bf16x3", 24)):
+        ctx = qmk.Context.from_system(s, bits=bits, mode=mode)
+        dt = torch.float64 if mode == "fp64" else torch.float32
+        mo = torch.empty((s.walk_num, s.elec_num, 5, N), dtype=dt, device=dev)
+        out = {}
+        for screened in (False, True):
+            if screened and mode == "mixed_bf16x3":
+                continue
+            ctx.set_screening(screened)
+            for i in range(a.warmup):
+                ctx.set_point(r0 if i % 2 == 0 else r1)
+                ctx.get_mo_vgl(out=mo)
+            torch.cuda.synchronize()
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            for i in range(a.steps):
+                ctx.set_point(r0 if i % 2 == 0 else r1)
+                ctx.get_mo_vgl(out=mo)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / a.steps
+            t = ctx.timing()
+            key = "screened" if screened else "dense"
+            out[key] = {"forward_ms": ms, "e_evals_per_s": P / (ms * 1e-3),
+                        "mo_ms": t["mo"]["ms"] / max(1, t["mo"]["launches"]),
+                        "ao_ms": t["ao"]["ms"] / max(1, t["ao"]["launches"])}
+            if screened:
+                out[key]["sort_ms"] = t["sort"]["ms"] / max(1, t["sort"]["launches"])
+                out[key]["screening_density"] = ctx.screening_density()
+        if "screened" in out:
+            out["forward_speedup"] = out["dense"]["forward_ms"] / out["screened"]["forward_ms"]
+        out["mo_dense_TFLOPs"] = 2.0 * 5 * P * K * N / (out["dense"]["mo_ms"] * 1e-3) / 1e12
+        ctx.close()
+        del mo
+        torch.cuda.empty_cache()
+        res[mode] = out
+    line = {"metric": "mo_vgl electron-evals/s (forward), dense vs screened contraction",
+            "value": res["fp64"]["screened"]["e_evals_per_s"], "unit": "e-evals/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["fp64"]["screened"]["forward_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"ch300_7500ao: 150 C + 150 H in a 35-bohr cube, {K} AOs, {N} MOs, "
+                                   f"{s.elec_num} electrons, 64 walkers; forward", "points_per_step": P},
+            "modes": res}
+    print(json.dumps(line))
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: under a hardware-counter
     profile its FETCH_SIZE / WRITE_SIZE give the factor that turns those
@@ -401,6 +462,12 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "large":
+        if a.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        main_large(a)
         return
     if a.workload == "density":
         if a.gpus != 1:

@@ -195,6 +195,24 @@ qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, doub
 qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
                            const double* r_cusp);
 
+/* Screened contraction (Section 3.2: the sparsity of the AOs lowers the
+ * cost of the MO product).  With enable = 1, qmk_get_mo_vgl sorts the points
+ * by nearest nucleus, evaluates the AOs in that order while recording which
+ * (64-point block, 16-AO chunk) pairs hold a non-zero AO, and runs an MFMA
+ * product that skips, per output tile, every K stage whose AOs are zero for
+ * all of the tile's points; rows are written back in the caller's order.
+ * Only exact zeros (AOs beyond the exponent cutoff) are skipped, so the
+ * result equals the dense product's bit for bit (up to the sign of a zero).
+ * FP64 and FP32 modes; in the BF16x3 mode the dense product runs.  At most
+ * 16384 AOs (QMK_UNSUPPORTED above).  The other calls (AO values, MO values,
+ * density, adjoint) keep the dense path.  enable = 0 restores the default. */
+qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable);
+
+/* Fraction of (64-point block, 16-AO chunk) pairs with a non-zero AO in the
+ * last screened AO evaluation (the screening density; synchronises the
+ * device).  QMK_NOT_SET before the first screened evaluation. */
+qmk_status qmk_get_screening_density(qmk_ctx ctx, double* active_fraction);
+
 /* Adjoint of L = sum(W * mo_vgl) for the current points (Section 3.6 and
  * Section 3.5 motivate these derivatives; the nuclei carry their shells
  * rigidly, basis parameters are fixed):
@@ -226,7 +244,8 @@ enum {
   QMK_KERNEL_REDUCE = 5,     /* deterministic reductions               */
   QMK_KERNEL_DENSITY = 6,    /* MO values squared and summed (density) */
   QMK_KERNEL_CUSP = 7,       /* MO cusp correction                     */
-  QMK_KERNEL_CLASSES = 8
+  QMK_KERNEL_SORT = 8,       /* point sort of the screened contraction */
+  QMK_KERNEL_CLASSES = 9
 };
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);

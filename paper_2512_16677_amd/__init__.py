@@ -46,13 +46,14 @@ EXPORTED = [
     "qmk_status_string", "qmk_last_error", "qmk_ctx_create", "qmk_ctx_destroy",
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
-    "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp",
+    "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp", "qmk_set_screening",
+    "qmk_get_screening_density",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
     "qmk_get_tile_count", "qmk_set_tile",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
-KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp"]
+KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp", "sort"]
 
 _lib = None
 
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_mo_value": ([P, P, I64, I32, P], I32),
         "qmk_get_density": ([P, P, I64, P, I64, P], I32),
         "qmk_set_mo_cusp": ([P, I64, P, P], I32),
+        "qmk_set_screening": ([P, I32], I32),
+        "qmk_get_screening_density": ([P, P], I32),
         "qmk_mo_vgl_adjoint": ([P, P, I32, P, P, P, P], I32),
         "qmk_get_launch_count": ([P, P], I32),
         "qmk_set_timing": ([P, I32], I32),
@@ -279,6 +282,17 @@ class Context:
         z = _np(charge, np.float64).reshape(-1)
         r = _np(r_cusp, np.float64).reshape(-1)
         self._check(self._lib.qmk_set_mo_cusp(self._h, r.shape[0], _ptr(z), _ptr(r)))
+
+    def set_screening(self, enable: bool = True):
+        """Screened (block-sparse) forward contraction on or off."""
+        self._check(self._lib.qmk_set_screening(self._h, 1 if enable else 0))
+
+    def screening_density(self) -> float:
+        """Fraction of (64-point block, 16-AO chunk) pairs with a non-zero AO
+        in the last screened evaluation."""
+        v = ctypes.c_double()
+        self._check(self._lib.qmk_get_screening_density(self._h, ctypes.byref(v)))
+        return v.value
 
     def get_mo_value(self, out=None, dtype=None, stream=None):
         """MO values only: CUDA tensor [walk, elec, mo]."""

@@ -115,9 +115,10 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
   const bool valid = p < pts.P;
   double rx = 0.0, ry = 0.0, rz = 0.0;
   if (valid) {
-    rx = pts.coord[p * pts.s_pt];
-    ry = pts.coord[p * pts.s_pt + pts.s_ax];
-    rz = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
+    const int64_t src = pts.perm ? static_cast<int64_t>(pts.perm[p]) : p;
+    rx = pts.coord[src * pts.s_pt];
+    ry = pts.coord[src * pts.s_pt + pts.s_ax];
+    rz = pts.coord[src * pts.s_pt + 2 * pts.s_ax];
   }
   OutT* const obase = static_cast<OutT*>(out.out) + p * out.sP;
   const double T = t.T;
@@ -137,17 +138,26 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
     for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
       const ShellDev sh = s_shell[s];
       double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+      bool any_on = false;
       for (int k = sh.p_begin; k < sh.p_end; ++k) {
         const PrimDev pr = s_prim[k];
         const double x = pr.gamma * u;
         const bool on = near && (x < T);
         if (!__any(on)) break;  // ascending exponents: every later one is cut too
+        any_on = true;
         if (on) {
           const double e = pr.coef * exp(-x);
           g0 += e;
           g1 -= pr.gamma * e;
           g2 += pr.gamma * pr.gamma * e;
         }
+      }
+      if (out.act && any_on && (threadIdx.x & 63) == 0) {
+        // this wave's block has non-zero AOs in the shell's chunks
+        uint32_t* const w = out.act + (p >> 6) * out.act_words;
+        const int c0 = sh.ao_off / kSparseChunk;
+        const int c1 = (sh.ao_off + (sh.l + 1) * (sh.l + 2) / 2 - 1) / kSparseChunk;
+        for (int c = c0; c <= c1; ++c) atomicOr(w + (c >> 5), 1u << (c & 31));
       }
       if (valid) {
         if (VAL)

@@ -348,6 +348,55 @@ qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
 }
 
 // Tile for one product: forced by qmk_set_tile, else the autotuner's choice.
+// Screened contraction input: the points sorted by nearest nucleus, the AO
+// array in that order and the (64-point block, 16-AO chunk) activity bitmap.
+qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s) {
+  qmk_status st = ensure_tables(ctx);
+  if (st != QMK_OK) return st;
+  const int f32 = ctx->f32_storage() ? 1 : 0;
+  const int64_t P = ctx->P(), Pp = round_up(P, kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
+  if (ctx->aos_date == ctx->date && ctx->aos_f32 == f32 && ctx->aos_Pp == Pp && ctx->aos_Kp == Kp)
+    return QMK_OK;
+  const int64_t nn = ctx->nucl_num;
+  if (ctx->nuc_xyz_version != ctx->geom_version) {
+    QMK_HIP(ctx, ctx->d_nuc_xyz.ensure(static_cast<size_t>(3 * nn) * 8), "alloc nuclei");
+    QMK_HIP(ctx, hipMemcpy(ctx->d_nuc_xyz.p, ctx->nucl.data(), static_cast<size_t>(3 * nn) * 8,
+                           hipMemcpyHostToDevice), "upload nuclei");
+    ctx->nuc_xyz_version = ctx->geom_version;
+  }
+  QMK_HIP(ctx, ctx->d_sort_key.ensure(static_cast<size_t>(P) * 4), "alloc sort keys");
+  QMK_HIP(ctx, ctx->d_sort_counts.ensure(static_cast<size_t>(nn + 1) * 4), "alloc sort counts");
+  QMK_HIP(ctx, ctx->d_perm.ensure(static_cast<size_t>(P) * 4), "alloc permutation");
+  ctx->act_words = (Kp / kSparseChunk + 31) / 32;
+  const int64_t act_n = (Pp / 64) * ctx->act_words;
+  QMK_HIP(ctx, ctx->d_act.ensure(static_cast<size_t>(act_n) * 4), "alloc activity bitmap");
+  if (ctx->aos_Pp != Pp || ctx->aos_Kp != Kp || ctx->aos_f32 != f32 || !ctx->aos.p) {
+    const size_t bytes = static_cast<size_t>(Kp * 5 * Pp) * (f32 ? 4 : 8);
+    ctx->aos.release();
+    QMK_HIP(ctx, ctx->aos.ensure(bytes), "alloc sorted AO array");
+    QMK_HIP(ctx, hipMemsetAsync(ctx->aos.p, 0, bytes, s), "clear sorted AO array");
+    ctx->aos_Pp = Pp;
+    ctx->aos_Kp = Kp;
+    ctx->aos_f32 = f32;
+  }
+  PointArgs pa = point_args(ctx);
+  {
+    LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
+    QMK_HIP(ctx, launch_sort_points(pa, ctx->d_nuc_xyz.as<double>(), nn, ctx->d_sort_key.as<int32_t>(),
+                                    ctx->d_sort_counts.as<int32_t>(), ctx->d_perm.as<int32_t>(), s),
+            "sort points");
+    QMK_HIP(ctx, launch_fill_u32(ctx->d_act.as<uint32_t>(), act_n, 0u, s), "clear activity bitmap");
+  }
+  pa.perm = ctx->d_perm.as<int32_t>();
+  AoOut o{ctx->aos.p, 5 * Pp, Pp, 1, ctx->d_act.as<uint32_t>(), ctx->act_words};
+  {
+    LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
+    QMK_HIP(ctx, launch_ao_vgl(ctx->tab, pa, o, f32, f32, s), "AO kernel (sorted points)");
+  }
+  ctx->aos_date = ctx->date;
+  return QMK_OK;
+}
+
 // AO values for the current points: the value plane of the full AO array
 // when that is current, else the value-only kernel into its own plane.
 // Returns the plane and its AO-row stride.
@@ -617,6 +666,63 @@ GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void*
 }  // namespace qmk
 
 // ===========================================================================
+namespace qmk {
+
+qmk_status apply_cusp(qmk_ctx ctx, void* out, int o32, hipStream_t s) {
+  if (!ctx->cusp_on) return QMK_OK;
+  qmk_status st = ensure_cusp(ctx, s);
+  if (st != QMK_OK) return st;
+  LaunchTimer lt(ctx, QMK_KERNEL_CUSP, s);
+  QMK_HIP(ctx, launch_cusp(ctx->cusp, point_args(ctx), out, o32, ctx->mo_num, s), "cusp correction");
+  return QMK_OK;
+}
+
+// Screened forward product (Section 3.2, sparsity of the AOs): the AO array
+// in sorted point order, and a product that visits only the K stages with a
+// non-zero AO chunk in its M tile; rows go back to the caller's order.
+qmk_status get_mo_vgl_screened(qmk_ctx ctx, void* out, int32_t dtype, hipStream_t s) {
+  const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
+  if (round_up(K, kAoPad) / kSparseChunk > kSparseMaxStages)
+    return fail(ctx, QMK_UNSUPPORTED, "the screened product supports at most " +
+                                          std::to_string(kSparseMaxStages * kSparseChunk) + " AOs");
+  qmk_status st = provide_ao_sorted(ctx, s);
+  if (st != QMK_OK) return st;
+  const int64_t Pp = ctx->aos_Pp;
+  GemmArgs ga{};
+  ga.A = ctx->aos.p;
+  ga.sAi = 1;
+  ga.sAl = 5 * Pp;
+  ga.oAc = Pp;
+  ga.B = ctx->d_Ct.p;
+  ga.sBl = ctx->Np;
+  ga.sBj = 1;
+  ga.D = out;
+  ga.sDi = 5 * N;
+  ga.sDj = 1;
+  ga.oDz = N;
+  ga.M = P;
+  ga.N = N;
+  ga.L = ga.Lchunk = K;
+  ga.nsplit = 1;
+  ga.nbatch = 5;
+  ga.act = ctx->d_act.as<uint32_t>();
+  ga.act_words = ctx->act_words;
+  ga.perm = ctx->d_perm.as<int32_t>();
+  const Prec prec = gemm_prec(ctx);
+  const int o32 = dtype == QMK_F32;
+  GemmProblem pb{GemmKind::kForward, prec, 0, o32, P, N, K};
+  pb.sparse = 1;
+  int cfg = 0;
+  if ((st = pick_tile(ctx, pb, s, [&](int c) { return launch_gemm_sparse(prec, c, ga, o32, s); }, &cfg)) !=
+      QMK_OK)
+    return st;
+  LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
+  QMK_HIP(ctx, launch_gemm_sparse(prec, cfg, ga, o32, s), "screened MO contraction");
+  return QMK_OK;
+}
+
+}  // namespace qmk
+
 extern "C" {
 
 const char* qmk_status_string(qmk_status st) {
@@ -830,6 +936,29 @@ qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
   return QMK_OK;
 }
 
+qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable) {
+  QMK_CHECK_CTX(ctx);
+  if (enable != 0 && enable != 1) return bad_arg(ctx, 2, "enable must be 0 or 1");
+  ctx->sparse = enable == 1;
+  return QMK_OK;
+}
+
+qmk_status qmk_get_screening_density(qmk_ctx ctx, double* active_fraction) {
+  QMK_CHECK_CTX(ctx);
+  if (!active_fraction) return bad_arg(ctx, 2, "NULL");
+  if (ctx->aos_date < 0 || !ctx->d_act.p) return fail(ctx, QMK_NOT_SET, "no screened AO evaluation yet");
+  DeviceGuard g(ctx->device);
+  const int64_t blocks = (ctx->P() + 63) / 64, nchunk = ctx->aos_Kp / kSparseChunk;
+  std::vector<uint32_t> bits(static_cast<size_t>(blocks * ctx->act_words));
+  QMK_HIP(ctx, hipDeviceSynchronize(), "wait for the AO stage");
+  QMK_HIP(ctx, hipMemcpy(bits.data(), ctx->d_act.p, bits.size() * 4, hipMemcpyDeviceToHost), "download bitmap");
+  int64_t on = 0;
+  for (int64_t b = 0; b < blocks; ++b)
+    for (int64_t c = 0; c < nchunk; ++c) on += (bits[b * ctx->act_words + (c >> 5)] >> (c & 31)) & 1u;
+  *active_fraction = static_cast<double>(on) / static_cast<double>(std::max<int64_t>(1, blocks * nchunk));
+  return QMK_OK;
+}
+
 qmk_status qmk_set_point(qmk_ctx ctx, char transp, int64_t walk_num, int64_t elec_num,
                          const double* coord, int32_t coord_on_device) {
   QMK_CHECK_CTX(ctx);
@@ -958,6 +1087,10 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   DeviceGuard g(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
+  if (ctx->sparse && ctx->mode != QMK_MIXED_BF16X3) {
+    if ((st = get_mo_vgl_screened(ctx, out, dtype, s)) != QMK_OK) return st;
+    return apply_cusp(ctx, out, dtype == QMK_F32, s);
+  }
   if ((st = provide_ao(ctx, s)) != QMK_OK) return st;
   const int64_t Pp = ctx->ao_Pp;
   GemmArgs ga{};
@@ -998,12 +1131,7 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
     LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
     QMK_HIP(ctx, launch_gemm_typed(GemmKind::kForward, prec, cfg, ga, 0, o32, s), "MO contraction");
   }
-  if (ctx->cusp_on) {
-    if ((st = ensure_cusp(ctx, s)) != QMK_OK) return st;
-    LaunchTimer lt(ctx, QMK_KERNEL_CUSP, s);
-    QMK_HIP(ctx, launch_cusp(ctx->cusp, point_args(ctx), out, o32, N, s), "cusp correction");
-  }
-  return QMK_OK;
+  return apply_cusp(ctx, out, o32, s);
 }
 
 qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,

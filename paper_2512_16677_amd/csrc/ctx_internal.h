@@ -120,6 +120,13 @@ struct qmk_ctx_s {
   int occ_f32 = -1;
   int64_t coef_version = 0;
 
+  // screened contraction: points sorted by nearest nucleus, the AO array in
+  // that order [Kp][5][Pp] and its activity bitmap, valid at aos_date
+  bool sparse = false;
+  DevBuf d_sort_key, d_sort_counts, d_perm, d_act, aos, d_nuc_xyz;
+  int64_t aos_Pp = 0, aos_Kp = 0, aos_date = -1, act_words = 0, nuc_xyz_version = -1;
+  int aos_f32 = -1;
+
   // MO cusp correction: inputs, and device tables valid for cusp_key
   bool cusp_on = false;
   std::vector<double> cusp_charge, cusp_rc;

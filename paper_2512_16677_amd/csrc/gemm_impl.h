@@ -55,10 +55,14 @@ struct GemmSmem {
 // the density epilogue: each wave reduces occ[j] * D(i, j)^2 over its own
 // columns and stores the partial sum of row i in slot nt * WGN + wn, at
 // D[i*sDi + slot*sDj] (FP64).
+// EPI = 2 is the screened forward product: the K loop visits only the
+// stages listed in stage_list (the rest of A is zero for every row of the
+// tile), and row i of D is stored at row perm[i].
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
           int BK, bool A_I, bool B_J, int EPI = 0>
 __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int z,
-                                          GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK>& sm) {
+                                          GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK>& sm,
+                                          const int16_t* stage_list = nullptr, int n_stages = 0) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
@@ -147,15 +151,18 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  const int64_t nk = (Ls + BK - 1) / BK;
+  const int64_t nk = EPI == 2 ? n_stages : (Ls + BK - 1) / BK;
+  auto l0_of = [&](int64_t t) -> int64_t {
+    return (EPI == 2 ? static_cast<int64_t>(stage_list[t]) : t) * BK;
+  };
   if (nk > 0) {
-    load(0);
+    load(l0_of(0));
     stash(0);
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = static_cast<int>(kt & 1);
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (kt + 1 < nk) load(l0_of(kt + 1));
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4), ci = lane & 15;
@@ -197,6 +204,22 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
         if ((lane & 15) == 0 && gi < g.M) part[gi * g.sDi] = v;
       }
     }
+  } else if constexpr (EPI == 2) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        if (gi >= g.M) continue;
+        TD* const row = Dp + static_cast<int64_t>(g.perm[gi]) * g.sDi;
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+          if (gj < g.N) row[gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+        }
+      }
+    }
   } else {
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -209,6 +232,46 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
           if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
         }
   }
+}
+
+// Screened forward product (A = the AO array in sorted point order, i
+// contiguous; B = C^T, j contiguous).  Wave 0 lists the K stages for which
+// any 64-point block of this M tile has an active 16-AO chunk (g.act bitmap
+// written by the AO kernel); the tile then runs over those stages only.
+// Skipped stages hold exact zeros of A for every row of the tile, so each
+// row's result is the dense product's, bit for bit.
+template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
+          int BK>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_sparse_kernel(GemmArgs g, int nM, int nN) {
+  constexpr int BM = 16 * WGM * TM;
+  __shared__ GemmSmem<T, BM, 16 * WGN * TN, BK> sm;
+  __shared__ int16_t s_list[kSparseMaxStages];
+  __shared__ int s_n;
+  int mt, nt, z;
+  if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int64_t i0 = static_cast<int64_t>(mt) * BM;
+    const int64_t wb0 = i0 / 64, wb1 = (min(i0 + BM, g.M) - 1) / 64;
+    const int64_t nk = (g.L + BK - 1) / BK, nchunk = (g.L + kSparseChunk - 1) / kSparseChunk;
+    int count = 0;
+    for (int64_t base = 0; base < nk; base += 64) {
+      const int64_t t = base + lane;
+      bool on = false;
+      if (t < nk) {
+        const int64_t c1 = min((t + 1) * BK / kSparseChunk, nchunk);
+        for (int64_t c = t * BK / kSparseChunk; c < c1 && !on; ++c)
+          for (int64_t wb = wb0; wb <= wb1 && !on; ++wb)
+            on = (g.act[wb * g.act_words + (c >> 5)] >> (c & 31)) & 1u;
+      }
+      const uint64_t mask = __ballot(on);
+      if (on) s_list[count + __popcll(mask & ((1ull << lane) - 1))] = static_cast<int16_t>(t);
+      count += __popcll(mask);
+    }
+    if (lane == 0) s_n = count;
+  }
+  __syncthreads();
+  gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, true, true, 2>(g, mt, nt, z, sm, s_list, s_n);
 }
 
 // Density product: partial sums over columns of occ[j] (sum_l A(i,l) B(l,j))^2
@@ -336,6 +399,29 @@ hipError_t run_density_tile(const GemmArgs& g, hipStream_t s) {
   hipLaunchKernelGGL((gemm_density_kernel<T, WGM, WGN, TM, TN, BK>), grid_of(g, nM, nN),
                      dim3(64 * WGM * WGN), 0, s, g, nM, nN);
   return hipGetLastError();
+}
+
+template <typename T, typename TD, int WGM, int WGN, int TM, int TN, int BK>
+hipError_t run_sparse_tile(const GemmArgs& g, hipStream_t s) {
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+  const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
+  if (nM <= 0 || nN <= 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_sparse_kernel<T, T, T, TD, WGM, WGN, TM, TN, BK>), grid_of(g, nM, nN),
+                     dim3(64 * WGM * WGN), 0, s, g, nM, nN);
+  return hipGetLastError();
+}
+
+template <typename T, typename TD>
+hipError_t run_sparse(int cfg, const GemmArgs& g, hipStream_t s) {
+  switch (cfg) {
+#define QMK_TILE_SCASE(id, wgm, wgn, tm, tn, bk) \
+  case id:                                       \
+    return run_sparse_tile<T, TD, wgm, wgn, tm, tn, bk>(g, s);
+    QMK_TILE_LIST(QMK_TILE_SCASE)
+#undef QMK_TILE_SCASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>

@@ -9,6 +9,8 @@
 //             16 consecutive points, so the output is written in full lines)
 //   dC        ws[c,s][n][k] = sum_{p in split s} W[p][c][n] ao[k][c][p]
 //   density   part[t][p]    = sum_{n in tile t} occ[n] (sum_k ao[k][p] Ct[k][n])^2
+//   screened  mo[perm[q]][c][n] = sum_{k in active chunks} aos[k][c][q] Ct[k][n]
+//             (aos: the AO array in sorted point order)
 // (see GemmArgs for the index algebra).  A tile is WGM x WGN wavefronts,
 // each owning TM x TN MFMA 16x16x4 blocks (FP64 or FP32); the shapes on
 // offer are listed in QMK_TILE_LIST and chosen per problem by the host
@@ -72,6 +74,13 @@ hipError_t gemm_unit_f32_dc(int cfg, const GemmArgs* g, const PersistLaunch* pl,
   return alt ? run<float, float, float, double, true, false>(cfg, *g, s) : run<float, double, float, double, true, false>(cfg, *g, s);
 }
 #endif
+#if QMK_GEMM_UNIT == 8
+hipError_t gemm_unit_sparse(int cfg, const GemmArgs* g, Prec prec, int o32, hipStream_t s) {
+  if (prec == Prec::kF64)
+    return o32 ? run_sparse<double, float>(cfg, *g, s) : run_sparse<double, double>(cfg, *g, s);
+  return o32 ? run_sparse<float, float>(cfg, *g, s) : run_sparse<float, double>(cfg, *g, s);
+}
+#endif
 #if QMK_GEMM_UNIT == 7
 hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t s) {
   return prec == Prec::kF64 ? run_density<double>(cfg, *g, s) : run_density<float>(cfg, *g, s);
@@ -79,7 +88,7 @@ hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t 
 #endif
 #else
 // Products of each (precision, kind) are instantiated in their own
-// translation unit (this file compiled with QMK_GEMM_UNIT = 1..7) so that
+// translation unit (this file compiled with QMK_GEMM_UNIT = 1..8) so that
 // they build in parallel; the unit without QMK_GEMM_UNIT holds the tables
 // and the dispatch.
 hipError_t gemm_unit_f64_fwd(int cfg, const GemmArgs* g, const PersistLaunch* pl, int w32, int o32,
@@ -96,6 +105,7 @@ hipError_t gemm_unit_f32_dc(int cfg, const GemmArgs* g, const PersistLaunch* pl,
                          hipStream_t s);
 
 hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t s);
+hipError_t gemm_unit_sparse(int cfg, const GemmArgs* g, Prec prec, int o32, hipStream_t s);
 namespace {
 hipError_t unit_dispatch(GemmKind kind, Prec prec, int cfg, const GemmArgs* g, const PersistLaunch* pl,
                          int w32, int o32, hipStream_t s) {
@@ -131,6 +141,11 @@ size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
   const size_t pad = 16 / esz;
   return 2 * static_cast<size_t>(t.bk) *
          ((16 * t.wgm * t.tm + pad) + (16 * t.wgn * t.tn + pad)) * esz;
+}
+
+hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s) {
+  if (prec == Prec::kBF16x3 || cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
+  return gemm_unit_sparse(cfg, &g, prec, out_is_f32, s);
 }
 
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s) {

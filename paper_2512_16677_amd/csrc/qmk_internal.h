@@ -22,6 +22,8 @@ constexpr int kGroupMaxAo = 120;
 constexpr int kPointPad = 256;      // points are padded to a multiple of this
 constexpr int kAoPad = 128;         // AOs (K) padded to a multiple of this
 constexpr int kMoPad = 128;         // MOs (N) padded to a multiple of this
+constexpr int kSparseChunk = 16;    // AOs per chunk of the screened product's bitmap
+constexpr int kSparseMaxStages = 1024;  // K stages a screened product can list (K <= 16384)
 
 // One nucleus as the AO kernels see it.  gmin = smallest exponent of all its
 // primitives: if gmin*u >= T for every point of a wavefront, the whole
@@ -66,12 +68,17 @@ struct PointArgs {
   const double* coord;      // device
   int64_t s_pt, s_ax;       // coord of point p, axis i: coord[p*s_pt + i*s_ax]
   int64_t P;                // number of points
+  const int32_t* perm;      // AO kernel only: point p reads coordinates perm[p] (NULL: p)
 };
 
 // Strided AO output: element (k, c, p) at out[k*sK + c*sC + p*sP].
 struct AoOut {
   void* out;
   int64_t sK, sC, sP;
+  // when non-NULL: bit c of act[(p/64)*act_words + c/32] is set if any point
+  // of the 64-point block of p has a non-zero AO in chunk c (16 AOs)
+  uint32_t* act;
+  int64_t act_words;
 };
 
 // Cusp correction tables (see cusp_kernels.hip).  One entry per nucleus
@@ -126,6 +133,12 @@ struct GemmArgs {
   int32_t map_slab;
   // Density epilogue only: occupation of column j (device, N entries).
   const double* occ;
+  // Screened forward product only: activity bitmap of (64-point block,
+  // 16-AO chunk) pairs, act_words 32-bit words per block, and the original
+  // row of each sorted row.
+  const uint32_t* act;
+  const int32_t* perm;
+  int64_t act_words;
 };
 
 // Tile of workgroup `bid` of a grid launch; false if it has none.  The
@@ -201,6 +214,13 @@ struct TileCfg {
 int gemm_num_tiles(Prec prec);
 TileCfg gemm_tile(Prec prec, int cfg);
 size_t gemm_tile_lds_bytes(Prec prec, int cfg);
+// Screened forward product (FP64 or FP32 tile cfg; D in FP64 or FP32).
+hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s);
+// Point sort by nearest nucleus (counting sort): perm[i] = original index of
+// sorted point i.  key, counts are scratch of P and n_nuc + 1 entries.
+hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64_t n_nuc,
+                              int32_t* key, int32_t* counts, int32_t* perm, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // Density product (FP64 or FP32 tile cfg): partial row sums of
 // occ[j] D(i, j)^2 per (N tile, wave) slot; see gemm_body.
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s);
@@ -220,6 +240,7 @@ struct GemmProblem {
   int w32, o32;
   int64_t M, N, L;
   int nbatch = 5;  // components per product (1: values only)
+  int sparse = 0;  // screened forward product
 };
 bool tile_feasible(Prec prec, int cfg);
 int default_tile(const GemmProblem& p);

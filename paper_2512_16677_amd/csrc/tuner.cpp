@@ -87,6 +87,7 @@ std::string key_of(const GemmProblem& p, int device) {
   o << arch << "/k" << static_cast<int>(p.kind) << "/p" << static_cast<int>(p.prec) << "/w" << p.w32
     << "/o" << p.o32 << "/" << p.M << "x" << p.N << "x" << p.L;
   if (p.nbatch != 5) o << "/b" << p.nbatch;
+  if (p.sparse) o << "/s";
   return o.str();
 }
 

@@ -1,0 +1,114 @@
+"""Screened (block-sparse) forward contraction (Section 3.2, sparsity of the
+AOs) through the C ABI.
+
+Only exact zeros of the AO array are skipped, so the screened product must
+equal the dense product bit for bit (compared with ==, which treats the two
+zeros as equal), and therefore the oracle to the FP64 tolerance."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import component_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def qmk():
+    import paper_2512_16677_amd as q
+    return q
+
+
+def dense_and_screened(s, bits=53, mode="fp64", dtype=None, tile=None):
+    q = qmk()
+    ctx = q.Context.from_system(s, bits=bits, mode=mode)
+    if tile is not None:
+        ctx.set_tile("mo", tile)
+    dense = ctx.get_mo_vgl(dtype=dtype)
+    ctx.set_screening(True)
+    scr = ctx.get_mo_vgl(dtype=dtype)
+    frac = ctx.screening_density()
+    ctx.close()
+    return dense, scr, frac
+
+
+@pytest.mark.parametrize("system", ["water_like", "medium", "large"])
+def test_screened_equals_dense_and_oracle(system):
+    s = {"water_like": lambda: synth.water_like(walkers=5),
+         "medium": lambda: synth.medium(walkers=2),
+         "large": lambda: synth.large(walkers=1)}[system]()
+    dense, scr, frac = dense_and_screened(s)
+    print(json.dumps({"system": system, "screening_density": frac}))
+    assert 0.0 < frac <= 1.0
+    assert bool((dense == scr).all())
+    if system != "large":
+        e = component_errors(scr.cpu().numpy().reshape(-1, 5, s.mo_num), oracle.mo_vgl(s))
+        for k, v in e.items():
+            assert v <= 1e-12, (k, v)
+
+
+def test_screened_skips_work_on_the_large_system():
+    """Sorted 64-point blocks of the 7500-AO system use far from every AO
+    chunk (the screening density is well below 1) and the result still
+    equals the dense product; sampled rows match the oracle."""
+    s = synth.large(walkers=8)
+    dense, scr, frac = dense_and_screened(s, bits=24, mode="mixed_f32")
+    print(json.dumps({"large_B24_screening_density": frac}))
+    assert frac < 0.6
+    assert bool((dense == scr).all())
+    idx = np.arange(0, s.point_num, 997)
+    rows = scr.reshape(s.point_num, 5, s.mo_num)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    for k, v in component_errors(rows, oracle.mo_vgl(s, points=s.points()[idx], B=24)).items():
+        assert v <= 2e-5, (k, v)
+
+
+def test_screened_every_tile_shape():
+    s = synth.medium(walkers=1)
+    q = qmk()
+    ctx = q.Context.from_system(s, bits=24)
+    dense = ctx.get_mo_vgl()
+    ctx.set_screening(True)
+    for t in range(ctx.tile_count()):
+        ctx.set_tile("mo", t)
+        assert bool((ctx.get_mo_vgl() == dense).all()), t
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode,dtype", [("mixed_f32", "f32"), ("mixed_f32", "f64"), ("fp64", "f32")])
+def test_screened_mixed_and_output_types(mode, dtype):
+    s = synth.medium(walkers=1)
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    dense, scr, _ = dense_and_screened(s, bits=24, mode=mode, dtype=dt)
+    assert scr.dtype == dt
+    assert bool((dense == scr).all())
+
+
+def test_screened_new_points_cusp_and_other_calls():
+    """New points re-sort; the cusp correction applies on top; the AO array,
+    MO values and the adjoint keep the dense path."""
+    q = qmk()
+    s = synth.water_like(walkers=6)
+    z = s.nucl_charge.astype(np.float64)
+    rc = np.array([0.25, 0.2, 0.2])
+    ctx = q.Context.from_system(s)
+    ctx.set_screening(True)
+    ctx.set_mo_cusp(z, rc)
+    for shift in (0.0, 0.37):
+        pts = np.ascontiguousarray(s.elec_coord + shift)
+        ctx.set_point(pts)
+        got = ctx.get_mo_vgl().cpu().numpy().reshape(-1, 5, s.mo_num)
+        ref = oracle.mo_vgl_cusp(s, z, rc, points=pts.reshape(-1, 3))
+        for k, v in component_errors(got, ref).items():
+            assert v <= 1e-12, (k, v)
+    ctx.set_mo_cusp(None)
+    w = torch.from_numpy(synth.adjoint_weights(s, seed=1)).cuda()
+    g = ctx.adjoint(w)
+    r = oracle.adjoint(s, w.cpu().numpy(), points=pts.reshape(-1, 3))
+    assert float(np.max(np.abs(g["d_coef"].cpu().numpy() - r["d_coef"]) / r["d_coef_abs"])) <= 1e-11
+    ao = ctx.get_ao_vgl().cpu().numpy().reshape(-1, 5, s.ao_num)
+    for k, v in component_errors(ao, oracle.ao_vgl(s, points=pts.reshape(-1, 3))).items():
+        assert v <= 1e-12, (k, v)
+    ctx.close()
