@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large"],
+    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large", "det"],
                     help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes; "
                          "density: electron density of a 1114-AO molecule on a 100^3 grid; "
-                         "large: 7500-AO system, dense vs screened contraction")
+                         "large: 7500-AO system, dense vs screened contraction; "
+                         "det: batched determinants and adjugates of small matrices")
     ap.add_argument("--cpu-walkers", type=int, default=96,
                     help="walkers in the oracle's timed sample")
     ap.add_argument("--cpu-points", type=int, default=1000000,
@@ -444,6 +445,49 @@ def main_large(a):
     print(json.dumps(line))
 
 
+def main_det(a):
+    """Determinant + adjugate of 2^24 random n x n matrices, n = 2, 3, 4, and
+    2^16 matrices of n = 16 (LU path); one launch per step."""
+    import torch
+    import paper_2512_16677_amd as qmk
+    ctx = qmk.Context()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    res = {}
+    for n, batch in ((2, 1 << 24), (3, 1 << 24), (4, 1 << 24), (16, 1 << 16)):
+        A = torch.randn((batch, n, n), generator=g, device="cuda", dtype=torch.float64)
+        det = torch.empty((batch,), dtype=torch.float64, device="cuda")
+        adj = torch.empty_like(A)
+        ctx._check(ctx._lib.qmk_det_adj(ctx._h, n, batch, qmk._ptr(A), qmk._ptr(det), qmk._ptr(adj),
+                                        qmk._stream(None)))
+        for _ in range(a.warmup):
+            ctx._check(ctx._lib.qmk_det_adj(ctx._h, n, batch, qmk._ptr(A), qmk._ptr(det), qmk._ptr(adj),
+                                            qmk._stream(None)))
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        for _ in range(a.steps):
+            ctx._check(ctx._lib.qmk_det_adj(ctx._h, n, batch, qmk._ptr(A), qmk._ptr(det), qmk._ptr(adj),
+                                            qmk._stream(None)))
+        t = ctx.timing()["det"]
+        ms = t["ms"] / t["launches"]
+        nbytes = batch * (2 * n * n + 1) * 8.0
+        res[f"n{n}"] = {"batch": batch, "avg_ms": ms, "matrices_per_s": batch / (ms * 1e-3),
+                        "GBps": nbytes / (ms * 1e-3) / 1e9}
+        del A, adj, det
+        torch.cuda.empty_cache()
+    ctx.close()
+    d4 = res["n4"]
+    line = {"metric": "4x4 determinant+adjugate matrices/s", "value": d4["matrices_per_s"],
+            "unit": "matrices/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": d4["avg_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "2^24 random 4x4 FP64 matrices (also n = 2, 3; n = 16 by LU)"},
+            "roofline": {"bound": "hbm", "achieved": d4["GBps"], "peak": PEAKS["hbm_GBps"], "unit": "GB/s",
+                         "frac": d4["GBps"] / PEAKS["hbm_GBps"], "traffic": None, "kernel": "det_adj_small<4>"},
+            "sizes": res}
+    print(json.dumps(line))
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: under a hardware-counter
     profile its FETCH_SIZE / WRITE_SIZE give the factor that turns those
@@ -462,6 +506,12 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "det":
+        if a.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        main_det(a)
         return
     if a.workload == "large":
         if a.gpus != 1:

@@ -213,6 +213,21 @@ qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable);
  * device).  QMK_NOT_SET before the first screened evaluation. */
 qmk_status qmk_get_screening_density(qmk_ctx ctx, double* active_fraction);
 
+/* Determinant and adjugate of a batch of small matrices (Section 3.4: the
+ * inverse is adj(A) / det(A); determinant and adjugate are returned
+ * together because the electron gradients of a Slater determinant need
+ * adj(A) without the division):
+ *   a    device FP64 [batch][n][n], row-major
+ *   det  device FP64 [batch]
+ *   adj  device FP64 [batch][n][n], adj(A) = transpose of the cofactor matrix
+ * 1 <= n <= 4: explicit cofactors (exact also for singular matrices).
+ * 5 <= n <= 32: LU with partial pivoting, adj = det * A^{-1}; a singular
+ * matrix gives det = 0 and a non-finite adjugate.  batch = 0 does nothing
+ * (the pointers may then be NULL).  Runs on the context's device and the
+ * given stream; uses no other context state. */
+qmk_status qmk_det_adj(qmk_ctx ctx, int64_t n, int64_t batch, const double* a, double* det, double* adj,
+                       void* hip_stream);
+
 /* Adjoint of L = sum(W * mo_vgl) for the current points (Section 3.6 and
  * Section 3.5 motivate these derivatives; the nuclei carry their shells
  * rigidly, basis parameters are fixed):
@@ -245,7 +260,8 @@ enum {
   QMK_KERNEL_DENSITY = 6,    /* MO values squared and summed (density) */
   QMK_KERNEL_CUSP = 7,       /* MO cusp correction                     */
   QMK_KERNEL_SORT = 8,       /* point sort of the screened contraction */
-  QMK_KERNEL_CLASSES = 9
+  QMK_KERNEL_DET = 9,        /* determinants and adjugates             */
+  QMK_KERNEL_CLASSES = 10
 };
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);

@@ -295,3 +295,24 @@ def mo_vgl_cusp(sys_, charge, r_cusp, points: Optional[np.ndarray] = None, B: fl
             poly[:, 4] = p2 + 2.0 * p1 / ri
         mo[inside] += poly - phis
     return mo
+
+
+def det_adj(a: np.ndarray):
+    """Determinant and adjugate of every matrix of a [..., n, n] (Section 3.4:
+    adj(A) is the transpose of the cofactor matrix, A^-1 = adj(A) / det(A)).
+    The adjugate follows the definition: adj_ji = (-1)^(i+j) times the
+    determinant of A without row i and column j.  Determinants come from
+    numpy's LU routine (a library step)."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[-1]
+    flat = a.reshape(-1, n, n)
+    det = np.linalg.det(flat)
+    adj = np.empty_like(flat)
+    if n == 1:
+        adj[:] = 1.0
+    else:
+        for i in range(n):
+            for j in range(n):
+                minor = np.delete(np.delete(flat, i, axis=1), j, axis=2)
+                adj[:, j, i] = (-1.0) ** (i + j) * np.linalg.det(minor)
+    return det.reshape(a.shape[:-2]), adj.reshape(a.shape)

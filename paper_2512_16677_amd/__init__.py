@@ -47,13 +47,13 @@ EXPORTED = [
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
     "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp", "qmk_set_screening",
-    "qmk_get_screening_density",
+    "qmk_get_screening_density", "qmk_det_adj",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
     "qmk_get_tile_count", "qmk_set_tile",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
-KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp", "sort"]
+KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp", "sort", "det"]
 
 _lib = None
 
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "qmk_set_mo_cusp": ([P, I64, P, P], I32),
         "qmk_set_screening": ([P, I32], I32),
         "qmk_get_screening_density": ([P, P], I32),
+        "qmk_det_adj": ([P, I64, I64, P, P, P, P], I32),
         "qmk_mo_vgl_adjoint": ([P, P, I32, P, P, P, P], I32),
         "qmk_get_launch_count": ([P, P], I32),
         "qmk_set_timing": ([P, I32], I32),
@@ -293,6 +294,20 @@ class Context:
         v = ctypes.c_double()
         self._check(self._lib.qmk_get_screening_density(self._h, ctypes.byref(v)))
         return v.value
+
+    def det_adj(self, a, stream=None):
+        """Determinants and adjugates of a CUDA float64 tensor [..., n, n]:
+        returns (det [...], adj [..., n, n])."""
+        import torch
+        if not (a.is_cuda and a.dtype == torch.float64 and a.dim() >= 2 and a.shape[-1] == a.shape[-2]):
+            raise ValueError("a must be a CUDA float64 tensor [..., n, n]")
+        a = a.contiguous()
+        n = a.shape[-1]
+        batch = a.numel() // (n * n)
+        det = torch.empty(a.shape[:-2], dtype=torch.float64, device=a.device)
+        adj = torch.empty_like(a)
+        self._check(self._lib.qmk_det_adj(self._h, n, batch, _ptr(a), _ptr(det), _ptr(adj), _stream(stream)))
+        return det, adj
 
     def get_mo_value(self, out=None, dtype=None, stream=None):
         """MO values only: CUDA tensor [walk, elec, mo]."""

@@ -936,6 +936,22 @@ qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
   return QMK_OK;
 }
 
+qmk_status qmk_det_adj(qmk_ctx ctx, int64_t n, int64_t batch, const double* a, double* det, double* adj,
+                       void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (n < 1 || n > 32) return bad_arg(ctx, 2, "n must be in 1..32");
+  if (batch < 0) return bad_arg(ctx, 3, "batch must be >= 0");
+  if (batch == 0) return QMK_OK;  // nothing to do; the buffers may be NULL
+  if (!a) return bad_arg(ctx, 4, "NULL");
+  if (!det) return bad_arg(ctx, 5, "NULL");
+  if (!adj) return bad_arg(ctx, 6, "NULL");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  LaunchTimer lt(ctx, QMK_KERNEL_DET, s);
+  QMK_HIP(ctx, launch_det_adj(static_cast<int>(n), batch, a, det, adj, s), "determinant / adjugate");
+  return QMK_OK;
+}
+
 qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable) {
   QMK_CHECK_CTX(ctx);
   if (enable != 0 && enable != 1) return bad_arg(ctx, 2, "enable must be 0 or 1");

@@ -220,6 +220,9 @@ hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_
 // sorted point i.  key, counts are scratch of P and n_nuc + 1 entries.
 hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64_t n_nuc,
                               int32_t* key, int32_t* counts, int32_t* perm, hipStream_t s);
+// Determinants det[b] and adjugates adj[b] (row-major n x n) of a batch of
+// row-major n x n FP64 matrices, 1 <= n <= 32.
+hipError_t launch_det_adj(int n, int64_t batch, const double* A, double* det, double* adj, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // Density product (FP64 or FP32 tile cfg): partial row sums of
 // occ[j] D(i, j)^2 per (N tile, wave) slot; see gemm_body.
