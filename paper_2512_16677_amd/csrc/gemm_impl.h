@@ -329,7 +329,9 @@ __global__ void reduce_splits_kernel(const double* __restrict__ ws, int64_t nz, 
   X(6, 2, 2, 4, 4, 32)   \
   X(7, 2, 2, 4, 3, 16)   \
   X(8, 2, 1, 5, 5, 16)   \
-  X(9, 4, 1, 2, 5, 32)
+  X(9, 4, 1, 2, 5, 32)   \
+  X(10, 2, 2, 5, 5, 16)  \
+  X(11, 4, 1, 5, 5, 16)
 
 constexpr TileCfg kTiles[] = {
 #define QMK_TILE_ENTRY(id, wgm, wgn, tm, tn, bk) {wgm, wgn, tm, tn, bk},
