@@ -427,20 +427,43 @@ def main_large(a):
             if screened:
                 out[key]["sort_ms"] = t["sort"]["ms"] / max(1, t["sort"]["launches"])
                 out[key]["screening_density"] = ctx.screening_density()
+            # forward + adjoint of sum(W * mo_vgl)
+            w = torch.randn((s.walk_num, s.elec_num, 5, N), generator=g, device=dev, dtype=dt)
+            for i in range(a.warmup):
+                ctx.set_point(r0 if i % 2 == 0 else r1)
+                ctx.get_mo_vgl(out=mo)
+                ctx.adjoint(w)
+            torch.cuda.synchronize()
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            for i in range(a.steps):
+                ctx.set_point(r0 if i % 2 == 0 else r1)
+                ctx.get_mo_vgl(out=mo)
+                ctx.adjoint(w)
+            torch.cuda.synchronize()
+            ms2 = (time.perf_counter() - t0) * 1e3 / a.steps
+            t = ctx.timing()
+            out[key]["fwd_adjoint_ms"] = ms2
+            out[key]["fwd_adjoint_e_evals_per_s"] = P / (ms2 * 1e-3)
+            out[key]["per_kernel_ms"] = {k: v["ms"] / v["launches"] for k, v in t.items() if v["launches"]}
+            del w
+            torch.cuda.empty_cache()
         if "screened" in out:
             out["forward_speedup"] = out["dense"]["forward_ms"] / out["screened"]["forward_ms"]
+            out["fwd_adjoint_speedup"] = out["dense"]["fwd_adjoint_ms"] / out["screened"]["fwd_adjoint_ms"]
         out["mo_dense_TFLOPs"] = 2.0 * 5 * P * K * N / (out["dense"]["mo_ms"] * 1e-3) / 1e12
         ctx.close()
         del mo
         torch.cuda.empty_cache()
         res[mode] = out
-    line = {"metric": "mo_vgl electron-evals/s (forward), dense vs screened contraction",
-            "value": res["fp64"]["screened"]["e_evals_per_s"], "unit": "e-evals/s", "n_gpus": 1,
-            "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["fp64"]["screened"]["forward_ms"],
+    line = {"metric": "mo_vgl electron-evals/s (fwd+adjoint), dense vs screened contraction",
+            "value": res["fp64"]["screened"]["fwd_adjoint_e_evals_per_s"], "unit": "e-evals/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["fp64"]["screened"]["fwd_adjoint_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
             "config": {"workload": f"ch300_7500ao: 150 C + 150 H in a 35-bohr cube, {K} AOs, {N} MOs, "
-                                   f"{s.elec_num} electrons, 64 walkers; forward", "points_per_step": P},
+                                   f"{s.elec_num} electrons, 64 walkers; forward + adjoint",
+                       "points_per_step": P},
             "modes": res}
     print(json.dumps(line))
 

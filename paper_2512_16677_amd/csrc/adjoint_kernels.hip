@@ -107,11 +107,14 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
   const int64_t wave = p >> 6;
   const int lane = threadIdx.x & 63;
   const bool valid = p < pts.P;
+  // with a point order (screened adjoint), point p of G-bar is point perm[p]
+  // of the caller's coordinates and electron gradients
+  const int64_t src = valid && pts.perm ? static_cast<int64_t>(pts.perm[p]) : p;
   double rx = 0.0, ry = 0.0, rz = 0.0;
   if (valid) {
-    rx = pts.coord[p * pts.s_pt];
-    ry = pts.coord[p * pts.s_pt + pts.s_ax];
-    rz = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
+    rx = pts.coord[src * pts.s_pt];
+    ry = pts.coord[src * pts.s_pt + pts.s_ax];
+    rz = pts.coord[src * pts.s_pt + 2 * pts.s_ax];
   }
   const GT* gb_p = gbar + p;
   const double T = t.T;
@@ -158,7 +161,7 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
     }
   }
   if (valid) {
-    double* o = elec_out + gy * elec_group_stride + p * 3;
+    double* o = elec_out + gy * elec_group_stride + src * 3;
     o[0] = ex;
     o[1] = ey;
     o[2] = ez;

@@ -365,8 +365,11 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s) {
     ctx->nuc_xyz_version = ctx->geom_version;
   }
   QMK_HIP(ctx, ctx->d_sort_key.ensure(static_cast<size_t>(P) * 4), "alloc sort keys");
-  QMK_HIP(ctx, ctx->d_sort_counts.ensure(static_cast<size_t>(nn + 1) * 4), "alloc sort counts");
+  QMK_HIP(ctx, ctx->d_sort_key2.ensure(static_cast<size_t>(P) * 4), "alloc sorted keys");
+  QMK_HIP(ctx, ctx->d_sort_idx.ensure(static_cast<size_t>(P) * 4), "alloc sort indices");
   QMK_HIP(ctx, ctx->d_perm.ensure(static_cast<size_t>(P) * 4), "alloc permutation");
+  const size_t scratch = std::max<size_t>(sort_scratch_bytes(P, nn), 16);
+  QMK_HIP(ctx, ctx->d_sort_scratch.ensure(scratch), "alloc sort scratch");
   ctx->act_words = (Kp / kSparseChunk + 31) / 32;
   const int64_t act_n = (Pp / 64) * ctx->act_words;
   QMK_HIP(ctx, ctx->d_act.ensure(static_cast<size_t>(act_n) * 4), "alloc activity bitmap");
@@ -383,7 +386,8 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s) {
   {
     LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
     QMK_HIP(ctx, launch_sort_points(pa, ctx->d_nuc_xyz.as<double>(), nn, ctx->d_sort_key.as<int32_t>(),
-                                    ctx->d_sort_counts.as<int32_t>(), ctx->d_perm.as<int32_t>(), s),
+                                    ctx->d_sort_key2.as<int32_t>(), ctx->d_sort_idx.as<int32_t>(),
+                                    ctx->d_perm.as<int32_t>(), ctx->d_sort_scratch.p, scratch, s),
             "sort points");
     QMK_HIP(ctx, launch_fill_u32(ctx->d_act.as<uint32_t>(), act_n, 0u, s), "clear activity bitmap");
   }
@@ -1313,12 +1317,29 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   DeviceGuard g(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
-  if ((st = provide_ao(ctx, s)) != QMK_OK) return st;
+  // screened adjoint: every product in sorted point order (Section 3.2)
+  const bool scr = ctx->sparse && ctx->mode != QMK_MIXED_BF16X3;
+  if ((st = scr ? provide_ao_sorted(ctx, s) : provide_ao(ctx, s)) != QMK_OK) return st;
   const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
-  const int64_t Pp = ctx->ao_Pp, Kp = ctx->Kp, Np = ctx->Np;
+  const int64_t Pp = scr ? ctx->aos_Pp : ctx->ao_Pp, Kp = ctx->Kp, Np = ctx->Np;
+  const void* ao_arr = scr ? ctx->aos.p : ctx->ao.p;
+  auto screen = [&](GemmArgs& ga) {
+    ga.act = ctx->d_act.as<uint32_t>();
+    ga.act_words = ctx->act_words;
+  };
   const int w32 = w_dtype == QMK_F32;
   const int f32 = ctx->f32_storage() ? 1 : 0;
   const Prec prec = gemm_prec(ctx);
+  if (scr) {
+    // W in the sorted point order, once, so that both products read it with
+    // their ordinary loaders
+    const int64_t row_bytes = 5 * N * (w32 ? 4 : 8);
+    QMK_HIP(ctx, ctx->w_sorted.ensure(static_cast<size_t>(P * row_bytes)), "alloc sorted W");
+    LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
+    QMK_HIP(ctx, launch_gather_rows(w, ctx->d_perm.as<int32_t>(), P, row_bytes, ctx->w_sorted.p, s),
+            "sort W");
+    w = ctx->w_sorted.p;
+  }
 
   if (d_elec || d_nucl) {
     // Gbar[k][c][p] = sum_n W[p][c][n] C[n][k]
@@ -1329,17 +1350,20 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ctx->gbar_Kp = Kp;
       ctx->gbar_f32 = f32;
     }
-    const GemmArgs ga = gbar_args(prec, w, w32, ctx->d_C.p, ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p,
-                                  ctx->gbar.p, P, Pp, K, Kp, N, Np);
-    const GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
+    GemmArgs ga = gbar_args(prec, w, w32, ctx->d_C.p, ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p, ctx->gbar.p, P,
+                            Pp, K, Kp, N, Np);
+    if (scr) screen(ga);
+    GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
+    pb.sparse = scr ? 1 : 0;
+    auto launch = [&](int c) {
+      return scr ? launch_gemm_screened_adj(GemmKind::kGbar, prec, c, ga, w32, s)
+                 : launch_gemm_typed(GemmKind::kGbar, prec, c, ga, w32, f32, s);
+    };
     int cfg = 0;
-    if ((st = pick_tile(ctx, pb, s, [&](int c) {
-           return launch_gemm_typed(GemmKind::kGbar, prec, c, ga, w32, f32, s);
-         }, &cfg)) != QMK_OK)
-      return st;
+    if ((st = pick_tile(ctx, pb, s, launch, &cfg)) != QMK_OK) return st;
     {
       LaunchTimer lt(ctx, QMK_KERNEL_GBAR, s);
-      QMK_HIP(ctx, launch_gemm_typed(GemmKind::kGbar, prec, cfg, ga, w32, f32, s), "Gbar product");
+      QMK_HIP(ctx, launch(cfg), "Gbar product");
     }
 
     const int64_t n_waves = (P + 255) / 256 * 4;
@@ -1354,7 +1378,9 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     int64_t nw = 0;
     {
       LaunchTimer lt(ctx, QMK_KERNEL_AO_ADJOINT, s);
-      QMK_HIP(ctx, launch_ao_adjoint(ctx->tab, point_args(ctx), ctx->gbar.p, f32, 5 * Pp, Pp, elec_out,
+      PointArgs pa = point_args(ctx);
+      if (scr) pa.perm = ctx->d_perm.as<int32_t>();
+      QMK_HIP(ctx, launch_ao_adjoint(ctx->tab, pa, ctx->gbar.p, f32, 5 * Pp, Pp, elec_out,
                                      gstride, ctx->ws_nuc.as<double>(), &nw, s),
               "AO adjoint kernel");
     }
@@ -1406,7 +1432,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ga.sAl = 5 * N;
       ga.oAc = N;
       ga.oAs = chunk * 5 * N;
-      ga.B = ctx->ao.p;
+      ga.B = ao_arr;
       ga.sBl = 1;
       ga.sBj = 5 * Pp;
       ga.oBc = Pp;
@@ -1423,16 +1449,19 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ga.nbatch = 5;
       ga.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
       ga.map_slab = 1;
+      if (scr) screen(ga);
       hipError_t e;
       {
         LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);
-        e = launch_gemm_typed(GemmKind::kDcoef, prec, cfg, ga, w32, 0, s);
+        e = scr ? launch_gemm_screened_adj(GemmKind::kDcoef, prec, cfg, ga, w32, s)
+                : launch_gemm_typed(GemmKind::kDcoef, prec, cfg, ga, w32, 0, s);
       }
       if (e != hipSuccess) return e;
       LaunchTimer lt(ctx, QMK_KERNEL_REDUCE, s);
       return launch_reduce_splits(ctx->ws_dc.as<double>(), 5 * nsplit, N, K, Kp, Np * Kp, d_coef, K, s);
     };
-    const GemmProblem pb{GemmKind::kDcoef, prec, w32, 0, N, K, P};
+    GemmProblem pb{GemmKind::kDcoef, prec, w32, 0, N, K, P};
+    pb.sparse = scr ? 1 : 0;
     int cfg = 0;
     if ((st = pick_tile(ctx, pb, s, enqueue, &cfg)) != QMK_OK) return st;
     QMK_HIP(ctx, enqueue(cfg), "dC product");

@@ -58,6 +58,12 @@ struct GemmSmem {
 // EPI = 2 is the screened forward product: the K loop visits only the
 // stages listed in stage_list (the rest of A is zero for every row of the
 // tile), and row i of D is stored at row perm[i].
+// EPI = 3 is the screened G-bar product (rows: AOs, columns: sorted points;
+// W already in sorted point order): a tile whose AO chunks are inactive for
+// all of its point blocks is stored as zeros without running the K loop.
+// EPI = 4 is the screened dC product (K runs over sorted points): the K
+// stages whose 64-point block has no active chunk among the tile's N
+// columns are skipped.
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
           int BK, bool A_I, bool B_J, int EPI = 0>
 __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int z,
@@ -151,18 +157,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  const int64_t nk = EPI == 2 ? n_stages : (Ls + BK - 1) / BK;
-  auto l0_of = [&](int64_t t) -> int64_t {
-    return (EPI == 2 ? static_cast<int64_t>(stage_list[t]) : t) * BK;
-  };
-  if (nk > 0) {
-    load(l0_of(0));
-    stash(0);
-  }
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int buf = static_cast<int>(kt & 1);
-    if (kt + 1 < nk) load(l0_of(kt + 1));
+  auto mma = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4), ci = lane & 15;
@@ -176,8 +171,66 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::op(fa[a], fb[b], acc[a][b]);
     }
-    if (kt + 1 < nk) stash(buf ^ 1);
+  };
+  if constexpr (EPI == 4) {
+    // K stages of sorted points: a stage is active if its 64-point block has
+    // an active chunk among the AO columns [j0, j0 + BN) of this tile
+    const int64_t nk = (Ls + BK - 1) / BK;
+    const int64_t c0 = j0 / kSparseChunk, c1 = (min(j0 + BN, g.N) - 1) / kSparseChunk;
+    const int64_t w0 = c0 >> 5, w1 = c1 >> 5;
+    const uint32_t m0 = (~0u << (c0 & 31)) & (w1 == w0 ? (~0u >> (31 - (c1 & 31))) : ~0u);
+    const uint32_t m1 = w1 == w0 ? 0u : (~0u >> (31 - (c1 & 31)));
+    const int64_t p0 = static_cast<int64_t>(s) * g.Lchunk;
+    auto next = [&](int64_t t) -> int64_t {
+      for (; t < nk; ++t) {
+        const uint32_t* w = g.act + ((p0 + t * BK) >> 6) * g.act_words;
+        if ((w[w0] & m0) | (w1 != w0 ? (w[w1] & m1) : 0u)) break;
+      }
+      return t;
+    };
+    int64_t cur = next(0);
+    int buf = 0;
+    if (cur < nk) {
+      load(cur * BK);
+      stash(0);
+    }
     __syncthreads();
+    while (cur < nk) {
+      const int64_t nxt = next(cur + 1);
+      if (nxt < nk) load(nxt * BK);
+      mma(buf);
+      if (nxt < nk) stash(buf ^ 1);
+      __syncthreads();
+      cur = nxt;
+      buf ^= 1;
+    }
+  } else {
+    int64_t nk = EPI == 2 ? n_stages : (Ls + BK - 1) / BK;
+    if constexpr (EPI == 3) {
+      // output tile (AO rows [i0, i0 + BM), sorted points [j0, j0 + BN)):
+      // skip the product if no point block of it has an active chunk there
+      const int64_t c0 = i0 / kSparseChunk, c1 = (min(i0 + BM, g.M) - 1) / kSparseChunk;
+      const int64_t b0 = j0 >> 6, b1 = (min(j0 + BN, g.N) - 1) >> 6;
+      bool on = false;
+      for (int64_t b = b0; b <= b1 && !on; ++b)
+        for (int64_t c = c0; c <= c1 && !on; ++c) on = (g.act[b * g.act_words + (c >> 5)] >> (c & 31)) & 1u;
+      if (!on) nk = 0;
+    }
+    auto l0_of = [&](int64_t t) -> int64_t {
+      return (EPI == 2 ? static_cast<int64_t>(stage_list[t]) : t) * BK;
+    };
+    if (nk > 0) {
+      load(l0_of(0));
+      stash(0);
+    }
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int buf = static_cast<int>(kt & 1);
+      if (kt + 1 < nk) load(l0_of(kt + 1));
+      mma(buf);
+      if (kt + 1 < nk) stash(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   if constexpr (EPI == 1) {
@@ -285,12 +338,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_density_kernel(GemmArgs g
 }
 
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
-          int BK, bool A_I, bool B_J>
+          int BK, bool A_I, bool B_J, int EPI = 0>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_kernel(GemmArgs g, int nM, int nN) {
   __shared__ GemmSmem<T, 16 * WGM * TM, 16 * WGN * TN, BK> sm;
   int mt, nt, z;
   if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
-  gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>(g, mt, nt, z, sm);
+  gemm_body<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J, EPI>(g, mt, nt, z, sm);
 }
 
 // Persistent form: the grid walks a list of (job, M tile, N tile, z).
@@ -341,13 +394,13 @@ constexpr TileCfg kTiles[] = {
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 template <typename T, typename TA, typename TB, typename TD, int WGM, int WGN, int TM, int TN,
-          int BK, bool A_I, bool B_J>
+          int BK, bool A_I, bool B_J, int EPI = 0>
 hipError_t run_tile(const GemmArgs& g, hipStream_t s) {
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
   if (nM <= 0 || nN <= 0) return hipSuccess;
   const dim3 grid = grid_of(g, nM, nN);
-  hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J>), grid,
+  hipLaunchKernelGGL((gemm_kernel<T, TA, TB, TD, WGM, WGN, TM, TN, BK, A_I, B_J, EPI>), grid,
                      dim3(64 * WGM * WGN), 0, s, g, nM, nN);
   return hipGetLastError();
 }
@@ -380,12 +433,12 @@ hipError_t run_persist(int cfg, const PersistLaunch& pl, hipStream_t s) {
   }
 }
 
-template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J>
+template <typename T, typename TA, typename TB, typename TD, bool A_I, bool B_J, int EPI = 0>
 hipError_t run(int cfg, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
 #define QMK_TILE_CASE(id, wgm, wgn, tm, tn, bk) \
   case id:                                      \
-    return run_tile<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J>(g, s);
+    return run_tile<T, TA, TB, TD, wgm, wgn, tm, tn, bk, A_I, B_J, EPI>(g, s);
     QMK_TILE_LIST(QMK_TILE_CASE)
 #undef QMK_TILE_CASE
     default:

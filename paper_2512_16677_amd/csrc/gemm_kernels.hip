@@ -74,6 +74,24 @@ hipError_t gemm_unit_f32_dc(int cfg, const GemmArgs* g, const PersistLaunch* pl,
   return alt ? run<float, float, float, double, true, false>(cfg, *g, s) : run<float, double, float, double, true, false>(cfg, *g, s);
 }
 #endif
+#if QMK_GEMM_UNIT == 9
+// Screened adjoint products (points in sorted order; see gemm_body EPI 3, 4).
+hipError_t gemm_unit_screened_adj(GemmKind kind, int cfg, const GemmArgs* g, Prec prec, int w32,
+                                  hipStream_t s) {
+  if (kind == GemmKind::kGbar) {
+    if (prec == Prec::kF64)
+      return w32 ? run<double, double, float, double, true, false, 3>(cfg, *g, s)
+                 : run<double, double, double, double, true, false, 3>(cfg, *g, s);
+    return w32 ? run<float, float, float, float, true, false, 3>(cfg, *g, s)
+               : run<float, float, double, float, true, false, 3>(cfg, *g, s);
+  }
+  if (prec == Prec::kF64)
+    return w32 ? run<double, float, double, double, true, false, 4>(cfg, *g, s)
+               : run<double, double, double, double, true, false, 4>(cfg, *g, s);
+  return w32 ? run<float, float, float, double, true, false, 4>(cfg, *g, s)
+             : run<float, double, float, double, true, false, 4>(cfg, *g, s);
+}
+#endif
 #if QMK_GEMM_UNIT == 8
 hipError_t gemm_unit_sparse(int cfg, const GemmArgs* g, Prec prec, int o32, hipStream_t s) {
   if (prec == Prec::kF64)
@@ -88,7 +106,7 @@ hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t 
 #endif
 #else
 // Products of each (precision, kind) are instantiated in their own
-// translation unit (this file compiled with QMK_GEMM_UNIT = 1..8) so that
+// translation unit (this file compiled with QMK_GEMM_UNIT = 1..9) so that
 // they build in parallel; the unit without QMK_GEMM_UNIT holds the tables
 // and the dispatch.
 hipError_t gemm_unit_f64_fwd(int cfg, const GemmArgs* g, const PersistLaunch* pl, int w32, int o32,
@@ -106,6 +124,8 @@ hipError_t gemm_unit_f32_dc(int cfg, const GemmArgs* g, const PersistLaunch* pl,
 
 hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t s);
 hipError_t gemm_unit_sparse(int cfg, const GemmArgs* g, Prec prec, int o32, hipStream_t s);
+hipError_t gemm_unit_screened_adj(GemmKind kind, int cfg, const GemmArgs* g, Prec prec, int w32,
+                                  hipStream_t s);
 namespace {
 hipError_t unit_dispatch(GemmKind kind, Prec prec, int cfg, const GemmArgs* g, const PersistLaunch* pl,
                          int w32, int o32, hipStream_t s) {
@@ -146,6 +166,14 @@ size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
 hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s) {
   if (prec == Prec::kBF16x3 || cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   return gemm_unit_sparse(cfg, &g, prec, out_is_f32, s);
+}
+
+hipError_t launch_gemm_screened_adj(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
+                                    hipStream_t s) {
+  if (prec == Prec::kBF16x3 || cfg < 0 || cfg >= kNumTiles ||
+      (kind != GemmKind::kGbar && kind != GemmKind::kDcoef))
+    return hipErrorInvalidValue;
+  return gemm_unit_screened_adj(kind, cfg, &g, prec, w_is_f32, s);
 }
 
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s) {

@@ -214,16 +214,27 @@ struct TileCfg {
 int gemm_num_tiles(Prec prec);
 TileCfg gemm_tile(Prec prec, int cfg);
 size_t gemm_tile_lds_bytes(Prec prec, int cfg);
+// Screened adjoint products in sorted point order (kind kGbar or kDcoef;
+// FP64 or FP32 tile cfg).
+hipError_t launch_gemm_screened_adj(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
+                                    hipStream_t s);
 // Screened forward product (FP64 or FP32 tile cfg; D in FP64 or FP32).
 hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s);
-// Point sort by nearest nucleus (counting sort): perm[i] = original index of
-// sorted point i.  key, counts are scratch of P and n_nuc + 1 entries.
-hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64_t n_nuc,
-                              int32_t* key, int32_t* counts, int32_t* perm, hipStream_t s);
+// Point sort by nearest nucleus (stable radix sort): perm[i] = original
+// index of sorted point i.  key, key_sorted, index: P entries each; scratch
+// of sort_scratch_bytes(P, n_nuc) bytes.
+size_t sort_scratch_bytes(int64_t P, int64_t n_nuc);
+hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64_t n_nuc, int32_t* key,
+                              int32_t* key_sorted, int32_t* index, int32_t* perm, void* scratch,
+                              size_t scratch_bytes, hipStream_t s);
 // Determinants det[b] and adjugates adj[b] (row-major n x n) of a batch of
 // row-major n x n FP64 matrices, 1 <= n <= 32.
 hipError_t launch_det_adj(int n, int64_t batch, const double* A, double* det, double* adj, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+// dst row q = src row perm[q] for q < rows (rows of row_bytes bytes, a
+// multiple of 4).
+hipError_t launch_gather_rows(const void* src, const int32_t* perm, int64_t rows, int64_t row_bytes, void* dst,
+                              hipStream_t s);
 // Density product (FP64 or FP32 tile cfg): partial row sums of
 // occ[j] D(i, j)^2 per (N tile, wave) slot; see gemm_body.
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s);

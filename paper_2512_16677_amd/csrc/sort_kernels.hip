@@ -1,9 +1,12 @@
 // Point ordering for the screened contraction (QMCkl paper, Section 3.2: the
 // sparsity of the AOs reduces the cost of the MO product).  On MFMA tiles the
 // sparsity is usable only if the points of a tile are close in space: points
-// are counting-sorted by their nearest nucleus, so that a 64-point block sees
-// the AOs of one neighbourhood.  Points of one nucleus keep no particular
-// order among themselves (atomic slots); the product does not depend on it.
+// are sorted by their nearest nucleus, so that a 64-point block sees the AOs
+// of one neighbourhood.  The sort is a stable radix sort of (nearest
+// nucleus, point index) pairs, so the order -- and with it every sum over
+// sorted points -- is the same on every run.
+#include <hipcub/hipcub.hpp>
+
 #include "qmk_internal.h"
 
 namespace qmk {
@@ -11,7 +14,7 @@ namespace {
 
 __global__ __launch_bounds__(256) void nearest_nucleus_kernel(PointArgs pts, const double* __restrict__ nuc,
                                                               int64_t n_nuc, int32_t* __restrict__ key,
-                                                              int32_t* __restrict__ counts) {
+                                                              int32_t* __restrict__ index) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= pts.P) return;
   const double x = pts.coord[p * pts.s_pt], y = pts.coord[p * pts.s_pt + pts.s_ax],
@@ -27,40 +30,18 @@ __global__ __launch_bounds__(256) void nearest_nucleus_kernel(PointArgs pts, con
     }
   }
   key[p] = arg;
-  atomicAdd(counts + arg, 1);
+  index[p] = static_cast<int32_t>(p);
 }
 
-// Exclusive prefix sum of counts[0..n) in place (one workgroup; the sums of
-// 256-entry pieces are carried serially).
-__global__ __launch_bounds__(256) void scan_counts_kernel(int32_t* __restrict__ counts, int64_t n) {
-  __shared__ int32_t part[256];
-  __shared__ int32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < n; base += 256) {
-    const int64_t i = base + threadIdx.x;
-    const int32_t v = i < n ? counts[i] : 0;
-    part[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int32_t t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-      __syncthreads();
-      part[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < n) counts[i] = carry + part[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 255) carry += part[255];
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256) void scatter_points_kernel(const int32_t* __restrict__ key, int64_t P,
-                                                             int32_t* __restrict__ cursor,
-                                                             int32_t* __restrict__ perm) {
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  perm[atomicAdd(cursor + key[p], 1)] = static_cast<int32_t>(p);
+// dst row q = src row perm[q]; rows of `row` elements of `esz` bytes, moved
+// as 4-byte words (row * esz is a multiple of 4).
+__global__ __launch_bounds__(256) void gather_rows_kernel(const uint32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ perm, int64_t rows,
+                                                          int64_t words, uint32_t* __restrict__ dst) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= rows * words) return;
+  const int64_t q = e / words, x = e - q * words;
+  dst[e] = src[static_cast<int64_t>(perm[q]) * words + x];
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -70,24 +51,46 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p,
 
 }  // namespace
 
+hipError_t launch_gather_rows(const void* src, const int32_t* perm, int64_t rows, int64_t row_bytes, void* dst,
+                              hipStream_t s) {
+  if (rows <= 0 || row_bytes % 4 != 0) return rows <= 0 ? hipSuccess : hipErrorInvalidValue;
+  const int64_t words = row_bytes / 4, n = rows * words;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const uint32_t*>(src), perm, rows, words, static_cast<uint32_t*>(dst));
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 
+static int key_bits(int64_t n_nuc) {
+  int b = 1;
+  while ((int64_t{1} << b) < n_nuc) ++b;
+  return b;
+}
+
+size_t sort_scratch_bytes(int64_t P, int64_t n_nuc) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, static_cast<const int32_t*>(nullptr),
+                                           static_cast<int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                                           static_cast<int32_t*>(nullptr), static_cast<int>(P), 0,
+                                           key_bits(n_nuc));
+  return bytes;
+}
+
 hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64_t n_nuc, int32_t* key,
-                              int32_t* counts, int32_t* perm, hipStream_t s) {
+                              int32_t* key_sorted, int32_t* index, int32_t* perm, void* scratch,
+                              size_t scratch_bytes, hipStream_t s) {
   if (pts.P <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(counts), n_nuc, 0u, s);
+  hipLaunchKernelGGL(nearest_nucleus_kernel, dim3(static_cast<unsigned>((pts.P + 255) / 256)), dim3(256), 0, s,
+                     pts, nuc_xyz, n_nuc, key, index);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid(static_cast<unsigned>((pts.P + 255) / 256));
-  hipLaunchKernelGGL(nearest_nucleus_kernel, grid, dim3(256), 0, s, pts, nuc_xyz, n_nuc, key, counts);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(256), 0, s, counts, n_nuc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(scatter_points_kernel, grid, dim3(256), 0, s, key, pts.P, counts, perm);
-  return hipGetLastError();
+  return hipcub::DeviceRadixSort::SortPairs(scratch, scratch_bytes, key, key_sorted, index, perm,
+                                            static_cast<int>(pts.P), 0, key_bits(n_nuc), s);
 }
 
 }  // namespace qmk
