@@ -204,8 +204,14 @@ qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
  * Only exact zeros (AOs beyond the exponent cutoff) are skipped, so the
  * result equals the dense product's bit for bit (up to the sign of a zero).
  * FP64 and FP32 modes; in the BF16x3 mode the dense product runs.  At most
- * 16384 AOs (QMK_UNSUPPORTED above).  The other calls (AO values, MO values,
- * density, adjoint) keep the dense path.  enable = 0 restores the default. */
+ * 16384 AOs (QMK_UNSUPPORTED above).  qmk_mo_vgl_adjoint screens too: W is
+ * reordered once into the sorted point order, G-bar tiles whose AOs are zero
+ * at all of their points are stored as zeros, and dC skips point stages with
+ * no non-zero AO in its columns; electron gradients equal the dense path bit
+ * for bit, dL/dC and nuclear gradients agree to rounding (sums over points in
+ * sorted order; the sort is stable, so runs repeat bitwise).  AO values, MO
+ * values and the density keep the dense path.  enable = 0 restores the
+ * default. */
 qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable);
 
 /* Fraction of (64-point block, 16-AO chunk) pairs with a non-zero AO in the
