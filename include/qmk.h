@@ -20,7 +20,11 @@
  *   - get_* and adjoint calls write into DEVICE buffers owned by the caller
  *     (for example a torch tensor's data pointer) on the given HIP stream
  *     (NULL = the null stream); they return once the work is enqueued.  The
- *     library never frees caller memory.
+ *     library never frees caller memory.  Every buffer a kernel reads or
+ *     writes must be accessible from the context's GPU: its device memory,
+ *     managed memory, or pinned host memory mapped for the device.  Other
+ *     pointers (pageable host memory) are rejected with
+ *     QMK_INVALID_ARG_BASE + k before any work is enqueued.
  *   - A context is not thread-safe: use one context per host thread, as in
  *     the paper's parallelisation model (Section 2.4).  Contexts are
  *     independent of each other (Section 2.2).

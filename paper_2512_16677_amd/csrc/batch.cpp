@@ -420,11 +420,19 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
   if (!outs) return bfail(b, QMK_INVALID_ARG_BASE + 2, "argument 2: NULL outputs");
   if (dtype != QMK_F64 && dtype != QMK_F32) return bfail(b, QMK_INVALID_ARG_BASE + 3, "argument 3: dtype");
   const size_t n = b->ctxs.size();
-  for (size_t i = 0; i < n; ++i) {
-    if (!outs[i]) return bfail(b, QMK_INVALID_ARG_BASE + 2, "argument 2: NULL output " + std::to_string(i));
-    if (ws && !ws[i]) return bfail(b, QMK_INVALID_ARG_BASE + 4, "argument 4: NULL weights " + std::to_string(i));
-  }
   DeviceGuard guard(b->device);
+  auto dev_ok = [&](const void* p) { return p && device_accessible(p, b->device); };
+  for (size_t i = 0; i < n; ++i) {
+    const std::string at = " " + std::to_string(i) + " (NULL or not memory the device can access)";
+    if (!dev_ok(outs[i])) return bfail(b, QMK_INVALID_ARG_BASE + 2, "argument 2: output" + at);
+    if (ws && !dev_ok(ws[i])) return bfail(b, QMK_INVALID_ARG_BASE + 4, "argument 4: weights" + at);
+    if (ws && d_coefs && d_coefs[i] && !dev_ok(d_coefs[i]))
+      return bfail(b, QMK_INVALID_ARG_BASE + 5, "argument 5: dL/dC" + at);
+    if (ws && d_elecs && d_elecs[i] && !dev_ok(d_elecs[i]))
+      return bfail(b, QMK_INVALID_ARG_BASE + 6, "argument 6: dL/dr" + at);
+    if (ws && d_nucls && d_nucls[i] && !dev_ok(d_nucls[i]))
+      return bfail(b, QMK_INVALID_ARG_BASE + 7, "argument 7: dL/dR" + at);
+  }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const bool own = s == nullptr;
   if (own) {

@@ -60,6 +60,36 @@ qmk_status hip_fail(qmk_ctx ctx, hipError_t e, const char* what) {
 }
 bool valid_ctx(qmk_ctx ctx) { return ctx != nullptr && ctx->magic == kMagic; }
 
+// True if the GPU `device` can read and write p: device memory of that GPU,
+// managed memory, or pinned host memory mapped into the device's address
+// space.  Pageable host memory (or an unknown address) is rejected before
+// any kernel would touch it.
+bool device_accessible(const void* p, int device) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  switch (a.type) {
+    case hipMemoryTypeDevice:
+    case hipMemoryTypeArray:
+      return a.device == device;
+    case hipMemoryTypeManaged:
+    case hipMemoryTypeUnified:
+      return true;
+    case hipMemoryTypeHost:
+      return a.devicePointer != nullptr;
+    default:
+      return false;
+  }
+}
+
+qmk_status check_dev_arg(qmk_ctx ctx, int k, const void* p) {
+  if (!p) return bad_arg(ctx, k, "NULL");
+  if (!device_accessible(p, ctx->device)) return bad_arg(ctx, k, "not memory the device can access");
+  return QMK_OK;
+}
+
 hipEvent_t take_event(qmk_ctx ctx) {
   if (!ctx->event_pool.empty()) {
     hipEvent_t e = ctx->event_pool.back();
@@ -946,10 +976,11 @@ qmk_status qmk_det_adj(qmk_ctx ctx, int64_t n, int64_t batch, const double* a, d
   if (n < 1 || n > 32) return bad_arg(ctx, 2, "n must be in 1..32");
   if (batch < 0) return bad_arg(ctx, 3, "batch must be >= 0");
   if (batch == 0) return QMK_OK;  // nothing to do; the buffers may be NULL
-  if (!a) return bad_arg(ctx, 4, "NULL");
-  if (!det) return bad_arg(ctx, 5, "NULL");
-  if (!adj) return bad_arg(ctx, 6, "NULL");
   DeviceGuard g(ctx->device);
+  qmk_status st;
+  if ((st = check_dev_arg(ctx, 4, a)) != QMK_OK || (st = check_dev_arg(ctx, 5, det)) != QMK_OK ||
+      (st = check_dev_arg(ctx, 6, adj)) != QMK_OK)
+    return st;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   LaunchTimer lt(ctx, QMK_KERNEL_DET, s);
   QMK_HIP(ctx, launch_det_adj(static_cast<int>(n), batch, a, det, adj, s), "determinant / adjugate");
@@ -990,6 +1021,9 @@ qmk_status qmk_set_point(qmk_ctx ctx, char transp, int64_t walk_num, int64_t ele
   if (coord_on_device != 0 && coord_on_device != 1) return bad_arg(ctx, 6, "must be 0 or 1");
   const int64_t n = 3 * walk_num * elec_num;
   if (coord_on_device) {
+    DeviceGuard g(ctx->device);
+    qmk_status st = check_dev_arg(ctx, 5, coord);
+    if (st != QMK_OK) return st;
     ctx->pts = coord;
   } else {
     for (int64_t i = 0; i < n; ++i)
@@ -1076,7 +1110,11 @@ qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, i
 qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                           void* hip_stream) {
   QMK_CHECK_CTX(ctx);
-  if (!out) return bad_arg(ctx, 2, "NULL");
+  {
+    DeviceGuard dg(ctx->device);
+    const qmk_status pst = check_dev_arg(ctx, 2, out);
+    if (pst != QMK_OK) return pst;
+  }
   if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, false);
   if (st != QMK_OK) return st;
@@ -1097,7 +1135,11 @@ qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
 qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                           void* hip_stream) {
   QMK_CHECK_CTX(ctx);
-  if (!out) return bad_arg(ctx, 2, "NULL");
+  {
+    DeviceGuard dg(ctx->device);
+    const qmk_status pst = check_dev_arg(ctx, 2, out);
+    if (pst != QMK_OK) return pst;
+  }
   if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
@@ -1157,7 +1199,11 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
 qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                             void* hip_stream) {
   QMK_CHECK_CTX(ctx);
-  if (!out) return bad_arg(ctx, 2, "NULL");
+  {
+    DeviceGuard dg(ctx->device);
+    const qmk_status pst = check_dev_arg(ctx, 2, out);
+    if (pst != QMK_OK) return pst;
+  }
   if (dtype != QMK_F64 && dtype != QMK_F32) return bad_arg(ctx, 4, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
@@ -1204,7 +1250,11 @@ qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, doub
                            int64_t size_max, void* hip_stream) {
   QMK_CHECK_CTX(ctx);
   if (!occ) return bad_arg(ctx, 2, "NULL");
-  if (!rho) return bad_arg(ctx, 4, "NULL");
+  {
+    DeviceGuard dg(ctx->device);
+    const qmk_status pst = check_dev_arg(ctx, 4, rho);
+    if (pst != QMK_OK) return pst;
+  }
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;
   if (ctx->cusp_on) return fail(ctx, QMK_UNSUPPORTED, "the density with the cusp correction on is not implemented");
@@ -1309,7 +1359,14 @@ qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, doub
 qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, double* d_coef,
                               double* d_elec, double* d_nucl, void* hip_stream) {
   QMK_CHECK_CTX(ctx);
-  if (!w) return bad_arg(ctx, 2, "NULL");
+  {
+    DeviceGuard dg(ctx->device);
+    qmk_status pst = check_dev_arg(ctx, 2, w);
+    if (pst == QMK_OK && d_coef) pst = check_dev_arg(ctx, 4, d_coef);
+    if (pst == QMK_OK && d_elec) pst = check_dev_arg(ctx, 5, d_elec);
+    if (pst == QMK_OK && d_nucl) pst = check_dev_arg(ctx, 6, d_nucl);
+    if (pst != QMK_OK) return pst;
+  }
   if (w_dtype != QMK_F64 && w_dtype != QMK_F32) return bad_arg(ctx, 3, "dtype must be QMK_F64 or QMK_F32");
   qmk_status st = check_ready(ctx, true);
   if (st != QMK_OK) return st;

@@ -187,6 +187,7 @@ qmk_status check_ready(qmk_ctx ctx, bool need_coef);
 PointArgs point_args(qmk_ctx ctx);
 Prec gemm_prec(qmk_ctx ctx);
 bool w_vec_ok(const void* w, int64_t N, int w32);
+bool device_accessible(const void* p, int device);
 // Arguments of the product Gbar[k][c][p] = sum_n W[p][c][n] C[n][k] (the
 // FP64 / FP32 kernels take C as the left operand, the BF16x3 kernel W).
 GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void* Ct_hi,

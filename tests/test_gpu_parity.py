@@ -268,3 +268,31 @@ def test_every_tile_shape_matches_oracle():
             assert e <= 1e-11, (t, k, e)
     assert tried >= 6
     ctx.close()
+
+
+def test_host_buffers_are_rejected_before_any_launch():
+    """Pageable host memory as a buffer argument returns an argument error
+    and enqueues nothing.  Every call also carries a second invalid argument
+    that is checked after the pointer (too small a size, a wrong length, an
+    unknown dtype), so that it would stop before any kernel even if the
+    pointer check let the host buffer through; the device-pointer set_point
+    comes last and nothing runs after it."""
+    import ctypes
+    q = qmk()
+    s = synth.water_like(walkers=2)
+    ctx = q.Context.from_system(s)
+    n0 = ctx.launch_count()
+    host = np.zeros(16)
+    hp = host.ctypes.data_as(ctypes.c_void_p)
+    lib = ctx._lib
+    assert lib.qmk_get_mo_vgl(ctx._h, hp, 1, q.QMK_F64, None) == q.QMK_INVALID_ARG_BASE + 2
+    assert lib.qmk_get_ao_vgl(ctx._h, hp, 1, q.QMK_F64, None) == q.QMK_INVALID_ARG_BASE + 2
+    assert lib.qmk_get_mo_value(ctx._h, hp, 1, q.QMK_F64, None) == q.QMK_INVALID_ARG_BASE + 2
+    occ = np.zeros(s.mo_num + 1)  # wrong length as well
+    assert lib.qmk_get_density(ctx._h, occ.ctypes.data_as(ctypes.c_void_p), occ.shape[0], hp, 1,
+                               None) == q.QMK_INVALID_ARG_BASE + 4
+    assert lib.qmk_mo_vgl_adjoint(ctx._h, hp, 99, None, None, None, None) == q.QMK_INVALID_ARG_BASE + 2
+    assert "device can access" in lib.qmk_last_error(ctx._h).decode()
+    assert ctx.launch_count() == n0
+    assert lib.qmk_set_point(ctx._h, b"N", 1, 1, hp, 1) == q.QMK_INVALID_ARG_BASE + 5
+    ctx.close()
