@@ -3,7 +3,8 @@
 // together serves the gradients of Slater determinants, and for n < 5 the
 // explicit cofactor form beats an LU factorisation).
 //
-// n <= 4: one lane per matrix; the n*n entries live in registers and every
+// n <= 4: one lane per matrix (staged through LDS for coalesced loads and
+// stores); the n*n entries live in registers and every
 // cofactor is an unrolled signed minor determinant (Laplace expansion along
 // the first row, compile-time n), so the result is exact also for singular
 // matrices.  5 <= n <= 32: one wavefront per matrix, LU with partial
@@ -43,38 +44,55 @@ struct Minor<N, 1> {
   }
 };
 
+// The 256 matrices of a workgroup pass through LDS (rows padded by one
+// element against bank conflicts), so that the global loads and stores of the
+// workgroup cover one contiguous range, coalesced across lanes.
 template <int N>
 __global__ __launch_bounds__(256) void det_adj_small_kernel(const double* __restrict__ A, int64_t batch,
                                                             double* __restrict__ det,
                                                             double* __restrict__ adj) {
-  const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  double a[N * N];
+  constexpr int E = N * N, LD = E + 1;
+  __shared__ double s_m[256 * LD];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * 256;
+  const int64_t nb = min<int64_t>(256, batch - b0);
+  const double* src = A + b0 * E;
+  for (int64_t e = threadIdx.x; e < nb * E; e += 256) s_m[(e / E) * LD + e % E] = src[e];
+  __syncthreads();
+  const int t = threadIdx.x;
+  double a[E];
+  if (t < nb) {
 #pragma unroll
-  for (int i = 0; i < N * N; ++i) a[i] = A[b * N * N + i];
-  if constexpr (N == 1) {
-    det[b] = a[0];
-    adj[b] = 1.0;
-  } else {
-    double d = 0.0;
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        // cofactor C_ij = (-1)^(i+j) det(A without row i, column j); adj = C^T
-        int r[N - 1], c[N - 1];
-#pragma unroll
-        for (int k = 0; k < N - 1; ++k) {
-          r[k] = k < i ? k : k + 1;
-          c[k] = k < j ? k : k + 1;
-        }
-        const double m = Minor<N, N - 1>::det(a, r, c);
-        const double cij = ((i + j) & 1) ? -m : m;
-        adj[b * N * N + j * N + i] = cij;
-        if (i == 0) d += a[j] * cij;
-      }
-    det[b] = d;
+    for (int i = 0; i < E; ++i) a[i] = s_m[t * LD + i];
   }
+  __syncthreads();  // s_m is reused for the adjugates
+  if (t < nb) {
+    if constexpr (N == 1) {
+      det[b0 + t] = a[0];
+      s_m[t * LD] = 1.0;
+    } else {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          // cofactor C_ij = (-1)^(i+j) det(A without row i, column j); adj = C^T
+          int r[N - 1], c[N - 1];
+#pragma unroll
+          for (int k = 0; k < N - 1; ++k) {
+            r[k] = k < i ? k : k + 1;
+            c[k] = k < j ? k : k + 1;
+          }
+          const double m = Minor<N, N - 1>::det(a, r, c);
+          const double cij = ((i + j) & 1) ? -m : m;
+          s_m[t * LD + j * N + i] = cij;
+          if (i == 0) d += a[j] * cij;
+        }
+      det[b0 + t] = d;
+    }
+  }
+  __syncthreads();
+  double* dst = adj + b0 * E;
+  for (int64_t e = threadIdx.x; e < nb * E; e += 256) dst[e] = s_m[(e / E) * LD + e % E];
 }
 
 // One wavefront per matrix, 4 per workgroup; n <= 32.
