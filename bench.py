@@ -50,11 +50,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large", "det"],
+    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large", "det", "jastrow"],
                     help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes; "
                          "density: electron density of a 1114-AO molecule on a 100^3 grid; "
                          "large: 7500-AO system, dense vs screened contraction; "
-                         "det: batched determinants and adjugates of small matrices")
+                         "det: batched determinants and adjugates of small matrices; "
+                         "jastrow: three-body Jastrow factor of the 80-atom molecule")
     ap.add_argument("--cpu-walkers", type=int, default=96,
                     help="walkers in the oracle's timed sample")
     ap.add_argument("--cpu-points", type=int, default=1000000,
@@ -511,6 +512,58 @@ def main_det(a):
     print(json.dumps(line))
 
 
+def main_jastrow(a):
+    """Three-body Jastrow factor of the ch80_800ao molecule (80 nuclei, 280
+    electrons) for `walkers` walkers at expansion order 5: rescaled distances,
+    the P product on MFMA and the contraction, one call per step."""
+    import torch
+    import oracle
+    import synth
+    import paper_2512_16677_amd as qmk
+    nord, kappa = 5, 0.6
+    s = synth.medium(walkers=a.walkers)
+    rng = np.random.default_rng(0)
+    c = rng.normal(scale=0.2, size=(qmk.jastrow_een_terms(nord), s.nucl_num))
+    ctx = qmk.Context.from_system(s)
+    out = torch.empty((s.walk_num,), dtype=torch.float64, device="cuda")
+    for _ in range(1 + a.warmup):
+        ctx.jastrow_een(nord, kappa, c, out=out)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.jastrow_een(nord, kappa, c, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    tm = ctx.timing()
+    ctx.close()
+    W, ne, nn = s.walk_num, s.elec_num, s.nucl_num
+    # the product: rows (m = 1..nord/2, nucleus), splits k = 0..nord-2
+    M, nsplit = (nord // 2) * nn, nord - 1
+    flops = 2.0 * W * nsplit * M * ne * ne
+    p_ms = tm["jastrow_p"]["ms"] / tm["jastrow_p"]["launches"]
+    tf = flops / (p_ms * 1e-3) / 1e12
+    line = {"metric": "three-body Jastrow electron-evals/s", "value": W * ne / (ms * 1e-3),
+            "unit": "electron-evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"ch80_800ao: 40 C + 40 H, {ne} electrons, {W} walkers, "
+                                   f"J_een order {nord}, kappa {kappa}"},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAKS["fp64_TFLOPs"], "unit": "TFLOP/s",
+                         "frac": tf / PEAKS["fp64_TFLOPs"], "traffic": None,
+                         "kernel": "gemm_kernel EPI 5 (P product, fused weights)"},
+            "kernels_ms_per_step": {k: tm[k]["ms"] / a.steps for k in ("jastrow", "jastrow_p")}}
+    if not a.no_cpu_baseline:
+        n = max(1, min(a.cpu_walkers, W))
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.jastrow_een(s.elec_coord[:n], s.nucl_coord, kappa, nord, c)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": n * ne / dt, "unit": "electron-evals/s", "cores": threads,
+                                "kind": "oracle", "sample": f"{n} walkers of the same workload"}
+    print(json.dumps(line))
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: under a hardware-counter
     profile its FETCH_SIZE / WRITE_SIZE give the factor that turns those
@@ -529,6 +582,12 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "jastrow":
+        if a.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        main_jastrow(a)
         return
     if a.workload == "det":
         if a.gpus != 1:

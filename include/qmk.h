@@ -238,6 +238,27 @@ qmk_status qmk_get_screening_density(qmk_ctx ctx, double* active_fraction);
 qmk_status qmk_det_adj(qmk_ctx ctx, int64_t n, int64_t batch, const double* a, double* det, double* adj,
                        void* hip_stream);
 
+/* Three-body (electron-electron-nucleus) Jastrow factor of every walker
+ * (Section 3.5), computed through the intermediate matrix
+ *   P^{k,m}_{i a} = sum_{j != i} rt_ij^k Rt_ja^m,
+ *   J = sum_t sum_a c[t][a] sum_i Rt_ia^((p-k+l)/2) P^{k,(p-k-l)/2}_{i a},
+ * rt_ij = exp(-kappa r_ij), Rt_ia = exp(-kappa |r_i - R_a|), for the
+ * context's nuclei and points (walk_num walkers of elec_num electrons; the
+ * basis is not needed).  Terms t run over p = 2..nord, k = 0..p-1,
+ * l = 0..p-k-2 delta(k,0), each ascending, keeping those with p-k-l even
+ * (qmk_jastrow_een_terms gives the count).  The P^{k,m} with m >= 1 are one
+ * MFMA product per walker and k whose epilogue applies the coefficients, so
+ * P is never stored; the m = 0 terms use the nucleus-independent row sums
+ * of rt^k.  c: host FP64 [n_terms][nucl_num]; j_een: device FP64
+ * [walk_num], overwritten.  2 <= nord <= 8, kappa > 0.  FP64 in every
+ * precision mode; deterministic.  Errors: QMK_INVALID_ARG_BASE + 2/3/4 for
+ * nord, kappa, n_terms; + 5 NULL c; + 6 j_een not device memory;
+ * QMK_NONFINITE for a non-finite coefficient; QMK_NOT_SET without nuclei or
+ * points. */
+qmk_status qmk_jastrow_een_terms(int64_t nord, int64_t* n_terms);
+qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_terms, const double* c,
+                           double* j_een, void* hip_stream);
+
 /* Adjoint of L = sum(W * mo_vgl) for the current points (Section 3.6 and
  * Section 3.5 motivate these derivatives; the nuclei carry their shells
  * rigidly, basis parameters are fixed):
@@ -271,13 +292,15 @@ enum {
   QMK_KERNEL_CUSP = 7,       /* MO cusp correction                     */
   QMK_KERNEL_SORT = 8,       /* point sort of the screened contraction */
   QMK_KERNEL_DET = 9,        /* determinants and adjugates             */
-  QMK_KERNEL_CLASSES = 10
+  QMK_KERNEL_JASTROW = 10,   /* Jastrow: rescaled distances, final sum */
+  QMK_KERNEL_JASTROW_P = 11, /* Jastrow: the P product on MFMA         */
+  QMK_KERNEL_CLASSES = 12
 };
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);
 
 /* Tile shapes of the MFMA products (QMK_KERNEL_MO, QMK_KERNEL_GBAR,
- * QMK_KERNEL_DCOEF, QMK_KERNEL_DENSITY).  By default the library's autotuner times every tile
+ * QMK_KERNEL_DCOEF, QMK_KERNEL_DENSITY, QMK_KERNEL_JASTROW_P).  By default the library's autotuner times every tile
  * shape on the first call of each distinct product size and keeps the
  * fastest (process-wide; QMK_TUNE_CACHE=<file> persists the choices,
  * QMK_TUNE=0 picks by least padded work without timing).  qmk_set_tile

@@ -316,3 +316,48 @@ def det_adj(a: np.ndarray):
                 minor = np.delete(np.delete(flat, i, axis=1), j, axis=2)
                 adj[:, j, i] = (-1.0) ** (i + j) * np.linalg.det(minor)
     return det.reshape(a.shape[:-2]), adj.reshape(a.shape)
+
+
+def een_terms(nord: int):
+    """(p, k, l) of the three-body Jastrow terms in the order of the
+    coefficient array (Section 3.5): p = 2..nord, k = 0..p-1,
+    l = 0..p-k-2*delta(k,0), each ascending, keeping the terms with p-k-l
+    even (so that (p-k-l)/2 is a whole power)."""
+    out = []
+    for p in range(2, nord + 1):
+        for k in range(0, p):
+            for l in range(0, p - k - (2 if k == 0 else 0) + 1):
+                if (p - k - l) % 2 == 0:
+                    out.append((p, k, l))
+    return out
+
+
+def jastrow_een(elec: np.ndarray, nucl: np.ndarray, kappa: float, nord: int, c: np.ndarray) -> np.ndarray:
+    """Three-body (electron-electron-nucleus) Jastrow factor of every walker
+    by its original pairwise definition (Section 3.5):
+      J = sum_a sum_{i>j} sum_{(p,k,l)} c[t, a] rt_ij^k (Rt_ia^l + Rt_ja^l) (Rt_ia Rt_ja)^((p-k-l)/2)
+    with rt_ij = exp(-kappa r_ij), Rt_ia = exp(-kappa |r_i - R_a|).
+    elec [walk, elec, 3], nucl [nucl, 3], c [n_terms, nucl] (een_terms order).
+    Returns J [walk]."""
+    elec = np.asarray(elec, dtype=np.float64)
+    nucl = np.asarray(nucl, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    terms = een_terms(nord)
+    assert c.shape == (len(terms), nucl.shape[0])
+    W, ne = elec.shape[0], elec.shape[1]
+    iu, ju = np.triu_indices(ne, k=1)                      # pairs i < j (the sum is symmetric)
+    out = np.zeros(W)
+    for w in range(W):
+        x = elec[w]
+        r = np.linalg.norm(x[iu] - x[ju], axis=1)          # [pairs]
+        rt = np.exp(-kappa * r)
+        R = np.linalg.norm(x[:, None, :] - nucl[None, :, :], axis=2)  # [elec, nucl]
+        Rt = np.exp(-kappa * R)
+        Ri, Rj = Rt[iu], Rt[ju]                            # [pairs, nucl]
+        total = 0.0
+        for t, (p, k, l) in enumerate(terms):
+            m = (p - k - l) // 2
+            val = (rt ** k)[:, None] * (Ri ** l + Rj ** l) * (Ri * Rj) ** m   # [pairs, nucl]
+            total += float(np.sum(val.sum(axis=0) * c[t]))
+        out[w] = total
+    return out

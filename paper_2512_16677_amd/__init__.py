@@ -47,13 +47,14 @@ EXPORTED = [
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
     "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
     "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp", "qmk_set_screening",
-    "qmk_get_screening_density", "qmk_det_adj",
+    "qmk_get_screening_density", "qmk_det_adj", "qmk_jastrow_een_terms", "qmk_jastrow_een",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
     "qmk_get_tile_count", "qmk_set_tile",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
-KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp", "sort", "det"]
+KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp", "sort", "det",
+                  "jastrow", "jastrow_p"]
 
 _lib = None
 
@@ -95,6 +96,8 @@ def load_library(path: str = LIB_PATH):
         "qmk_set_screening": ([P, I32], I32),
         "qmk_get_screening_density": ([P, P], I32),
         "qmk_det_adj": ([P, I64, I64, P, P, P, P], I32),
+        "qmk_jastrow_een_terms": ([I64, P], I32),
+        "qmk_jastrow_een": ([P, I64, D, I64, P, P, P], I32),
         "qmk_mo_vgl_adjoint": ([P, P, I32, P, P, P, P], I32),
         "qmk_get_launch_count": ([P, P], I32),
         "qmk_set_timing": ([P, I32], I32),
@@ -112,6 +115,15 @@ def load_library(path: str = LIB_PATH):
         f.restype = res
     _lib = lib
     return lib
+
+
+def jastrow_een_terms(nord: int) -> int:
+    """Number of three-body Jastrow terms of order nord."""
+    n = ctypes.c_int64()
+    st = load_library().qmk_jastrow_een_terms(int(nord), ctypes.byref(n))
+    if st != QMK_OK:
+        raise QmkError(st, "invalid nord")
+    return n.value
 
 
 def _np(a, dtype):
@@ -249,7 +261,8 @@ class Context:
         return v.value
 
     def set_tile(self, kernel: str, tile: int):
-        """Force MFMA tile `tile` for kernel class 'mo', 'gbar', 'dcoef' or 'density' (-1: autotune)."""
+        """Force MFMA tile `tile` for kernel class 'mo', 'gbar', 'dcoef', 'density' or
+        'jastrow_p' (-1: autotune)."""
         self._check(self._lib.qmk_set_tile(self._h, KERNEL_CLASSES.index(kernel), int(tile)))
 
     def _out(self, out, shape, dtype):
@@ -294,6 +307,18 @@ class Context:
         v = ctypes.c_double()
         self._check(self._lib.qmk_get_screening_density(self._h, ctypes.byref(v)))
         return v.value
+
+    def jastrow_een(self, nord: int, kappa: float, c, out=None, stream=None):
+        """Three-body Jastrow factor of every walker: CUDA float64 tensor
+        [walk].  c: host array [n_terms, nucl] (jastrow_een_terms order)."""
+        import torch
+        d = self.dims()
+        cc = _np(c, np.float64)
+        if out is None:
+            out = torch.empty((d["walk_num"],), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._check(self._lib.qmk_jastrow_een(self._h, int(nord), float(kappa), cc.shape[0], _ptr(cc),
+                                              _ptr(out), _stream(stream)))
+        return out
 
     def det_adj(self, a, stream=None):
         """Determinants and adjugates of a CUDA float64 tensor [..., n, n]:

@@ -25,9 +25,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [], None),
            ("ao_kernels.hip", [], None), ("adjoint_kernels.hip", [], None),
            ("cusp_kernels.hip", [], None), ("sort_kernels.hip", [], None),
-           ("det_kernels.hip", [], None),
+           ("det_kernels.hip", [], None), ("jastrow_kernels.hip", [], None),
            ("gemm_kernels.hip", [], None), ("gemm_bf16.hip", [], None)]
-SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_kernels_u{u}") for u in range(1, 10)]
+SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_kernels_u{u}") for u in range(1, 11)]
 SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_bf16_u{u}") for u in range(1, 4)]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

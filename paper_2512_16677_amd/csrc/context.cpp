@@ -987,6 +987,143 @@ qmk_status qmk_det_adj(qmk_ctx ctx, int64_t n, int64_t batch, const double* a, d
   return QMK_OK;
 }
 
+// Terms of the three-body Jastrow in coefficient order (Section 3.5):
+// p = 2..nord, k = 0..p-1, l = 0..p-k-2 delta(k,0), each ascending, keeping
+// p-k-l even.  Appends (k, m = (p-k-l)/2, e = (p-k+l)/2) per term to kme.
+static int64_t een_term_list(int64_t nord, std::vector<int32_t>* kme) {
+  int64_t n = 0;
+  for (int64_t p = 2; p <= nord; ++p)
+    for (int64_t k = 0; k < p; ++k)
+      for (int64_t l = 0; l <= p - k - (k == 0 ? 2 : 0); ++l) {
+        if ((p - k - l) % 2 != 0) continue;
+        if (kme) kme->insert(kme->end(), {static_cast<int32_t>(k), static_cast<int32_t>((p - k - l) / 2),
+                                          static_cast<int32_t>((p - k + l) / 2)});
+        ++n;
+      }
+  return n;
+}
+
+qmk_status qmk_jastrow_een_terms(int64_t nord, int64_t* n_terms) {
+  if (!n_terms) return QMK_INVALID_ARG_BASE + 2;
+  if (nord < 2 || nord > 8) return QMK_INVALID_ARG_BASE + 1;
+  *n_terms = een_term_list(nord, nullptr);
+  return QMK_OK;
+}
+
+qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_terms, const double* c,
+                           double* j_een, void* hip_stream) {
+  QMK_CHECK_CTX(ctx);
+  if (nord < 2 || nord > 8) return bad_arg(ctx, 2, "nord must be in 2..8");
+  if (!std::isfinite(kappa) || kappa <= 0.0) return bad_arg(ctx, 3, "kappa must be finite and > 0");
+  std::vector<int32_t> kme;
+  if (n_terms != een_term_list(nord, &kme)) return bad_arg(ctx, 4, "n_terms does not match nord");
+  if (!c) return bad_arg(ctx, 5, "NULL");
+  DeviceGuard g(ctx->device);
+  qmk_status st = check_dev_arg(ctx, 6, j_een);
+  if (st != QMK_OK) return st;
+  if (ctx->nucl_num <= 0) return fail(ctx, QMK_NOT_SET, "nuclei not set");
+  if (!ctx->has_points) return fail(ctx, QMK_NOT_SET, "points not set");
+  const int64_t nn = ctx->nucl_num, nw = ctx->walk_num, ne = ctx->elec_num, P = ctx->P();
+  for (int64_t i = 0; i < n_terms * nn; ++i)
+    if (!std::isfinite(c[i])) return fail(ctx, QMK_NONFINITE, "non-finite Jastrow coefficient");
+  // Terms grouped by (k, m): the coefficient of x^e in the weight of
+  // P^{k,m}_{ia} is c[t][a] of the one term with that (k, m, e).  m >= 1
+  // needs k <= nord-2 and m <= nord/2 (the product's splits and rows);
+  // m = 0 needs k >= 1 (handled per electron).
+  const int nsplit = static_cast<int>(nord - 1), mh = static_cast<int>(nord / 2), deg = static_cast<int>(nord);
+  std::vector<double> q(static_cast<size_t>(nsplit * mh * nn * (deg + 1)), 0.0);
+  std::vector<double> q0(static_cast<size_t>((nord - 1) * nn * (deg + 1)), 0.0);
+  for (int64_t t = 0; t < n_terms; ++t) {
+    const int k = kme[3 * t], m = kme[3 * t + 1], e = kme[3 * t + 2];
+    for (int64_t a = 0; a < nn; ++a) {
+      if (m == 0)
+        q0[((k - 1) * nn + a) * (deg + 1) + e] = c[t * nn + a];
+      else
+        q[((static_cast<int64_t>(k) * mh + (m - 1)) * nn + a) * (deg + 1) + e] = c[t * nn + a];
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (ctx->nuc_xyz_version != ctx->geom_version) {
+    QMK_HIP(ctx, ctx->d_nuc_xyz.ensure(static_cast<size_t>(3 * nn) * 8), "alloc nuclei");
+    QMK_HIP(ctx, hipMemcpy(ctx->d_nuc_xyz.p, ctx->nucl.data(), static_cast<size_t>(3 * nn) * 8,
+                           hipMemcpyHostToDevice), "upload nuclei");
+    ctx->nuc_xyz_version = ctx->geom_version;
+  }
+  const int64_t M = mh * nn;
+  QMK_HIP(ctx, ctx->een_ra.ensure(static_cast<size_t>(P * M) * 8), "alloc rescaled e-n powers");
+  QMK_HIP(ctx, ctx->een_x.ensure(static_cast<size_t>(P * nn) * 8), "alloc rescaled e-n distances");
+  QMK_HIP(ctx, ctx->een_rt.ensure(static_cast<size_t>(nw * nsplit * ne * ne) * 8), "alloc rescaled e-e powers");
+  QMK_HIP(ctx, ctx->een_j0.ensure(static_cast<size_t>(P) * 8), "alloc per-electron parts");
+  QMK_HIP(ctx, ctx->een_q.ensure((q.size() + q0.size()) * 8), "alloc weight polynomials");
+  double* const d_q = ctx->een_q.as<double>();
+  double* const d_q0 = d_q + q.size();
+  QMK_HIP(ctx, hipMemcpy(d_q, q.data(), q.size() * 8, hipMemcpyHostToDevice), "upload weight polynomials");
+  QMK_HIP(ctx, hipMemcpy(d_q0, q0.data(), q0.size() * 8, hipMemcpyHostToDevice), "upload weight polynomials");
+  // per-wave partial sums of the product: slots per (walker, k) for a tile
+  auto slots_of = [&](int cfg) -> int64_t {
+    const TileCfg t = gemm_tile(Prec::kF64, cfg);
+    return (M + t.bm() - 1) / t.bm() * t.wgm * ((ne + t.bn() - 1) / t.bn() * t.wgn);
+  };
+  int64_t slots_max = 1;
+  for (int cfg = 0; cfg < gemm_num_tiles(Prec::kF64); ++cfg) slots_max = std::max(slots_max, slots_of(cfg));
+  QMK_HIP(ctx, ctx->een_part.ensure(static_cast<size_t>(nw * nsplit * slots_max) * 8), "alloc partial sums");
+  {
+    LaunchTimer lt(ctx, QMK_KERNEL_JASTROW, s);
+    const PointArgs pa = point_args(ctx);
+    QMK_HIP(ctx, launch_een_en(pa, ne, ctx->d_nuc_xyz.as<double>(), nn, kappa, mh, ctx->een_ra.as<double>(),
+                               ctx->een_x.as<double>(), s),
+            "Jastrow e-n distances");
+    QMK_HIP(ctx, launch_een_ee(pa, ne, kappa, static_cast<int>(nord), nsplit, ctx->een_x.as<double>(), d_q0, nn,
+                               ctx->een_rt.as<double>(), ctx->een_j0.as<double>(), s),
+            "Jastrow e-e distances");
+  }
+  // part[w, k][slot] = weighted sums of P^{k,m}[(m-1) nn + a][i] =
+  //   sum_j Ra[w][j][(m-1) nn + a] rt^k[w][j][i]   (rt^k symmetric)
+  GemmArgs ga{};
+  ga.A = ctx->een_ra.p;
+  ga.sAi = 1;
+  ga.sAl = M;
+  ga.oAc = ne * M;
+  ga.oAs = 0;
+  ga.B = ctx->een_rt.p;
+  ga.sBl = ne;
+  ga.sBj = 1;
+  ga.oBc = nsplit * ne * ne;
+  ga.oBs = ne * ne;
+  ga.D = ctx->een_part.p;
+  ga.M = M;
+  ga.N = ne;
+  ga.L = nsplit * ne;  // split s = k runs over j in [0, ne) of its own rt^k
+  ga.Lchunk = ne;
+  ga.nsplit = nsplit;
+  ga.nbatch = static_cast<int32_t>(nw);
+  ga.map_slab = 1;
+  ga.jx = ctx->een_x.as<double>();
+  ga.jq = d_q;
+  ga.j_nn = nn;
+  ga.j_deg = deg;
+  ga.j_mh = mh;
+  auto enqueue = [&](int cfg) -> hipError_t {
+    GemmArgs gc = ga;
+    gc.oDz = slots_of(cfg);
+    hipError_t e;
+    {
+      LaunchTimer lt(ctx, QMK_KERNEL_JASTROW_P, s);
+      e = launch_gemm_jastrow(cfg, gc, s);
+    }
+    if (e != hipSuccess) return e;
+    LaunchTimer lt(ctx, QMK_KERNEL_JASTROW, s);
+    return launch_een_finish(ctx->een_part.as<double>(), nsplit * gc.oDz, ctx->een_j0.as<double>(), nw, ne,
+                             j_een, s);
+  };
+  GemmProblem pb{GemmKind::kJastrow, Prec::kF64, 0, 0, M, ne, ne};
+  pb.nbatch = nsplit;
+  int cfg = 0;
+  if ((st = pick_tile(ctx, pb, s, enqueue, &cfg)) != QMK_OK) return st;
+  QMK_HIP(ctx, enqueue(cfg), "Jastrow product");
+  return QMK_OK;
+}
+
 qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable) {
   QMK_CHECK_CTX(ctx);
   if (enable != 0 && enable != 1) return bad_arg(ctx, 2, "enable must be 0 or 1");
@@ -1067,8 +1204,11 @@ qmk_status qmk_set_tile(qmk_ctx ctx, int32_t kernel_class, int32_t tile) {
   if (kernel_class == QMK_KERNEL_GBAR) kind = static_cast<int>(GemmKind::kGbar);
   if (kernel_class == QMK_KERNEL_DCOEF) kind = static_cast<int>(GemmKind::kDcoef);
   if (kernel_class == QMK_KERNEL_DENSITY) kind = static_cast<int>(GemmKind::kDensity);
+  if (kernel_class == QMK_KERNEL_JASTROW_P) kind = static_cast<int>(GemmKind::kJastrow);
   if (kind < 0) return bad_arg(ctx, 2, "kernel class has no tile choice");
   if (tile < -1 || tile >= gemm_num_tiles(Prec::kF64)) return bad_arg(ctx, 3, "unknown tile");
+  if (tile >= 0 && !tile_feasible(Prec::kF64, tile) && kind == static_cast<int>(GemmKind::kJastrow))
+    return bad_arg(ctx, 3, "tile does not fit in LDS");  // the Jastrow product is FP64 in every mode
   if (tile >= 0 && !tile_feasible(Prec::kF64, tile) && ctx->mode == QMK_FP64)
     return bad_arg(ctx, 3, "tile does not fit in LDS");
   ctx->forced_tile[kind] = tile;

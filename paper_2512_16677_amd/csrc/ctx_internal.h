@@ -135,12 +135,16 @@ struct qmk_ctx_s {
   DevBuf d_cusp_nuc, d_cusp_s, d_cusp_prim, d_cusp_cs, d_cusp_f, d_cusp_pts, d_cusp_ao;
   qmk::CuspArgs cusp{};
 
+  // three-body Jastrow: operands of the product, rescaled e-n distances,
+  // per-electron parts, weight polynomials and per-wave partial sums
+  DevBuf een_ra, een_x, een_rt, een_j0, een_q, een_part;
+
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
   int64_t gbar_Pp = 0, gbar_Kp = 0;
   int gbar_f32 = -1;
 
   int64_t launches = 0;
-  int forced_tile[4] = {-1, -1, -1, -1};  // per GemmKind; -1 = autotuned
+  int forced_tile[5] = {-1, -1, -1, -1, -1};  // per GemmKind; -1 = autotuned
 
   // tracing: events around launches, per kernel class
   struct Pending {

@@ -61,6 +61,10 @@ struct GemmSmem {
 // EPI = 3 is the screened G-bar product (rows: AOs, columns: sorted points;
 // W already in sorted point order): a tile whose AO chunks are inactive for
 // all of its point blocks is stored as zeros without running the K loop.
+// EPI = 5 is the three-body Jastrow product (FP64): no output matrix; each
+// wave weighs its outputs by the row's polynomial in x (GemmArgs::jx, jq),
+// sums them and stores the sum in slot (mt WGM + wm) nNw + nt WGN + wn of
+// batch z, nNw = (N tiles) WGN.
 // EPI = 4 is the screened dC product (K runs over sorted points): the K
 // stages whose 64-point block has no active chunk among the tile's N
 // columns are skipped.
@@ -257,6 +261,37 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
         if ((lane & 15) == 0 && gi < g.M) part[gi * g.sDi] = v;
       }
     }
+  } else if constexpr (EPI == 5) {
+    // Jastrow: weight output (i, j) by the polynomial of row i in x[a][j],
+    // sum over the wave and store the sum in the wave's slot of batch z
+    const int64_t c_b = z / g.nsplit, s_k = z - c_b * g.nsplit;
+    const double* const xw = g.jx + c_b * g.j_nn * g.N;
+    const int64_t nNw = (g.N + BN - 1) / BN * WGN;
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        if (gi >= g.M) continue;
+        const int64_t m1 = gi / g.j_nn, na = gi - m1 * g.j_nn;
+        const double* const q = g.jq + ((s_k * g.j_mh + m1) * g.j_nn + na) * (g.j_deg + 1);
+        const double* const xr = xw + na * g.N;
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+          if (gj >= g.N) continue;
+          const double x = xr[gj];
+          double pw = q[g.j_deg];
+          for (int e = g.j_deg - 1; e >= 0; --e) pw = pw * x + q[e];
+          v += pw * static_cast<double>(acc[a][b][r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) Dp[(static_cast<int64_t>(mt) * WGM + wm) * nNw + static_cast<int64_t>(nt) * WGN + wn] = v;
   } else if constexpr (EPI == 2) {
 #pragma unroll
     for (int a = 0; a < TM; ++a) {

@@ -11,6 +11,8 @@
 //   density   part[t][p]    = sum_{n in tile t} occ[n] (sum_k ao[k][p] Ct[k][n])^2
 //   screened  mo[perm[q]][c][n] = sum_{k in active chunks} aos[k][c][q] Ct[k][n]
 //             (aos: the AO array in sorted point order)
+//   Jastrow   part[c,k][slot] = sum over the slot's (i, j) of
+//             w_k(i, j) sum_l Ra[c][l][i] rt^k[c][l][j]   (no output matrix)
 // (see GemmArgs for the index algebra).  A tile is WGM x WGN wavefronts,
 // each owning TM x TN MFMA 16x16x4 blocks (FP64 or FP32); the shapes on
 // offer are listed in QMK_TILE_LIST and chosen per problem by the host
@@ -99,6 +101,13 @@ hipError_t gemm_unit_sparse(int cfg, const GemmArgs* g, Prec prec, int o32, hipS
   return o32 ? run_sparse<float, float>(cfg, *g, s) : run_sparse<float, double>(cfg, *g, s);
 }
 #endif
+#if QMK_GEMM_UNIT == 10
+// Three-body Jastrow product with its fused weighted reduction (gemm_body
+// EPI 5).
+hipError_t gemm_unit_jastrow(int cfg, const GemmArgs* g, hipStream_t s) {
+  return run<double, double, double, double, true, true, 5>(cfg, *g, s);
+}
+#endif
 #if QMK_GEMM_UNIT == 7
 hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t s) {
   return prec == Prec::kF64 ? run_density<double>(cfg, *g, s) : run_density<float>(cfg, *g, s);
@@ -106,7 +115,7 @@ hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t 
 #endif
 #else
 // Products of each (precision, kind) are instantiated in their own
-// translation unit (this file compiled with QMK_GEMM_UNIT = 1..9) so that
+// translation unit (this file compiled with QMK_GEMM_UNIT = 1..10) so that
 // they build in parallel; the unit without QMK_GEMM_UNIT holds the tables
 // and the dispatch.
 hipError_t gemm_unit_f64_fwd(int cfg, const GemmArgs* g, const PersistLaunch* pl, int w32, int o32,
@@ -123,6 +132,7 @@ hipError_t gemm_unit_f32_dc(int cfg, const GemmArgs* g, const PersistLaunch* pl,
                          hipStream_t s);
 
 hipError_t gemm_unit_density(int cfg, const GemmArgs* g, Prec prec, hipStream_t s);
+hipError_t gemm_unit_jastrow(int cfg, const GemmArgs* g, hipStream_t s);
 hipError_t gemm_unit_sparse(int cfg, const GemmArgs* g, Prec prec, int o32, hipStream_t s);
 hipError_t gemm_unit_screened_adj(GemmKind kind, int cfg, const GemmArgs* g, Prec prec, int w32,
                                   hipStream_t s);
@@ -174,6 +184,11 @@ hipError_t launch_gemm_screened_adj(GemmKind kind, Prec prec, int cfg, const Gem
       (kind != GemmKind::kGbar && kind != GemmKind::kDcoef))
     return hipErrorInvalidValue;
   return gemm_unit_screened_adj(kind, cfg, &g, prec, w_is_f32, s);
+}
+
+hipError_t launch_gemm_jastrow(int cfg, const GemmArgs& g, hipStream_t s) {
+  if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
+  return gemm_unit_jastrow(cfg, &g, s);
 }
 
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s) {

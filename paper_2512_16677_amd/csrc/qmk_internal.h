@@ -139,6 +139,17 @@ struct GemmArgs {
   const uint32_t* act;
   const int32_t* perm;
   int64_t act_words;
+  // Three-body Jastrow product only (FP64, batch c = walker, split s = power
+  // k of the rescaled e-e distance): row i of the product is (m = 1 + i /
+  // j_nn, nucleus a = i % j_nn), column j an electron.  jx[c][a][j] holds
+  // x = exp(-kappa |r_j - R_a|) (N per nucleus), jq[s][m-1][a][0..j_deg] the
+  // coefficients of the polynomial in x that weighs output (i, j).  Each wave
+  // stores the weighted sum of its outputs in its own slot of D (see the
+  // product's epilogue).
+  const double* jx;
+  const double* jq;
+  int64_t j_nn;
+  int32_t j_deg, j_mh;
 };
 
 // Tile of workgroup `bid` of a grid launch; false if it has none.  The
@@ -193,7 +204,7 @@ __device__ __forceinline__ AxisD axis_derivs(int e, double t, double t2, double 
   return r;
 }
 
-enum class GemmKind { kForward, kGbar, kDcoef, kDensity };
+enum class GemmKind { kForward, kGbar, kDcoef, kDensity, kJastrow };
 enum class Prec { kF64, kF32, kBF16x3 };
 
 // Launchers (return hipError_t of the launch).
@@ -230,6 +241,15 @@ hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64
 // Determinants det[b] and adjugates adj[b] (row-major n x n) of a batch of
 // row-major n x n FP64 matrices, 1 <= n <= 32.
 hipError_t launch_det_adj(int n, int64_t batch, const double* A, double* det, double* adj, hipStream_t s);
+// Three-body Jastrow pieces (jastrow_kernels.hip; see there for layouts).
+hipError_t launch_een_en(const PointArgs& pts, int64_t ne, const double* nuc, int64_t nn, double kappa, int mh,
+                         double* ra, double* x, hipStream_t s);
+hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, double kappa, int nord, int nsplit, const double* x,
+                         const double* q0, int64_t nn, double* rt, double* j0, hipStream_t s);
+hipError_t launch_een_finish(const double* part, int64_t slots, const double* j0, int64_t nw, int64_t ne,
+                             double* J, hipStream_t s);
+// The Jastrow product with its fused weighted reduction (FP64).
+hipError_t launch_gemm_jastrow(int cfg, const GemmArgs& g, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // dst row q = src row perm[q] for q < rows (rows of row_bytes bytes, a
 // multiple of 4).

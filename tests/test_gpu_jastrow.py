@@ -1,0 +1,124 @@
+"""Three-body Jastrow factor through the C ABI vs the FP64 oracle.
+
+Tolerance: every term of J is a product of rescaled distances in (0, 1] and a
+coefficient, so the rounding error of any summation order is bounded relative
+to J_abs, the same sum with |c| (the oracle with the coefficients' absolute
+values); the P product and the contraction run in FP64: 1e-12 J_abs.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def qmk():
+    import paper_2512_16677_amd as q
+    return q
+
+
+def coefficients(nord, nn, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(scale=0.2, size=(len(oracle.een_terms(nord)), nn))
+
+
+def reference(s, kappa, nord, c):
+    ref = oracle.jastrow_een(s.elec_coord, s.nucl_coord, kappa, nord, c)
+    ref_abs = oracle.jastrow_een(s.elec_coord, s.nucl_coord, kappa, nord, np.abs(c))
+    return ref, ref_abs
+
+
+def test_term_count_matches_oracle():
+    q = qmk()
+    for nord in range(2, 9):
+        assert q.jastrow_een_terms(nord) == len(oracle.een_terms(nord))
+
+
+@pytest.mark.parametrize("system,nord", [("water_like", 3), ("water_like", 5), ("water_like", 8),
+                                         ("medium", 5)])
+def test_jastrow_een_matches_oracle(system, nord):
+    q = qmk()
+    s = synth.water_like(walkers=7) if system == "water_like" else synth.medium(walkers=2)
+    kappa = 0.6
+    c = coefficients(nord, s.nucl_num, seed=nord)
+    ctx = q.Context.from_system(s)
+    j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+    j2 = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+    ctx.close()
+    ref, ref_abs = reference(s, kappa, nord, c)
+    err = float(np.max(np.abs(j - ref) / ref_abs))
+    print(json.dumps({"system": system, "nord": nord, "jastrow_err": err}))
+    assert err <= 1e-12
+    np.testing.assert_array_equal(j, j2)  # deterministic
+
+
+def test_jastrow_een_every_tile_and_every_mode():
+    """Every tile of the P product gives the oracle's J; the precision mode of
+    the context does not change the (FP64) Jastrow."""
+    q = qmk()
+    s = synth.water_like(walkers=5)
+    nord, kappa = 4, 0.9
+    c = coefficients(nord, s.nucl_num, seed=11)
+    ref, ref_abs = reference(s, kappa, nord, c)
+    ctx = q.Context.from_system(s)
+    for t in range(ctx.tile_count()):
+        ctx.set_tile("jastrow_p", t)
+        j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+        assert np.all(np.abs(j - ref) <= 1e-12 * ref_abs), t
+    ctx.close()
+    for mode in ("mixed_f32", "mixed_bf16x3"):
+        ctx = q.Context.from_system(s, bits=24, mode=mode)
+        j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+        ctx.close()
+        assert np.all(np.abs(j - ref) <= 1e-12 * ref_abs), mode
+
+
+def test_jastrow_een_one_electron_is_zero_and_new_points_are_used():
+    q = qmk()
+    s = synth.water_like(walkers=3)
+    nord, kappa = 3, 1.0
+    c = coefficients(nord, s.nucl_num, seed=5)
+    ctx = q.Context.from_system(s)
+    one = s.elec_coord[:, :1, :].copy()
+    ctx.set_point(one)
+    j = ctx.jastrow_een(nord, kappa, c)
+    assert torch.count_nonzero(j).item() == 0
+    # moving the electrons changes J to the oracle's value at the new points
+    rng = np.random.default_rng(2)
+    moved = s.elec_coord + rng.normal(scale=0.3, size=s.elec_coord.shape)
+    ctx.set_point(moved)
+    j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+    ctx.close()
+    ref = oracle.jastrow_een(moved, s.nucl_coord, kappa, nord, c)
+    ref_abs = oracle.jastrow_een(moved, s.nucl_coord, kappa, nord, np.abs(c))
+    assert np.all(np.abs(j - ref) <= 1e-12 * ref_abs)
+
+
+def test_jastrow_een_rejects_bad_arguments():
+    q = qmk()
+    s = synth.water_like(walkers=2)
+    ctx = q.Context.from_system(s)
+    c = coefficients(3, s.nucl_num)
+    for nord, kappa, cc, status in [(1, 1.0, c, q.QMK_INVALID_ARG_BASE + 2),
+                                    (9, 1.0, c, q.QMK_INVALID_ARG_BASE + 2),
+                                    (3, 0.0, c, q.QMK_INVALID_ARG_BASE + 3),
+                                    (3, float("nan"), c, q.QMK_INVALID_ARG_BASE + 3),
+                                    (4, 1.0, c, q.QMK_INVALID_ARG_BASE + 4)]:
+        with pytest.raises(q.QmkError) as e:
+            ctx.jastrow_een(nord, kappa, cc)
+        assert e.value.status == status
+    bad = c.copy()
+    bad[1, 2] = np.inf
+    with pytest.raises(q.QmkError) as e:
+        ctx.jastrow_een(3, 1.0, bad)
+    assert e.value.status == q.QMK_NONFINITE
+    host = torch.empty(2, dtype=torch.float64)
+    with pytest.raises(q.QmkError) as e:
+        ctx.jastrow_een(3, 1.0, c, out=host)
+    assert e.value.status == q.QMK_INVALID_ARG_BASE + 6
+    ctx.close()
