@@ -19,6 +19,12 @@ OUT = os.path.join(HERE, "libqmk.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# Per-unit code generation flags.  Unit 10 (the Jastrow product, whose
+# epilogue does arithmetic on the accumulators): accumulate in vector
+# registers, so that the accumulators are not copied between register files
+# on every K step and the 64x160 tile keeps two waves per SIMD.
+UNIT_FLAGS = {10: ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 # (source, extra defines, object name): the MFMA product sources are compiled
 # once per (precision, product) unit so that their many tile instantiations
 # build in parallel.
@@ -27,7 +33,8 @@ SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [],
            ("cusp_kernels.hip", [], None), ("sort_kernels.hip", [], None),
            ("det_kernels.hip", [], None), ("jastrow_kernels.hip", [], None),
            ("gemm_kernels.hip", [], None), ("gemm_bf16.hip", [], None)]
-SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_kernels_u{u}") for u in range(1, 11)]
+SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"] + UNIT_FLAGS.get(u, []), f"gemm_kernels_u{u}")
+            for u in range(1, 11)]
 SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_bf16_u{u}") for u in range(1, 4)]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

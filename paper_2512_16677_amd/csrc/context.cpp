@@ -1031,7 +1031,7 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   // needs k <= nord-2 and m <= nord/2 (the product's splits and rows);
   // m = 0 needs k >= 1 (handled per electron).
   const int nsplit = static_cast<int>(nord - 1), mh = static_cast<int>(nord / 2), deg = static_cast<int>(nord);
-  std::vector<double> q(static_cast<size_t>(nsplit * mh * nn * (deg + 1)), 0.0);
+  std::vector<double> q(static_cast<size_t>(nsplit * mh * nn * kJasCoef), 0.0);
   std::vector<double> q0(static_cast<size_t>((nord - 1) * nn * (deg + 1)), 0.0);
   for (int64_t t = 0; t < n_terms; ++t) {
     const int k = kme[3 * t], m = kme[3 * t + 1], e = kme[3 * t + 2];
@@ -1039,7 +1039,7 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
       if (m == 0)
         q0[((k - 1) * nn + a) * (deg + 1) + e] = c[t * nn + a];
       else
-        q[((static_cast<int64_t>(k) * mh + (m - 1)) * nn + a) * (deg + 1) + e] = c[t * nn + a];
+        q[((static_cast<int64_t>(k) * mh + (m - 1)) * nn + a) * kJasCoef + e] = c[t * nn + a];
     }
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1052,7 +1052,7 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   const int64_t M = mh * nn;
   QMK_HIP(ctx, ctx->een_ra.ensure(static_cast<size_t>(P * M) * 8), "alloc rescaled e-n powers");
   QMK_HIP(ctx, ctx->een_x.ensure(static_cast<size_t>(P * nn) * 8), "alloc rescaled e-n distances");
-  QMK_HIP(ctx, ctx->een_rt.ensure(static_cast<size_t>(nw * nsplit * ne * ne) * 8), "alloc rescaled e-e powers");
+  QMK_HIP(ctx, ctx->een_rt.ensure(static_cast<size_t>(nw * ne * ne) * 8), "alloc rescaled e-e distances");
   QMK_HIP(ctx, ctx->een_j0.ensure(static_cast<size_t>(P) * 8), "alloc per-electron parts");
   QMK_HIP(ctx, ctx->een_q.ensure((q.size() + q0.size()) * 8), "alloc weight polynomials");
   double* const d_q = ctx->een_q.as<double>();
@@ -1073,12 +1073,13 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
     QMK_HIP(ctx, launch_een_en(pa, ne, ctx->d_nuc_xyz.as<double>(), nn, kappa, mh, ctx->een_ra.as<double>(),
                                ctx->een_x.as<double>(), s),
             "Jastrow e-n distances");
-    QMK_HIP(ctx, launch_een_ee(pa, ne, kappa, static_cast<int>(nord), nsplit, ctx->een_x.as<double>(), d_q0, nn,
+    QMK_HIP(ctx, launch_een_ee(pa, ne, ctx->d_nuc_xyz.as<double>(), nn, kappa, static_cast<int>(nord), d_q0,
                                ctx->een_rt.as<double>(), ctx->een_j0.as<double>(), s),
             "Jastrow e-e distances");
   }
-  // part[w, k][slot] = weighted sums of P^{k,m}[(m-1) nn + a][i] =
-  //   sum_j Ra[w][j][(m-1) nn + a] rt^k[w][j][i]   (rt^k symmetric)
+  // part[w, k][slot] = weighted sums over the slot's outputs of
+  //   P^{k,m}[(m-1) nn + a][i] = sum_j Ra[w][j][(m-1) nn + a] rt[w][j][i]^k
+  //   (rt symmetric; the product takes the power as it stages rt)
   GemmArgs ga{};
   ga.A = ctx->een_ra.p;
   ga.sAi = 1;
@@ -1088,12 +1089,12 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   ga.B = ctx->een_rt.p;
   ga.sBl = ne;
   ga.sBj = 1;
-  ga.oBc = nsplit * ne * ne;
-  ga.oBs = ne * ne;
+  ga.oBc = ne * ne;
+  ga.oBs = 0;
   ga.D = ctx->een_part.p;
   ga.M = M;
   ga.N = ne;
-  ga.L = nsplit * ne;  // split s = k runs over j in [0, ne) of its own rt^k
+  ga.L = nsplit * ne;  // split s = k runs over j in [0, ne) of rt, to the power k
   ga.Lchunk = ne;
   ga.nsplit = nsplit;
   ga.nbatch = static_cast<int32_t>(nw);
@@ -1101,7 +1102,6 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   ga.jx = ctx->een_x.as<double>();
   ga.jq = d_q;
   ga.j_nn = nn;
-  ga.j_deg = deg;
   ga.j_mh = mh;
   auto enqueue = [&](int cfg) -> hipError_t {
     GemmArgs gc = ga;

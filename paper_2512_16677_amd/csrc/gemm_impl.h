@@ -61,10 +61,11 @@ struct GemmSmem {
 // EPI = 3 is the screened G-bar product (rows: AOs, columns: sorted points;
 // W already in sorted point order): a tile whose AO chunks are inactive for
 // all of its point blocks is stored as zeros without running the K loop.
-// EPI = 5 is the three-body Jastrow product (FP64): no output matrix; each
-// wave weighs its outputs by the row's polynomial in x (GemmArgs::jx, jq),
-// sums them and stores the sum in slot (mt WGM + wm) nNw + nt WGN + wn of
-// batch z, nNw = (N tiles) WGN.
+// EPI = 5 is the three-body Jastrow product (FP64, batch z = (walker, k)):
+// B holds rescaled distances and split s = k stages their k-th power; there
+// is no output matrix: each wave weighs its outputs by the row's polynomial
+// in x (GemmArgs::jx, jq), sums them and stores the sum in slot
+// (mt WGM + wm) nNw + nt WGN + wn of batch z, nNw = (N tiles) WGN.
 // EPI = 4 is the screened dC product (K runs over sorted points): the K
 // stages whose 64-point block has no active chunk among the tile's N
 // columns are skipped.
@@ -149,7 +150,15 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
       if (BK * BN % NT != 0 && e >= BK * BN) continue;
       const int j = B_J ? e % BN : e / BK;
       const int l = B_J ? e / BN : e % BK;
-      Bs[buf][l][j] = rb[r];
+      T val = rb[r];
+      if constexpr (EPI == 5) {
+        // Jastrow: B holds the rescaled e-e distances (diagonal < 0); split
+        // s takes their s-th power, zero on the diagonal
+        T pw = val < T(0) ? T(0) : T(1);
+        for (int t = 0; t < s; ++t) pw *= val;
+        val = pw;
+      }
+      Bs[buf][l][j] = val;
     }
   };
 
@@ -263,34 +272,64 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     }
   } else if constexpr (EPI == 5) {
     // Jastrow: weight output (i, j) by the polynomial of row i in x[a][j],
-    // sum over the wave and store the sum in the wave's slot of batch z
+    // sum over the wave and store the sum in the wave's slot of batch z.
+    // The coefficients of the tile's rows are staged in LDS (the operand
+    // buffers are free after the last K step's barrier); x comes from L2,
+    // one batch of loads per block row.
     const int64_t c_b = z / g.nsplit, s_k = z - c_b * g.nsplit;
     const double* const xw = g.jx + c_b * g.j_nn * g.N;
-    const int64_t nNw = (g.N + BN - 1) / BN * WGN;
+    const int nn = static_cast<int>(g.j_nn);
+    static_assert(sizeof(sm.A) >= sizeof(double) * BM * kJasCoef, "coefficient stage does not fit");
+    double* const qs = reinterpret_cast<double*>(&sm.A[0][0][0]);
+    for (int e = tid; e < BM * kJasCoef; e += NT) {
+      const int lr = e / kJasCoef, d = e - lr * kJasCoef;
+      const int gi = static_cast<int>(i0) + lr;
+      double q = 0.0;
+      if (gi < g.M) {
+        const int m1 = gi / nn, na = gi - m1 * nn;
+        q = g.jq[((s_k * g.j_mh + m1) * g.j_nn + na) * kJasCoef + d];
+      }
+      qs[e] = q;
+    }
+    __syncthreads();
     double v = 0.0;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
       __builtin_amdgcn_sched_barrier(0);
+      double xv[4][TN];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
-        if (gi >= g.M) continue;
-        const int64_t m1 = gi / g.j_nn, na = gi - m1 * g.j_nn;
-        const double* const q = g.jq + ((s_k * g.j_mh + m1) * g.j_nn + na) * (g.j_deg + 1);
-        const double* const xr = xw + na * g.N;
+        const int gi = static_cast<int>(i0) + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        const bool row_in = gi < g.M;
+        const int na = row_in ? gi % nn : 0;
+        const double* const xr = xw + static_cast<int64_t>(na) * g.N;
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
           const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
-          if (gj >= g.N) continue;
-          const double x = xr[gj];
-          double pw = q[g.j_deg];
-          for (int e = g.j_deg - 1; e >= 0; --e) pw = pw * x + q[e];
-          v += pw * static_cast<double>(acc[a][b][r]);
+          xv[r][b] = row_in && gj < g.N ? xr[gj] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* const q = qs + ((wm * TM + a) * 16 + Mfma<T>::row(lane, r)) * kJasCoef;
+        double qr[kJasCoef];
+#pragma unroll
+        for (int d = 0; d < kJasCoef; ++d) qr[d] = q[d];
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          // padded columns hold products with the k = 0 padding: masked
+          const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+          const double x = xv[r][b];
+          double pw = qr[kJasCoef - 1];
+#pragma unroll
+          for (int d = kJasCoef - 2; d >= 0; --d) pw = pw * x + qr[d];
+          v += gj < g.N ? pw * static_cast<double>(acc[a][b][r]) : 0.0;
         }
       }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int64_t nNw = (g.N + BN - 1) / BN * WGN;
     if (lane == 0) Dp[(static_cast<int64_t>(mt) * WGM + wm) * nNw + static_cast<int64_t>(nt) * WGN + wn] = v;
   } else if constexpr (EPI == 2) {
 #pragma unroll

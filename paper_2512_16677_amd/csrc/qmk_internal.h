@@ -22,6 +22,8 @@ constexpr int kGroupMaxAo = 120;
 constexpr int kPointPad = 256;      // points are padded to a multiple of this
 constexpr int kAoPad = 128;         // AOs (K) padded to a multiple of this
 constexpr int kMoPad = 128;         // MOs (N) padded to a multiple of this
+// Coefficients per row of the Jastrow weight polynomials (degree <= 8).
+constexpr int kJasCoef = 9;
 constexpr int kSparseChunk = 16;    // AOs per chunk of the screened product's bitmap
 constexpr int kSparseMaxStages = 1024;  // K stages a screened product can list (K <= 16384)
 
@@ -140,16 +142,17 @@ struct GemmArgs {
   const int32_t* perm;
   int64_t act_words;
   // Three-body Jastrow product only (FP64, batch c = walker, split s = power
-  // k of the rescaled e-e distance): row i of the product is (m = 1 + i /
-  // j_nn, nucleus a = i % j_nn), column j an electron.  jx[c][a][j] holds
-  // x = exp(-kappa |r_j - R_a|) (N per nucleus), jq[s][m-1][a][0..j_deg] the
-  // coefficients of the polynomial in x that weighs output (i, j).  Each wave
-  // stores the weighted sum of its outputs in its own slot of D (see the
-  // product's epilogue).
+  // k of the rescaled e-e distances rt, which B holds with the diagonal
+  // marked < 0): row i of the product is (m = 1 + i / j_nn, nucleus
+  // a = i % j_nn), column j an electron.  jx[c][a][j] holds
+  // x = exp(-kappa |r_j - R_a|) (N per nucleus), jq[s][m-1][a][0..kJasCoef)
+  // the coefficients (ascending powers, zero-padded) of the polynomial in x
+  // that weighs output (i, j).  Each wave stores the weighted sum of its
+  // outputs in its own slot of D (see the product's epilogue).
   const double* jx;
   const double* jq;
   int64_t j_nn;
-  int32_t j_deg, j_mh;
+  int32_t j_mh;
 };
 
 // Tile of workgroup `bid` of a grid launch; false if it has none.  The
@@ -244,8 +247,8 @@ hipError_t launch_det_adj(int n, int64_t batch, const double* A, double* det, do
 // Three-body Jastrow pieces (jastrow_kernels.hip; see there for layouts).
 hipError_t launch_een_en(const PointArgs& pts, int64_t ne, const double* nuc, int64_t nn, double kappa, int mh,
                          double* ra, double* x, hipStream_t s);
-hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, double kappa, int nord, int nsplit, const double* x,
-                         const double* q0, int64_t nn, double* rt, double* j0, hipStream_t s);
+hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, const double* nuc, int64_t nn, double kappa, int nord,
+                         const double* q0, double* rt, double* j0, hipStream_t s);
 hipError_t launch_een_finish(const double* part, int64_t slots, const double* j0, int64_t nw, int64_t ne,
                              double* J, hipStream_t s);
 // The Jastrow product with its fused weighted reduction (FP64).
