@@ -1054,6 +1054,7 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   QMK_HIP(ctx, ctx->een_x.ensure(static_cast<size_t>(P * nn) * 8), "alloc rescaled e-n distances");
   QMK_HIP(ctx, ctx->een_rt.ensure(static_cast<size_t>(nw * ne * ne) * 8), "alloc rescaled e-e distances");
   QMK_HIP(ctx, ctx->een_j0.ensure(static_cast<size_t>(P) * 8), "alloc per-electron parts");
+  QMK_HIP(ctx, ctx->een_g0.ensure(static_cast<size_t>(P * 7) * 8), "alloc m = 0 weight sums");
   QMK_HIP(ctx, ctx->een_q.ensure((q.size() + q0.size()) * 8), "alloc weight polynomials");
   double* const d_q = ctx->een_q.as<double>();
   double* const d_q0 = d_q + q.size();
@@ -1073,8 +1074,8 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
     QMK_HIP(ctx, launch_een_en(pa, ne, ctx->d_nuc_xyz.as<double>(), nn, kappa, mh, ctx->een_ra.as<double>(),
                                ctx->een_x.as<double>(), s),
             "Jastrow e-n distances");
-    QMK_HIP(ctx, launch_een_ee(pa, ne, ctx->d_nuc_xyz.as<double>(), nn, kappa, static_cast<int>(nord), d_q0,
-                               ctx->een_rt.as<double>(), ctx->een_j0.as<double>(), s),
+    QMK_HIP(ctx, launch_een_ee(pa, ne, nn, kappa, static_cast<int>(nord), ctx->een_x.as<double>(), d_q0,
+                               ctx->een_g0.as<double>(), ctx->een_rt.as<double>(), ctx->een_j0.as<double>(), s),
             "Jastrow e-e distances");
   }
   // part[w, k][slot] = weighted sums over the slot's outputs of

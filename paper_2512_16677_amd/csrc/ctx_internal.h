@@ -136,8 +136,9 @@ struct qmk_ctx_s {
   qmk::CuspArgs cusp{};
 
   // three-body Jastrow: operands of the product, rescaled e-n distances,
-  // per-electron parts, weight polynomials and per-wave partial sums
-  DevBuf een_ra, een_x, een_rt, een_j0, een_q, een_part;
+  // per-electron parts and m = 0 weight sums, weight polynomials and
+  // per-wave partial sums
+  DevBuf een_ra, een_x, een_rt, een_j0, een_g0, een_q, een_part;
 
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
   int64_t gbar_Pp = 0, gbar_Kp = 0;

@@ -12,6 +12,7 @@
 // Per walker:
 //   een_en      Ra[p][(m-1) nn + a] = Rt_pa^m (m = 1..mh), the left operand of
 //               the product, and x[w][a][i] = Rt_ia;
+//   een_g0      the nucleus sums of the m = 0 weights per electron;
 //   een_ee      rt[w][i][j] (diagonal marked), the right operand, plus the
 //               m = 0 part of J for electron i;
 //   the product (gemm_body, EPI 5) forms P^{k,m} for m >= 1 on MFMA, taking
@@ -66,19 +67,57 @@ __global__ __launch_bounds__(256) void een_en_kernel(PointArgs pts, int64_t ne, 
   }
 }
 
-// Block = (walker w, 16 electrons i); each wave takes 4 of them, its lanes
-// run over the electrons j and then over the nuclei, whose coordinates are
-// staged in LDS in chunks.  Writes rt[w][i][j] = exp(-kappa r_ij), -1 on the
-// diagonal (the product takes powers and maps the diagonal to zero), and
-// j0[w][i] = sum_{k=1}^{nord-1} (sum_{j != i} rt_ij^k) sum_a w_{k,0,a}(Rt_ia),
-// the polynomial coefficients in q0[k-1][a][0..nord].
-constexpr int kEeRows = 4, kEeChunk = 512;
-__global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, const double* __restrict__ nuc,
-                                                     int64_t nn, double kappa, int nord,
-                                                     const double* __restrict__ q0, double* __restrict__ rt,
+// One thread per point p = (walker w, electron i):
+//   g0[p][k-1] = sum_a w_{k,0,a}(x[w][a][i]),  k = 1..NORD-1,
+// with the polynomial coefficients q0[k-1][a][0..NORD] staged in LDS for 64
+// nuclei at a time.
+constexpr int kG0Chunk = 64;
+template <int NORD>
+__global__ __launch_bounds__(256) void een_g0_kernel(const double* __restrict__ x, int64_t P, int64_t ne, int64_t nn,
+                                                     const double* __restrict__ q0, double* __restrict__ g0) {
+  constexpr int NQ = (NORD - 1) * (NORD + 1);
+  __shared__ double qs[kG0Chunk * NQ];
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool valid = p < P;
+  const int64_t w = valid ? p / ne : 0, i = valid ? p - w * ne : 0;
+  double g[NORD - 1] = {};
+  for (int64_t a0 = 0; a0 < nn; a0 += kG0Chunk) {
+    const int an = static_cast<int>(min<int64_t>(kG0Chunk, nn - a0));
+    __syncthreads();
+    for (int t = threadIdx.x; t < an * NQ; t += blockDim.x) {
+      const int al = t / NQ, r = t - al * NQ;  // r = (k-1) (NORD+1) + e
+      const int k1 = r / (NORD + 1), e = r - k1 * (NORD + 1);
+      qs[t] = q0[(k1 * nn + a0 + al) * (NORD + 1) + e];
+    }
+    __syncthreads();
+    for (int al = 0; al < an; ++al) {
+      const double xv = valid ? x[(w * nn + a0 + al) * ne + i] : 0.0;
+      const double* q = qs + al * NQ;
+#pragma unroll
+      for (int k1 = 0; k1 < NORD - 1; ++k1) {
+        double pw = q[k1 * (NORD + 1) + NORD];
+#pragma unroll
+        for (int e = NORD - 1; e >= 0; --e) pw = pw * xv + q[k1 * (NORD + 1) + e];
+        g[k1] += pw;
+      }
+    }
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int k1 = 0; k1 < kMaxOrd - 1; ++k1) g0[p * (kMaxOrd - 1) + k1] = k1 < NORD - 1 ? g[k1] : 0.0;
+}
+
+// Block = (walker w, 16 electrons i); each wave takes 4 of them and its
+// lanes run over the electrons j, whose coordinates are staged in LDS in
+// chunks.  Writes rt[w][i][j] = exp(-kappa r_ij), -1 on the diagonal (the
+// product takes powers and maps the diagonal to zero), and
+//   j0[w][i] = sum_{k=1}^{nord-1} (sum_{j != i} rt_ij^k) g0[w][i][k-1]
+// (g0 from een_g0_kernel).
+constexpr int kEeRows = 2, kEeChunk = 512;
+__global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, double kappa, int nord,
+                                                     const double* __restrict__ g0, double* __restrict__ rt,
                                                      double* __restrict__ j0) {
   __shared__ double cs[3][kEeChunk];
-  __shared__ double gs[4][kEeRows][kMaxOrd];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nblk = (ne + 4 * kEeRows - 1) / (4 * kEeRows);
   const int64_t w = blockIdx.x / nblk, ib = (blockIdx.x - w * nblk) * 4 * kEeRows + wv * kEeRows;
@@ -90,49 +129,6 @@ __global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, 
     yi[r] = pts.coord[p * pts.s_pt + pts.s_ax];
     zi[r] = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
   }
-  // nuclei: G[r][k] = sum_a w_{k,0,a}(Rt_ia), kept in LDS per wave
-  {
-    double gk[kEeRows][kMaxOrd] = {};
-    for (int64_t c0 = 0; c0 < nn; c0 += kEeChunk) {
-      const int cn = static_cast<int>(min<int64_t>(kEeChunk, nn - c0));
-      __syncthreads();
-      for (int t = threadIdx.x; t < 3 * cn; t += blockDim.x) cs[t % 3][t / 3] = nuc[3 * c0 + t];
-      __syncthreads();
-      for (int t = lane; t < cn; t += 64) {
-        const int64_t a = c0 + t;
-        double x[kEeRows];
-#pragma unroll
-        for (int r = 0; r < kEeRows; ++r) {
-          const double dx = xi[r] - cs[0][t], dy = yi[r] - cs[1][t], dz = zi[r] - cs[2][t];
-          x[r] = exp(-kappa * sqrt(dx * dx + dy * dy + dz * dz));
-        }
-        for (int k = 1; k < nord; ++k) {
-          const double* q = q0 + ((k - 1) * nn + a) * (nord + 1);
-          double pw[kEeRows];
-#pragma unroll
-          for (int r = 0; r < kEeRows; ++r) pw[r] = q[nord];
-          for (int e = nord - 1; e >= 0; --e) {
-            const double qe = q[e];
-#pragma unroll
-            for (int r = 0; r < kEeRows; ++r) pw[r] = pw[r] * x[r] + qe;
-          }
-#pragma unroll
-          for (int r = 0; r < kEeRows; ++r)
-#pragma unroll
-            for (int kk = 1; kk < kMaxOrd; ++kk)
-              if (kk == k) gk[r][kk] += pw[r];
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kEeRows; ++r)
-#pragma unroll
-      for (int k = 1; k < kMaxOrd; ++k) {
-        const double g = wave_sum(gk[r][k]);
-        if (lane == 0) gs[wv][r][k] = g;
-      }
-  }
-  // electrons: rt row and S[r][k] = sum_{j != i} rt_ij^k
   double sk[kEeRows][kMaxOrd] = {};
   for (int64_t c0 = 0; c0 < ne; c0 += kEeChunk) {
     const int cn = static_cast<int>(min<int64_t>(kEeChunk, ne - c0));
@@ -147,30 +143,36 @@ __global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, 
     for (int t = lane; t < cn; t += 64) {
       const int64_t j = c0 + t;
       const double xj = cs[0][t], yj = cs[1][t], zj = cs[2][t];
+      // the rows are independent chains: no branch between them
+      double x[kEeRows];
+#pragma unroll
+      for (int r = 0; r < kEeRows; ++r) {
+        const double dx = xi[r] - xj, dy = yi[r] - yj, dz = zi[r] - zj;
+        x[r] = exp(-kappa * sqrt(dx * dx + dy * dy + dz * dz));
+      }
 #pragma unroll
       for (int r = 0; r < kEeRows; ++r) {
         const int64_t i = ib + r;
-        if (i >= ne) break;
-        const double dx = xi[r] - xj, dy = yi[r] - yj, dz = zi[r] - zj;
-        const double x = exp(-kappa * sqrt(dx * dx + dy * dy + dz * dz));
-        rt[(w * ne + i) * ne + j] = j == i ? -1.0 : x;
-        double v = j == i ? 0.0 : x;
+        const bool diag = j == i;
+        if (i < ne) rt[(w * ne + i) * ne + j] = diag ? -1.0 : x[r];
+        double v = diag ? 0.0 : x[r];
 #pragma unroll
         for (int k = 1; k < kMaxOrd; ++k) {
-          if (k >= nord) break;
-          sk[r][k] += v;
-          v *= x;
+          sk[r][k] += k < nord ? v : 0.0;
+          v *= x[r];
         }
       }
     }
   }
 #pragma unroll
   for (int r = 0; r < kEeRows; ++r) {
+    const int64_t i = min(ib + r, ne - 1);
+    const double* g = g0 + (w * ne + i) * (kMaxOrd - 1);
     double acc = 0.0;
 #pragma unroll
     for (int k = 1; k < kMaxOrd; ++k) {
       if (k >= nord) break;
-      acc += wave_sum(sk[r][k]) * gs[wv][r][k];
+      acc += wave_sum(sk[r][k]) * g[k - 1];
     }
     if (lane == 0 && ib + r < ne) j0[w * ne + ib + r] = acc;
   }
@@ -203,14 +205,25 @@ hipError_t launch_een_en(const PointArgs& pts, int64_t ne, const double* nuc, in
   return hipGetLastError();
 }
 
-hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, const double* nuc, int64_t nn, double kappa, int nord,
-                         const double* q0, double* rt, double* j0, hipStream_t s) {
+hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, int64_t nn, double kappa, int nord, const double* x,
+                         const double* q0, double* g0, double* rt, double* j0, hipStream_t s) {
   if (pts.P <= 0) return hipSuccess;
   if (nord < 2 || nord > kMaxOrd) return hipErrorInvalidValue;
+  const dim3 gg(static_cast<unsigned>((pts.P + 255) / 256));
+  switch (nord) {
+#define QMK_EEN_G0(n) \
+  case n:             \
+    hipLaunchKernelGGL(een_g0_kernel<n>, gg, dim3(256), 0, s, x, pts.P, ne, nn, q0, g0); \
+    break;
+    QMK_EEN_G0(2) QMK_EEN_G0(3) QMK_EEN_G0(4) QMK_EEN_G0(5) QMK_EEN_G0(6) QMK_EEN_G0(7) QMK_EEN_G0(8)
+#undef QMK_EEN_G0
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int64_t nw = pts.P / ne, g = nw * ((ne + 4 * kEeRows - 1) / (4 * kEeRows));
   if (g > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(een_ee_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, pts, ne, nuc, nn, kappa, nord,
-                     q0, rt, j0);
+  hipLaunchKernelGGL(een_ee_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, pts, ne, kappa, nord, g0, rt,
+                     j0);
   return hipGetLastError();
 }
 

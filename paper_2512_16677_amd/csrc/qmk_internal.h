@@ -247,8 +247,9 @@ hipError_t launch_det_adj(int n, int64_t batch, const double* A, double* det, do
 // Three-body Jastrow pieces (jastrow_kernels.hip; see there for layouts).
 hipError_t launch_een_en(const PointArgs& pts, int64_t ne, const double* nuc, int64_t nn, double kappa, int mh,
                          double* ra, double* x, hipStream_t s);
-hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, const double* nuc, int64_t nn, double kappa, int nord,
-                         const double* q0, double* rt, double* j0, hipStream_t s);
+// g0: scratch of 7 doubles per point.
+hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, int64_t nn, double kappa, int nord, const double* x,
+                         const double* q0, double* g0, double* rt, double* j0, hipStream_t s);
 hipError_t launch_een_finish(const double* part, int64_t slots, const double* j0, int64_t nw, int64_t ne,
                              double* J, hipStream_t s);
 // The Jastrow product with its fused weighted reduction (FP64).
