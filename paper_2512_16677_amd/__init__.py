@@ -314,8 +314,12 @@ class Context:
         import torch
         d = self.dims()
         cc = _np(c, np.float64)
+        if cc.ndim != 2 or cc.shape[1] != d["nucl_num"]:
+            raise ValueError("c must have shape [n_terms, nucl_num]")
         if out is None:
             out = torch.empty((d["walk_num"],), dtype=torch.float64, device=f"cuda:{self.device}")
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() < d["walk_num"]:
+            raise ValueError("out must be a contiguous float64 tensor of walk_num elements")
         self._check(self._lib.qmk_jastrow_een(self._h, int(nord), float(kappa), cc.shape[0], _ptr(cc),
                                               _ptr(out), _stream(stream)))
         return out

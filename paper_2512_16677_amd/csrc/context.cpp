@@ -1055,11 +1055,21 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   QMK_HIP(ctx, ctx->een_rt.ensure(static_cast<size_t>(nw * ne * ne) * 8), "alloc rescaled e-e distances");
   QMK_HIP(ctx, ctx->een_j0.ensure(static_cast<size_t>(P) * 8), "alloc per-electron parts");
   QMK_HIP(ctx, ctx->een_g0.ensure(static_cast<size_t>(P * 7) * 8), "alloc m = 0 weight sums");
-  QMK_HIP(ctx, ctx->een_q.ensure((q.size() + q0.size()) * 8), "alloc weight polynomials");
+  // the polynomial tables are uploaded only when the coefficients change
+  // (a blocking copy; the usual caller keeps c fixed over many steps)
+  std::vector<double> key(c, c + n_terms * nn);
+  key.push_back(static_cast<double>(nord));
+  if (key != ctx->een_key) {
+    // the previous call's kernels on this stream may still read the tables
+    QMK_HIP(ctx, hipStreamSynchronize(s), "wait for the previous Jastrow call");
+    QMK_HIP(ctx, ctx->een_q.ensure((q.size() + q0.size()) * 8), "alloc weight polynomials");
+    QMK_HIP(ctx, hipMemcpy(ctx->een_q.p, q.data(), q.size() * 8, hipMemcpyHostToDevice), "upload weight polynomials");
+    QMK_HIP(ctx, hipMemcpy(ctx->een_q.as<double>() + q.size(), q0.data(), q0.size() * 8, hipMemcpyHostToDevice),
+            "upload weight polynomials");
+    ctx->een_key = std::move(key);
+  }
   double* const d_q = ctx->een_q.as<double>();
   double* const d_q0 = d_q + q.size();
-  QMK_HIP(ctx, hipMemcpy(d_q, q.data(), q.size() * 8, hipMemcpyHostToDevice), "upload weight polynomials");
-  QMK_HIP(ctx, hipMemcpy(d_q0, q0.data(), q0.size() * 8, hipMemcpyHostToDevice), "upload weight polynomials");
   // per-wave partial sums of the product: slots per (walker, k) for a tile
   auto slots_of = [&](int cfg) -> int64_t {
     const TileCfg t = gemm_tile(Prec::kF64, cfg);

@@ -139,6 +139,7 @@ struct qmk_ctx_s {
   // per-electron parts and m = 0 weight sums, weight polynomials and
   // per-wave partial sums
   DevBuf een_ra, een_x, een_rt, een_j0, een_g0, een_q, een_part;
+  std::vector<double> een_key;  // coefficients and order behind een_q
 
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
   int64_t gbar_Pp = 0, gbar_Kp = 0;

@@ -122,3 +122,23 @@ def test_jastrow_een_rejects_bad_arguments():
         ctx.jastrow_een(3, 1.0, c, out=host)
     assert e.value.status == q.QMK_INVALID_ARG_BASE + 6
     ctx.close()
+
+
+def test_jastrow_een_new_coefficients_and_order_are_used():
+    """The coefficient tables are cached between calls: a change of c or of
+    the order must reach the kernels."""
+    q = qmk()
+    s = synth.water_like(walkers=4)
+    kappa = 0.8
+    ctx = q.Context.from_system(s)
+    for nord, seed in [(4, 1), (4, 2), (6, 3), (4, 1)]:
+        c = coefficients(nord, s.nucl_num, seed=seed)
+        j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+        ref, ref_abs = reference(s, kappa, nord, c)
+        assert np.all(np.abs(j - ref) <= 1e-12 * ref_abs), (nord, seed)
+    with pytest.raises(ValueError):
+        ctx.jastrow_een(4, kappa, coefficients(4, s.nucl_num + 1))
+    with pytest.raises(ValueError):
+        ctx.jastrow_een(4, kappa, coefficients(4, s.nucl_num), out=torch.empty(1, dtype=torch.float64,
+                                                                               device="cuda"))
+    ctx.close()
