@@ -40,9 +40,10 @@ __device__ __forceinline__ void split1(float x, __bf16& h, __bf16& l) {
   h = static_cast<__bf16>(x);
   l = static_cast<__bf16>(x - static_cast<float>(h));
 }
+// FP64 values are rounded to FP32 first (relative error 2^-24, far below
+// the 2^-18 of the split), so the residual is an FP32 subtraction.
 __device__ __forceinline__ void split1(double x, __bf16& h, __bf16& l) {
-  h = static_cast<__bf16>(static_cast<float>(x));
-  l = static_cast<__bf16>(static_cast<float>(x - static_cast<double>(static_cast<float>(h))));
+  split1(static_cast<float>(x), h, l);
 }
 
 // Source marker: values already split, hi plane at the operand pointer and
