@@ -142,3 +142,27 @@ def test_jastrow_een_new_coefficients_and_order_are_used():
         ctx.jastrow_een(4, kappa, coefficients(4, s.nucl_num), out=torch.empty(1, dtype=torch.float64,
                                                                                device="cuda"))
     ctx.close()
+
+
+def test_jastrow_een_many_electrons_and_nuclei_transposed_points():
+    """600 electrons (more than one 512-electron LDS chunk of the e-e
+    kernel), 70 nuclei (two 64-nucleus blocks of the e-n kernels), points
+    given transposed ([3][walk * elec], on the device); no basis is needed."""
+    q = qmk()
+    rng = np.random.default_rng(8)
+    nn, ne, W = 70, 600, 1
+    nucl = rng.uniform(-6.0, 6.0, size=(nn, 3))
+    elec = nucl[rng.integers(nn, size=(W, ne))] + rng.normal(size=(W, ne, 3))
+    nord, kappa = 5, 0.7
+    c = coefficients(nord, nn, seed=9)
+    ctx = q.Context()
+    ctx.set_nucleus(nucl)
+    pts = torch.from_numpy(np.ascontiguousarray(elec.reshape(-1, 3).T)).cuda()
+    ctx.set_point(pts, W, ne, transp="T")
+    j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+    ctx.close()
+    ref = oracle.jastrow_een(elec, nucl, kappa, nord, c)
+    ref_abs = oracle.jastrow_een(elec, nucl, kappa, nord, np.abs(c))
+    err = float(np.max(np.abs(j - ref) / ref_abs))
+    print(json.dumps({"ne": ne, "nn": nn, "jastrow_err": err}))
+    assert err <= 1e-12
