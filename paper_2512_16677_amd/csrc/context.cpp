@@ -1026,22 +1026,10 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   const int64_t nn = ctx->nucl_num, nw = ctx->walk_num, ne = ctx->elec_num, P = ctx->P();
   for (int64_t i = 0; i < n_terms * nn; ++i)
     if (!std::isfinite(c[i])) return fail(ctx, QMK_NONFINITE, "non-finite Jastrow coefficient");
-  // Terms grouped by (k, m): the coefficient of x^e in the weight of
-  // P^{k,m}_{ia} is c[t][a] of the one term with that (k, m, e).  m >= 1
-  // needs k <= nord-2 and m <= nord/2 (the product's splits and rows);
-  // m = 0 needs k >= 1 (handled per electron).
+  // m >= 1 needs k <= nord-2 and m <= nord/2 (the product's splits and
+  // rows); m = 0 needs k >= 1 (handled per electron)
   const int nsplit = static_cast<int>(nord - 1), mh = static_cast<int>(nord / 2), deg = static_cast<int>(nord);
-  std::vector<double> q(static_cast<size_t>(nsplit * mh * nn * kJasCoef), 0.0);
-  std::vector<double> q0(static_cast<size_t>((nord - 1) * nn * (deg + 1)), 0.0);
-  for (int64_t t = 0; t < n_terms; ++t) {
-    const int k = kme[3 * t], m = kme[3 * t + 1], e = kme[3 * t + 2];
-    for (int64_t a = 0; a < nn; ++a) {
-      if (m == 0)
-        q0[((k - 1) * nn + a) * (deg + 1) + e] = c[t * nn + a];
-      else
-        q[((static_cast<int64_t>(k) * mh + (m - 1)) * nn + a) * kJasCoef + e] = c[t * nn + a];
-    }
-  }
+  const size_t nq = static_cast<size_t>(nsplit * mh * nn * kJasCoef);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (ctx->nuc_xyz_version != ctx->geom_version) {
     QMK_HIP(ctx, ctx->d_nuc_xyz.ensure(static_cast<size_t>(3 * nn) * 8), "alloc nuclei");
@@ -1060,6 +1048,19 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   std::vector<double> key(c, c + n_terms * nn);
   key.push_back(static_cast<double>(nord));
   if (key != ctx->een_key) {
+    // Terms grouped by (k, m): the coefficient of x^e in the weight of
+    // P^{k,m}_{ia} is c[t][a] of the one term with that (k, m, e).
+    std::vector<double> q(nq, 0.0);
+    std::vector<double> q0(static_cast<size_t>((nord - 1) * nn * (deg + 1)), 0.0);
+    for (int64_t t = 0; t < n_terms; ++t) {
+      const int k = kme[3 * t], m = kme[3 * t + 1], e = kme[3 * t + 2];
+      for (int64_t a = 0; a < nn; ++a) {
+        if (m == 0)
+          q0[((k - 1) * nn + a) * (deg + 1) + e] = c[t * nn + a];
+        else
+          q[((static_cast<int64_t>(k) * mh + (m - 1)) * nn + a) * kJasCoef + e] = c[t * nn + a];
+      }
+    }
     // the previous call's kernels on this stream may still read the tables
     QMK_HIP(ctx, hipStreamSynchronize(s), "wait for the previous Jastrow call");
     QMK_HIP(ctx, ctx->een_q.ensure((q.size() + q0.size()) * 8), "alloc weight polynomials");
@@ -1069,7 +1070,7 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
     ctx->een_key = std::move(key);
   }
   double* const d_q = ctx->een_q.as<double>();
-  double* const d_q0 = d_q + q.size();
+  double* const d_q0 = d_q + nq;
   // per-wave partial sums of the product: slots per (walker, k) for a tile
   auto slots_of = [&](int cfg) -> int64_t {
     const TileCfg t = gemm_tile(Prec::kF64, cfg);
