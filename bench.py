@@ -97,14 +97,20 @@ def run_gpu(s, mode: str, steps: int, warmup: int, bits: int, keep_outputs: bool
         step(i)
     torch.cuda.synchronize()
     ctx.set_timing(True)
+    # events between steps on the launch stream give the per-step spread
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
+    ev[0].record()
     for i in range(steps):
         step(i)
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timing = ctx.timing()
     ctx.set_timing(False)
     ms = (t1 - t0) * 1e3 / steps
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    timing["_step_ms"] = {"min": per[0], "median": per[len(per) // 2], "max": per[-1]}
     outs = None
     if keep_outputs:  # one more (untimed) step on the first coordinate set
         ctx.set_point(r0)
@@ -235,7 +241,19 @@ def cpu_baseline(walkers: int):
     dt = time.perf_counter() - t0
     return {"value": s.point_num / dt, "unit": "e-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{walkers} walkers x {s.elec_num} electrons of the same 800-AO/400-MO "
-                      f"system (forward + adjoint), {dt:.1f} s"}
+                      f"system (forward + adjoint), {dt:.1f} s", "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    """Model name of the host CPU (Linux), or an empty string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def run_batch(mols, mode, steps, warmup, bits, batched=True):
@@ -639,6 +657,7 @@ def main():
                                "forward + adjoint", "points_per_step": s.point_num,
                    "bits": bits, "mode": a.mode},
         "roofline": roof,
+        "step_ms_spread": timing.get("_step_ms"),
     }
     variants = {}
     for m in variants_list:
@@ -646,6 +665,7 @@ def main():
         peak_v = PEAKS[{"mixed_f32": "fp32_TFLOPs", "mixed_bf16x3": "bf16_TFLOPs", "fp64": "fp64_TFLOPs"}[m]]
         kv = kernel_roofline(s, m, vt)
         variants[m] = {"value": s.point_num / (vms * 1e-3), "unit": "e-evals/s", "ms_per_step": vms,
+                       "step_ms_spread": vt.get("_step_ms"),
                        "speedup_vs_primary": ms / vms, "bits": a.mixed_bits,
                        "mo_gemm_frac_of_peak": (kv["mo"]["TFLOPs"] * (3 if m == "mixed_bf16x3" else 1) / peak_v)
                        if "mo" in kv else None,
