@@ -19,11 +19,11 @@ OUT = os.path.join(HERE, "libqmk.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Per-unit code generation flags.  Unit 10 (the Jastrow product, whose
-# epilogue does arithmetic on the accumulators): accumulate in vector
-# registers, so that the accumulators are not copied between register files
-# on every K step and the 64x160 tile keeps two waves per SIMD.
-UNIT_FLAGS = {10: ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-unit code generation flags.  Units 7 and 10 (the density and Jastrow
+# products, whose epilogues do arithmetic on the accumulators): accumulate in
+# vector registers, so that the accumulators are not copied between register
+# files on every K step (and the large tiles do not spill).
+UNIT_FLAGS = {7: ["-mllvm", "-amdgpu-mfma-vgpr-form"], 10: ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 # (source, extra defines, object name): the MFMA product sources are compiled
 # once per (precision, product) unit so that their many tile instantiations
