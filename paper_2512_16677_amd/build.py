@@ -19,11 +19,15 @@ OUT = os.path.join(HERE, "libqmk.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Per-unit code generation flags.  Units 7 and 10 (the density and Jastrow
-# products, whose epilogues do arithmetic on the accumulators): accumulate in
-# vector registers, so that the accumulators are not copied between register
-# files on every K step (and the large tiles do not spill).
-UNIT_FLAGS = {7: ["-mllvm", "-amdgpu-mfma-vgpr-form"], 10: ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-unit code generation flags.  The FP32 products (units 4-6, whose FP32
+# accumulators are converted to FP64 on output), the density and Jastrow
+# products (units 7 and 10, whose epilogues do arithmetic on the
+# accumulators) and the BF16x3 units accumulate in vector registers, so that
+# the accumulators are not copied between register files on every K step (and
+# the large tiles do not spill).  The FP64 units store the accumulation
+# registers directly and are faster without it.
+VGPR_ACC = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+UNIT_FLAGS = {u: VGPR_ACC for u in (4, 5, 6, 7, 10)}
 
 # (source, extra defines, object name): the MFMA product sources are compiled
 # once per (precision, product) unit so that their many tile instantiations
@@ -35,7 +39,7 @@ SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [],
            ("gemm_kernels.hip", [], None), ("gemm_bf16.hip", [], None)]
 SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"] + UNIT_FLAGS.get(u, []), f"gemm_kernels_u{u}")
             for u in range(1, 11)]
-SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"], f"gemm_bf16_u{u}") for u in range(1, 4)]
+SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"] + VGPR_ACC, f"gemm_bf16_u{u}") for u in range(1, 4)]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
