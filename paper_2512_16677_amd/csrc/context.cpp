@@ -1128,8 +1128,10 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
     return launch_een_finish(ctx->een_part.as<double>(), nsplit * gc.oDz, ctx->een_j0.as<double>(), nw, ne,
                              j_een, s);
   };
+  // tuning key: the product's size and its batch count (walkers x powers),
+  // which decides how many tiles there are to spread over the CUs
   GemmProblem pb{GemmKind::kJastrow, Prec::kF64, 0, 0, M, ne, ne};
-  pb.nbatch = nsplit;
+  pb.nbatch = static_cast<int>(std::min<int64_t>(nw * nsplit, 0x7fffffff));
   int cfg = 0;
   if ((st = pick_tile(ctx, pb, s, enqueue, &cfg)) != QMK_OK) return st;
   QMK_HIP(ctx, enqueue(cfg), "Jastrow product");
