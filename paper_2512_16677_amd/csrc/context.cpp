@@ -628,10 +628,22 @@ qmk_status ensure_cusp(qmk_ctx ctx, hipStream_t s) {
   return QMK_OK;
 }
 
+// Precision a product of this kind runs in under the context's mode: the
+// Jastrow product is FP64 always; the density product has no BF16x3 form
+// and runs FP32 in that mode.
+Prec product_prec(qmk_ctx ctx, GemmKind kind) {
+  if (kind == GemmKind::kJastrow) return Prec::kF64;
+  const Prec p = gemm_prec(ctx);
+  return kind == GemmKind::kDensity && p == Prec::kBF16x3 ? Prec::kF32 : p;
+}
+
 qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
                      const std::function<hipError_t(int)>& enqueue, int* cfg) {
   const int forced = ctx->forced_tile[static_cast<int>(pb.kind)];
   if (forced >= 0) {
+    // a tile forced under another precision mode may not exist in this one
+    if (forced >= gemm_num_tiles(pb.prec) || !tile_feasible(pb.prec, forced))
+      return fail(ctx, QMK_INVALID_ARG_BASE + 3, "the forced tile does not exist for this product's precision");
     *cfg = forced;
     return QMK_OK;
   }
@@ -1220,11 +1232,9 @@ qmk_status qmk_set_tile(qmk_ctx ctx, int32_t kernel_class, int32_t tile) {
   if (kernel_class == QMK_KERNEL_DENSITY) kind = static_cast<int>(GemmKind::kDensity);
   if (kernel_class == QMK_KERNEL_JASTROW_P) kind = static_cast<int>(GemmKind::kJastrow);
   if (kind < 0) return bad_arg(ctx, 2, "kernel class has no tile choice");
-  if (tile < -1 || tile >= gemm_num_tiles(Prec::kF64)) return bad_arg(ctx, 3, "unknown tile");
-  if (tile >= 0 && !tile_feasible(Prec::kF64, tile) && kind == static_cast<int>(GemmKind::kJastrow))
-    return bad_arg(ctx, 3, "tile does not fit in LDS");  // the Jastrow product is FP64 in every mode
-  if (tile >= 0 && !tile_feasible(Prec::kF64, tile) && ctx->mode == QMK_FP64)
-    return bad_arg(ctx, 3, "tile does not fit in LDS");
+  const Prec prec = product_prec(ctx, static_cast<GemmKind>(kind));
+  if (tile < -1 || tile >= gemm_num_tiles(prec)) return bad_arg(ctx, 3, "unknown tile for this product's precision");
+  if (tile >= 0 && !tile_feasible(prec, tile)) return bad_arg(ctx, 3, "tile does not fit in LDS");
   ctx->forced_tile[kind] = tile;
   return QMK_OK;
 }

@@ -192,6 +192,7 @@ qmk_status ensure_coef(qmk_ctx ctx);
 qmk_status check_ready(qmk_ctx ctx, bool need_coef);
 PointArgs point_args(qmk_ctx ctx);
 Prec gemm_prec(qmk_ctx ctx);
+Prec product_prec(qmk_ctx ctx, GemmKind kind);
 bool w_vec_ok(const void* w, int64_t N, int w32);
 bool device_accessible(const void* p, int device);
 // Arguments of the product Gbar[k][c][p] = sum_n W[p][c][n] C[n][k] (the

@@ -60,3 +60,56 @@ def test_mixed_adjoint_error(mode):
     print(json.dumps({"mode": mode, "adjoint_vs_B24": e}))
     for k, v in e.items():
         assert v <= TOL[mode]["grad"], (k, v)
+
+
+@pytest.mark.parametrize("mode", list(TOL))
+def test_mixed_every_tile_shape(mode):
+    """Every tile shape of the mode's own table (the BF16x3 table has shapes
+    the FP64/FP32 one does not) gives the oracle's result at the stated
+    tolerance, forward and adjoint."""
+    import paper_2512_16677_amd as q
+    s = synth.medium(walkers=1)
+    w = synth.adjoint_weights(s, seed=5)
+    ref_mo = oracle.mo_vgl(s, B=24)
+    ref = oracle.adjoint(s, w, B=24)
+    wt = torch.from_numpy(w).cuda()
+    ctx = q.Context.from_system(s, bits=24, mode=mode)
+    tried = 0
+    for t in range(ctx.tile_count()):
+        try:
+            for k in ("mo", "gbar", "dcoef"):
+                ctx.set_tile(k, t)
+        except q.QmkError:
+            continue  # does not fit in LDS
+        tried += 1
+        mo = ctx.get_mo_vgl().cpu().numpy().reshape(-1, 5, s.mo_num)
+        e = component_errors(mo, ref_mo)
+        for k in ("value", "gradient", "laplacian"):
+            assert e[k] <= TOL[mode][k], (t, k, e[k])
+        g = ctx.adjoint(wt)
+        for k in ("d_coef", "d_elec", "d_nucl"):
+            err = grad_err(g[k].cpu().numpy().reshape(ref[k].shape), ref[k], ref[k + "_abs"])
+            assert err <= TOL[mode]["grad"], (t, k, err)
+    assert tried == ctx.tile_count()
+    ctx.close()
+
+
+def test_forced_tile_of_another_precision_is_an_error():
+    """A tile index forced in BF16x3 mode that the FP64 table does not have
+    is reported as an argument error after a switch to FP64, not launched."""
+    import paper_2512_16677_amd as q
+    s = synth.water_like(walkers=2)
+    ctx = q.Context.from_system(s, bits=24, mode="mixed_bf16x3")
+    n_bf = ctx.tile_count()
+    ctx.set_tile("mo", n_bf - 1)
+    ctx.get_mo_vgl()
+    ctx.set_precision(53, "fp64")
+    assert ctx.tile_count() < n_bf
+    with pytest.raises(q.QmkError) as e:
+        ctx.get_mo_vgl()
+    assert e.value.status == q.QMK_INVALID_ARG_BASE + 3
+    with pytest.raises(q.QmkError):
+        ctx.set_tile("mo", n_bf - 1)
+    ctx.set_tile("mo", -1)
+    ctx.get_mo_vgl()
+    ctx.close()
