@@ -1548,9 +1548,19 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     ga.act = ctx->d_act.as<uint32_t>();
     ga.act_words = ctx->act_words;
   };
-  const int w32 = w_dtype == QMK_F32;
+  int w32 = w_dtype == QMK_F32;
   const int f32 = ctx->f32_storage() ? 1 : 0;
   const Prec prec = gemm_prec(ctx);
+  if (!w32 && ctx->mode == QMK_MIXED_F32) {
+    // the FP32 products round W to FP32 as they load it; one streaming pass
+    // does the same rounding and halves the bytes both products read
+    const int64_t n = P * 5 * N;
+    QMK_HIP(ctx, ctx->w_f32.ensure(static_cast<size_t>(n) * 4), "alloc FP32 W");
+    LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
+    QMK_HIP(ctx, launch_f64_to_f32(static_cast<const double*>(w), ctx->w_f32.as<float>(), n, s), "convert W");
+    w = ctx->w_f32.p;
+    w32 = 1;
+  }
   if (scr) {
     // W in the sorted point order, once, so that both products read it with
     // their ordinary loaders

@@ -142,6 +142,7 @@ struct qmk_ctx_s {
   std::vector<double> een_key;  // coefficients and order behind een_q
 
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
+  DevBuf w_f32;  // FP32 copy of FP64 adjoint weights (FP32 mode)
   int64_t gbar_Pp = 0, gbar_Kp = 0;
   int gbar_f32 = -1;
 

@@ -113,3 +113,18 @@ def test_forced_tile_of_another_precision_is_an_error():
     ctx.set_tile("mo", -1)
     ctx.get_mo_vgl()
     ctx.close()
+
+
+def test_fp32_mode_rounds_fp64_weights_like_fp32_weights():
+    """In the FP32 mode FP64 weights are rounded to FP32 once before the
+    products, so they give exactly the gradients of their FP32-rounded
+    copy."""
+    import paper_2512_16677_amd as q
+    s = synth.medium(walkers=2)
+    w = synth.adjoint_weights(s, seed=3)
+    ctx = q.Context.from_system(s, bits=24, mode="mixed_f32")
+    g64 = {k: v.cpu().numpy() for k, v in ctx.adjoint(torch.from_numpy(w).cuda()).items()}
+    g32 = {k: v.cpu().numpy() for k, v in ctx.adjoint(torch.from_numpy(w.astype(np.float32)).cuda()).items()}
+    ctx.close()
+    for k in ("d_coef", "d_elec", "d_nucl"):
+        np.testing.assert_array_equal(g64[k], g32[k])
