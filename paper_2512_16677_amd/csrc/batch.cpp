@@ -134,8 +134,7 @@ std::vector<WorkItem> gemm_items(qmk_batch b, GemmKind kind, int cfg) {
     if (kind == GemmKind::kForward) {
       M = mp.P; N = mp.N; L = mp.K; nz = 5;
     } else if (kind == GemmKind::kGbar) {
-      const bool rows_k = b->prec != Prec::kBF16x3;  // see gbar_args
-      M = rows_k ? mp.K : mp.P; N = rows_k ? mp.P : mp.K; L = mp.N; nz = 5;
+      M = mp.K; N = mp.P; L = mp.N; nz = 5;  // rows k, columns p (gbar_args)
     } else {
       M = mp.N; N = mp.K; L = mp.chunk; nz = 5 * mp.nsplit;
     }

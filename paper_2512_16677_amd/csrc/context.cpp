@@ -671,22 +671,25 @@ GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void*
   g.nsplit = 1;
   g.nbatch = 5;
   if (prec == Prec::kBF16x3) {
-    // rows (p, c), columns k: both operands read along the reduction index n
-    g.A = w;
-    g.sAi = 5 * N;
+    // rows k, columns p (as below, so that Gbar is stored in full lines);
+    // both operands are read along the reduction index n, as this kernel
+    // needs
+    g.A = Ct_hi;  // C^T [k][n], split into bf16 hi + lo
+    g.A2 = Ct_lo;
+    g.sAi = Np;
     g.sAl = 1;
-    g.oAc = N;
-    g.B = Ct_hi;  // C^T [k][n], split into bf16 hi + lo
-    g.B2 = Ct_lo;
+    g.B = w;  // W [p][c][n]
     g.sBl = 1;
-    g.sBj = Np;
-    g.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
+    g.sBj = 5 * N;
+    g.oBc = N;
+    g.vec_ok = 1 | (w_vec_ok(w, N, w32) ? 2 : 0);
     g.D = gbar;
-    g.sDi = 1;
-    g.sDj = 5 * Pp;
+    g.sDi = 5 * Pp;
+    g.sDj = 1;
     g.oDz = Pp;
-    g.M = P;
-    g.N = K;
+    g.M = K;
+    g.N = P;
+    g.map_slab = 2;
     return g;
   }
   // rows k, columns p: consecutive accumulator lanes own consecutive points,

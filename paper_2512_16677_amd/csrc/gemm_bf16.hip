@@ -10,8 +10,8 @@
 // indices of one row of A and one column of B.  Operand tiles are staged in
 // LDS k-contiguous per row ([row][k], hi and lo planes):
 //   * an operand whose reduction index is contiguous in memory (W in the
-//     W C product, the AO array in the W^T ao product, the pre-split C) is
-//     read in runs of eight along k;
+//     W C product, the AO array in the W^T ao product, the pre-split C and
+//     C^T) is read in runs of eight along k;
 //   * an operand whose rows are contiguous (the AO array in the forward
 //     product, W^T in the W^T ao product) is read as 2-row x 8-k
 //     micro-tiles (coalesced along the rows) and transposed in registers
@@ -469,8 +469,8 @@ hipError_t bf16_unit_fwd(int cfg, const GemmArgs* g, const BfPersist* pl, int w3
 hipError_t bf16_unit_gbar(int cfg, const GemmArgs* g, const BfPersist* pl, int w32, int o32,
                           hipStream_t s) {
   const bool alt = w32 != 0;
-  if (pl) return alt ? run_bf_persist<float, true, PreSplit, float>(cfg, *pl, s) : run_bf_persist<double, true, PreSplit, float>(cfg, *pl, s);
-  return alt ? run_bf<float, true, PreSplit, float>(cfg, *g, s) : run_bf<double, true, PreSplit, float>(cfg, *g, s);
+  if (pl) return alt ? run_bf_persist<PreSplit, true, float, float>(cfg, *pl, s) : run_bf_persist<PreSplit, true, double, float>(cfg, *pl, s);
+  return alt ? run_bf<PreSplit, true, float, float>(cfg, *g, s) : run_bf<PreSplit, true, double, float>(cfg, *g, s);
 }
 #endif
 #if QMK_GEMM_UNIT == 3
@@ -500,7 +500,7 @@ size_t gemm_bf16_tile_lds_bytes(int cfg) {
 }
 
 // forward: A = AO array (FP32, rows contiguous), B = C split (k contiguous)
-// Gbar:    A = W (k contiguous),                 B = C^T split (k contiguous)
+// Gbar:    A = C^T split (k contiguous),         B = W (k contiguous)
 // dC:      A = W^T (rows contiguous),            B = AO array (k contiguous)
 namespace {
 hipError_t bf16_dispatch(GemmKind kind, int cfg, const GemmArgs* g, const BfPersist* pl, int w32,
