@@ -14,6 +14,8 @@
 // early exit over the ascending exponents.  Reductions are deterministic:
 // per-wave nucleus sums are written to a partial array and summed in a
 // fixed order by a second kernel.
+#include <type_traits>
+
 #include "qmk_internal.h"
 
 namespace qmk {
@@ -28,29 +30,47 @@ namespace {
 //                    + ((8l+20) d_i P + 4 u P_i) g2 + 8 u d_i P g3)
 // Summed against Gbar as  sum_j Gj d_i d_j chi  =  M (g0 (Hess P . G)_i
 //   + 2 g1 (P_i (G.d) + d_i (G.grad P) + G_i P) + 4 g2 d_i P (G.d)).
+// The Cartesian components run in one flat loop.  FP64 Gbar: the five
+// values of a component are loaded one component ahead (those of the first
+// component before the radial sums, by the caller), so that their latency
+// overlaps the arithmetic (1.19 -> 1.08 ms at 800 AOs x 143,360 points).
+// FP32 Gbar is loaded where it is used (1.12 -> 0.82 ms with the flat loop;
+// loading it ahead made it slower, 1.25 ms).
+template <typename GT>
+__device__ __forceinline__ void load_gbar(const GT* __restrict__ q, int64_t sC, double* G) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) G[c] = static_cast<double>(q[c * sC]);
+}
+
 template <typename GT>
 __device__ __forceinline__ void shell_adjoint(int l, double dx, double dy, double dz, double u,
                                               double g0, double g1, double g2, double g3,
                                               const double* __restrict__ M,
                                               const GT* __restrict__ gb, int64_t sK, int64_t sC,
-                                              double& tx, double& ty, double& tz) {
+                                              const double* G_first, double& tx, double& ty, double& tz) {
   const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
   const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
   const double c1 = 4.0 * l + 6.0, c2 = 8.0 * l + 20.0;
   const double tg1 = 2.0 * g1, fg2 = 4.0 * g2, eug3 = 8.0 * u * g3, fug2 = 4.0 * u * g2;
-  int idx = 0;
+  // components (a, b, c) with a descending, then b descending
+  const int ncart = (l + 1) * (l + 2) / 2;
+  constexpr bool kAhead = std::is_same<GT, double>::value;
+  double Gc[5] = {G_first[0], G_first[1], G_first[2], G_first[3], G_first[4]};
+  int a = l, b = 0;
 #pragma unroll 1
-  for (int a = l; a >= 0; --a) {
-#pragma unroll 1
-    for (int b = l - a; b >= 0; --b, ++idx) {
+  for (int idx = 0; idx < ncart; ++idx) {
+    {
+      double Gn[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      if constexpr (kAhead) {
+        if (idx + 1 < ncart) load_gbar(gb + (idx + 1) * sK, sC, Gn);
+      } else {
+        load_gbar(gb + idx * sK, sC, Gc);
+      }
       const int c = l - a - b;
       const AxisD X = axis_derivs(a, dx, dx2, dx3);
       const AxisD Y = axis_derivs(b, dy, dy2, dy3);
       const AxisD Z = axis_derivs(c, dz, dz2, dz3);
-      const GT* q = gb + idx * sK;
-      const double G0 = static_cast<double>(q[0]), G1 = static_cast<double>(q[sC]),
-                   G2 = static_cast<double>(q[2 * sC]), G3 = static_cast<double>(q[3 * sC]),
-                   G4 = static_cast<double>(q[4 * sC]);
+      const double G0 = Gc[0], G1 = Gc[1], G2 = Gc[2], G3 = Gc[3], G4 = Gc[4];
       const double P = X.v0 * Y.v0 * Z.v0;
       const double Px = X.v1 * Y.v0 * Z.v0, Py = X.v0 * Y.v1 * Z.v0, Pz = X.v0 * Y.v0 * Z.v1;
       const double Pxx = X.v2 * Y.v0 * Z.v0, Pyy = X.v0 * Y.v2 * Z.v0, Pzz = X.v0 * Y.v0 * Z.v2;
@@ -76,6 +96,14 @@ __device__ __forceinline__ void shell_adjoint(int l, double dx, double dy, doubl
       tz += m * (G0 * (Pz * g0 + dz * P * tg1) + g0 * HGz + tg1 * (Pz * Gd + dz * GdP + G3 * P) +
                  dz * Pg + G4 * (lPz * g0 + (2.0 * dz * lapP + c1 * Pz) * g1 + dz * Pl + fug2 * Pz +
                                  dz * Pe));
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Gc[q] = Gn[q];
+    }
+    if (b > 0) {
+      --b;
+    } else {
+      --a;
+      b = l - a;
     }
   }
 }
@@ -130,6 +158,8 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
       for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
         const ShellDev sh = s_shell[s];
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        double G_first[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (std::is_same<GT, double>::value && near) load_gbar(gb_p + sh.ao_off * sK, sC, G_first);
         for (int k = sh.p_begin; k < sh.p_end; ++k) {
           const PrimDev pr = s_prim[k];
           const double x = pr.gamma * u;
@@ -146,7 +176,7 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
         }
         if (near)
           shell_adjoint(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2, g3,
-                        t.ao_factor + sh.ao_off, gb_p + sh.ao_off * sK, sK, sC, tx, ty, tz);
+                        t.ao_factor + sh.ao_off, gb_p + sh.ao_off * sK, sK, sC, G_first, tx, ty, tz);
       }
     }
     ex += tx;
