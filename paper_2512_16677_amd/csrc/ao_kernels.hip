@@ -40,11 +40,12 @@ __device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz
   const double tg1 = 2.0 * g1;
   const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
   const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
-  int idx = 0;
+  // components (a, b, c) with a descending, then b descending, in one loop
+  const int ncart = (l + 1) * (l + 2) / 2;
+  int a = l, b = 0;
 #pragma unroll 1
-  for (int a = l; a >= 0; --a) {
-#pragma unroll 1
-    for (int b = l - a; b >= 0; --b, ++idx) {
+  for (int idx = 0; idx < ncart; ++idx) {
+    {
       const int c = l - a - b;
       const AxisD X = axis_derivs(a, dx, dx2, dx3);
       const AxisD Y = axis_derivs(b, dy, dy2, dy3);
@@ -60,6 +61,12 @@ __device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz
       st(q + 2 * sC, m * (X.v0 * Y.v1 * Z.v0 * g0 + dy * tp));
       st(q + 3 * sC, m * (X.v0 * Y.v0 * Z.v1 * g0 + dz * tp));
       st(q + 4 * sC, m * (lapP * g0 + P * lapr));
+    }
+    if (b > 0) {
+      --b;
+    } else {
+      --a;
+      b = l - a;
     }
   }
 }
