@@ -168,7 +168,7 @@ def measured_traffic(mode: str, name: str):
     hardware-counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what
     the counter reads for a plain copy of known size).  None when the summary
     has no entry or the kernel's sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if name not in KERNEL_SOURCES or not os.path.exists(TRAFFIC_FILE):
         return None
     want = sources_digest(name)
     with open(TRAFFIC_FILE) as fh:
