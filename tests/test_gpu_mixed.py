@@ -128,3 +128,22 @@ def test_fp32_mode_rounds_fp64_weights_like_fp32_weights():
     ctx.close()
     for k in ("d_coef", "d_elec", "d_nucl"):
         np.testing.assert_array_equal(g64[k], g32[k])
+
+
+def test_fp32_mode_accepts_unaligned_fp64_weights():
+    """W as a contiguous view that starts one element into its storage (8-byte
+    but not 32-byte aligned) takes the conversion's element-wise path and
+    gives the gradients of an aligned copy."""
+    import paper_2512_16677_amd as q
+    s = synth.water_like(walkers=3)
+    w = synth.adjoint_weights(s, seed=6)
+    base = torch.zeros(w.size + 1, dtype=torch.float64, device="cuda")
+    base[1:] = torch.from_numpy(w.reshape(-1)).cuda()
+    w_view = base[1:].view(w.shape)
+    assert w_view.data_ptr() % 32 != 0
+    ctx = q.Context.from_system(s, bits=24, mode="mixed_f32")
+    g1 = {k: v.cpu().numpy() for k, v in ctx.adjoint(w_view).items()}
+    g2 = {k: v.cpu().numpy() for k, v in ctx.adjoint(torch.from_numpy(w).cuda()).items()}
+    ctx.close()
+    for k in ("d_coef", "d_elec", "d_nucl"):
+        np.testing.assert_array_equal(g1[k], g2[k])
