@@ -130,7 +130,13 @@ qmk_status qmk_set_mo_coef(qmk_ctx ctx, int64_t mo_num, int64_t ao_num, const do
  * copied now; = 1: device memory, NOT copied -- it must hold the
  * coordinates until the last get/adjoint call that uses them has run on its
  * stream.  Increments the context's time stamp (Section 2.2), so the next
- * get recomputes every intermediate that depends on the points. */
+ * get recomputes every intermediate that depends on the points.
+ * coord must hold 3 * walk_num * elec_num values: the library cannot check
+ * the length of a plain pointer.  Errors (the context keeps its previous
+ * points): QMK_INVALID_ARG_BASE + 2 (transp), + 3 (walk_num < 1, or more than
+ * 2^31 points), + 4 (elec_num < 1), + 5 (NULL, or a device pointer this
+ * device cannot access), + 6 (coord_on_device not 0 or 1); QMK_NONFINITE
+ * for a non-finite host coordinate. */
 qmk_status qmk_set_point(qmk_ctx ctx, char transp, int64_t walk_num, int64_t elec_num,
                          const double* coord, int32_t coord_on_device);
 

@@ -217,7 +217,14 @@ class Context:
         if walk_num is None or elec_num is None:
             if transp != "N" or len(shape) != 3:
                 raise ValueError("give walk_num and elec_num for this layout")
+            if shape[2] != 3:
+                raise ValueError("coordinates must have shape [walk, elec, 3]")
             walk_num, elec_num = shape[0], shape[1]
+        # the library reads 3 walk_num elec_num values through a plain pointer
+        size = int(np.prod(shape, dtype=np.int64))
+        if size != 3 * int(walk_num) * int(elec_num):
+            raise ValueError(f"coordinates hold {size} values, 3 * walk_num * elec_num = "
+                             f"{3 * int(walk_num) * int(elec_num)} expected")
         if isinstance(coord, np.ndarray):
             c = _np(coord, np.float64)
             self._check(self._lib.qmk_set_point(self._h, transp.encode(), int(walk_num),
@@ -295,6 +302,8 @@ class Context:
             return
         z = _np(charge, np.float64).reshape(-1)
         r = _np(r_cusp, np.float64).reshape(-1)
+        if z.shape != r.shape:
+            raise ValueError("charge and r_cusp must have one value per nucleus each")
         self._check(self._lib.qmk_set_mo_cusp(self._h, r.shape[0], _ptr(z), _ptr(r)))
 
     def set_screening(self, enable: bool = True):
@@ -378,6 +387,16 @@ class Context:
             res["d_elec"] = torch.empty((d["walk_num"], d["elec_num"], 3), dtype=torch.float64, device=dev)
         if d_nucl and "d_nucl" not in res:
             res["d_nucl"] = torch.empty((d["nucl_num"], 3), dtype=torch.float64, device=dev)
+        # the library writes these through plain pointers: check them here
+        sizes = {"d_coef": d["mo_num"] * d["ao_num"], "d_elec": d["walk_num"] * d["elec_num"] * 3,
+                 "d_nucl": d["nucl_num"] * 3}
+        for k, t in res.items():
+            if k not in sizes:
+                raise ValueError(f"unknown output {k!r}")
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64):
+                raise ValueError(f"{k} must be a contiguous CUDA float64 tensor")
+            if t.numel() != sizes[k]:
+                raise ValueError(f"{k} holds {t.numel()} values, {sizes[k]} expected")
         self._check(self._lib.qmk_mo_vgl_adjoint(
             self._h, _ptr(w), QMK_F32 if w.dtype == torch.float32 else QMK_F64,
             _ptr(res.get("d_coef")), _ptr(res.get("d_elec")), _ptr(res.get("d_nucl")),

@@ -164,6 +164,47 @@ def test_error_codes():
     ctx.close()
 
 
+def test_empty_points_and_wrong_buffer_sizes_are_rejected():
+    """Empty point sets are argument errors that leave the context's points in
+    place; coordinate arrays and adjoint outputs whose size does not match the
+    dimensions never reach the library (it reads and writes them through plain
+    pointers); nothing is launched for any of them."""
+    import ctypes
+    q = qmk()
+    s = synth.water_like(walkers=2)
+    ctx = q.Context.from_system(s)
+    ref = ctx.get_mo_vgl().cpu().numpy()
+    n0 = ctx.launch_count()
+    for shape, status in [((0, s.elec_num, 3), q.QMK_INVALID_ARG_BASE + 3),
+                          ((s.walk_num, 0, 3), q.QMK_INVALID_ARG_BASE + 4)]:
+        with pytest.raises(q.QmkError) as e:
+            ctx.set_point(np.zeros(shape))
+        assert e.value.status == status
+    pts = torch.from_numpy(np.ascontiguousarray(s.elec_coord.reshape(-1, 3).T)).cuda()
+    with pytest.raises(ValueError):
+        ctx.set_point(pts[:, :-1].contiguous(), s.walk_num, s.elec_num, transp="T")
+    with pytest.raises(ValueError):
+        ctx.set_point(s.elec_coord[:, :, :2].copy())
+    with pytest.raises(ValueError):
+        ctx.set_point(s.elec_coord.reshape(-1)[:-3].copy(), s.walk_num, s.elec_num)
+    # more than 2^31 points: refused before the pointer is used
+    assert ctx._lib.qmk_set_point(ctx._h, b"T", 1 << 16, (1 << 15) + 1,
+                                  ctypes.c_void_p(pts.data_ptr()), 1) == q.QMK_INVALID_ARG_BASE + 3
+    w = torch.ones((s.walk_num, s.elec_num, 5, s.mo_num), dtype=torch.float64, device="cuda")
+    for bad in [{"d_coef": torch.empty(3, dtype=torch.float64, device="cuda")},
+                {"d_elec": torch.empty((s.walk_num, s.elec_num, 3), dtype=torch.float32, device="cuda")},
+                {"d_nucl": torch.empty((s.nucl_num, 3), dtype=torch.float64)},
+                {"d_x": torch.empty(3, dtype=torch.float64, device="cuda")}]:
+        with pytest.raises(ValueError):
+            ctx.adjoint(w, out=bad)
+    with pytest.raises(ValueError):
+        ctx.set_mo_cusp(np.ones(s.nucl_num), np.ones(s.nucl_num - 1))
+    assert ctx.launch_count() == n0
+    np.testing.assert_array_equal(ctx.get_mo_vgl().cpu().numpy(), ref)
+    assert ctx.dims()["walk_num"] == s.walk_num
+    ctx.close()
+
+
 # ---------------------------------------------------------------- adjoint
 @pytest.mark.parametrize("system", ["water_like", "medium"])
 def test_adjoint_matches_oracle(system):
