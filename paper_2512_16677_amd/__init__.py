@@ -201,12 +201,23 @@ class Context:
         pf = None if prim_factor is None else _np(prim_factor, np.float64)
         sf = None if shell_factor is None else _np(shell_factor, np.float64)
         af = None if ao_factor is None else _np(ao_factor, np.float64)
+        # the library takes shell_num and prim_num from two of the arrays and
+        # reads the others at those lengths: check them here
+        n_sh, n_pr = sl.size, ex.size
+        n_ao = int(sum((l + 1) * (l + 2) // 2 for l in np.clip(sl.reshape(-1), 0, None)))
+        for name, a, n in [("shell_nucleus", sn, n_sh), ("shell_prim_offset", so, n_sh + 1),
+                           ("coefficient", co, n_pr), ("prim_factor", pf, n_pr),
+                           ("shell_factor", sf, n_sh), ("ao_factor", af, n_ao)]:
+            if a is not None and a.size != n:
+                raise ValueError(f"{name} holds {a.size} values, {n} expected")
         self._check(self._lib.qmk_set_basis(self._h, sl.shape[0], ex.shape[0], _ptr(sn), _ptr(sl),
                                             _ptr(so), _ptr(ex), _ptr(co), _ptr(pf), _ptr(sf),
                                             _ptr(af)))
 
     def set_mo_coef(self, coef):
         c = _np(coef, np.float64)
+        if c.ndim != 2:
+            raise ValueError("coef must have shape [mo_num, ao_num]")
         self._check(self._lib.qmk_set_mo_coef(self._h, c.shape[0], c.shape[1], _ptr(c)))
 
     def set_point(self, coord, walk_num: Optional[int] = None, elec_num: Optional[int] = None,

@@ -199,6 +199,17 @@ def test_empty_points_and_wrong_buffer_sizes_are_rejected():
             ctx.adjoint(w, out=bad)
     with pytest.raises(ValueError):
         ctx.set_mo_cusp(np.ones(s.nucl_num), np.ones(s.nucl_num - 1))
+    with pytest.raises(ValueError):
+        ctx.set_basis(s.shell_nucleus, s.shell_ang_mom, s.shell_prim_offset[:-1], s.exponent,
+                      s.coefficient)
+    with pytest.raises(ValueError):
+        ctx.set_basis(s.shell_nucleus, s.shell_ang_mom, s.shell_prim_offset, s.exponent,
+                      s.coefficient[:-1])
+    with pytest.raises(ValueError):
+        ctx.set_basis(s.shell_nucleus, s.shell_ang_mom, s.shell_prim_offset, s.exponent,
+                      s.coefficient, ao_factor=np.ones(s.ao_num + 1))
+    with pytest.raises(ValueError):
+        ctx.set_mo_coef(s.mo_coef.reshape(-1))
     assert ctx.launch_count() == n0
     np.testing.assert_array_equal(ctx.get_mo_vgl().cpu().numpy(), ref)
     assert ctx.dims()["walk_num"] == s.walk_num
