@@ -166,3 +166,28 @@ def test_jastrow_een_many_electrons_and_nuclei_transposed_points():
     err = float(np.max(np.abs(j - ref) / ref_abs))
     print(json.dumps({"ne": ne, "nn": nn, "jastrow_err": err}))
     assert err <= 1e-12
+
+
+def test_jastrow_een_full_size_sampled():
+    """The timed Jastrow workload at its full size (medium molecule: 80 nuclei,
+    280 electrons; 512 walkers; order 5, kappa 0.6, the same seeded
+    coefficients), in the launch configuration that is timed; the oracle
+    checks the first, a middle and the last walker.  Every J is finite and a
+    repeated call gives the same bits."""
+    q = qmk()
+    nord, kappa = 5, 0.6
+    s = synth.medium(walkers=512)
+    c = np.random.default_rng(0).normal(scale=0.2, size=(q.jastrow_een_terms(nord), s.nucl_num))
+    ctx = q.Context.from_system(s)
+    j = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+    j2 = ctx.jastrow_een(nord, kappa, c).cpu().numpy()
+    ctx.close()
+    assert np.all(np.isfinite(j))
+    np.testing.assert_array_equal(j, j2)
+    idx = [0, 257, 511]
+    elec = s.elec_coord[idx]
+    ref = oracle.jastrow_een(elec, s.nucl_coord, kappa, nord, c)
+    ref_abs = oracle.jastrow_een(elec, s.nucl_coord, kappa, nord, np.abs(c))
+    err = float(np.max(np.abs(j[idx] - ref) / ref_abs))
+    print(json.dumps({"walkers": s.walk_num, "sampled": idx, "jastrow_err": err}))
+    assert err <= 1e-12
