@@ -60,3 +60,45 @@ def test_det_errors_and_empty_batch():
             c.det_adj(torch.zeros((2, n, n), dtype=torch.float64, device="cuda"))
         assert e.value.status == q.QMK_INVALID_ARG_BASE + 2
     c.close()
+
+
+@pytest.mark.parametrize("n,batch", [(2, 1 << 24), (3, 1 << 24), (4, 1 << 24), (16, 1 << 16)])
+def test_full_size_sampled_and_adjugate_identity(n, batch):
+    """The timed determinant workload at full size (standard-normal matrices
+    drawn on the device): sampled matrices (the first, the last and 62 in
+    between) against the oracle, and A adj(A) = det(A) I for every matrix of
+    the batch.  For n <= 4 the residual bound follows the cofactor error
+    bound used above (Hadamard scales); for the LU path it is the backward
+    error form c n u |A| |adj| with growth allowed for, and the sampled
+    comparison is scaled by the condition number."""
+    c = ctx()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3 + n)
+    A = torch.randn((batch, n, n), generator=g, device="cuda", dtype=torch.float64)
+    det, adj = c.det_adj(A)
+    c.close()
+    assert bool(torch.isfinite(det).all()) and bool(torch.isfinite(adj).all())
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    R = (torch.bmm(A, adj) - det[:, None, None] * eye).abs()
+    if n <= 4:
+        rn = A.norm(dim=-1)
+        ds = rn.prod(dim=-1)
+        bound = 2e-13 * (n ** 0.5 * ds[:, None, None] * rn[:, :, None] / rn[:, None, :]
+                         + torch.bmm(A.abs(), adj.abs())) + 1e-13 * ds[:, None, None] * eye
+        assert bool((R <= bound).all())
+    else:
+        scale = A.norm(dim=(1, 2)) * adj.norm(dim=(1, 2))
+        assert bool((R.amax(dim=(1, 2)) <= 1e-12 * scale).all())
+    idx = np.unique(np.concatenate([[0, batch - 1], np.random.default_rng(n).integers(batch, size=62)]))
+    a = A[torch.from_numpy(idx).cuda()].cpu().numpy()
+    gd, ga = det.cpu().numpy()[idx], adj[torch.from_numpy(idx).cuda()].cpu().numpy()
+    rdet, radj = oracle.det_adj(a)
+    if n <= 4:
+        ds, as_ = hadamard_scales(a)
+        assert np.all(np.abs(gd - rdet) <= 1e-13 * ds + 1e-300)
+        assert np.all(np.abs(ga - radj) <= 1e-13 * as_ + 1e-300)
+    else:
+        cond = np.linalg.cond(a)
+        assert np.all(np.abs(gd - rdet) <= 1e-13 * n * cond * np.abs(rdet))
+        err = np.abs(ga - radj).max(axis=(1, 2))
+        assert np.all(err <= 1e-13 * n * cond * np.abs(radj).max(axis=(1, 2)))
