@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large", "det", "jastrow"],
+    ap.add_argument("--workload", default="medium", choices=["medium", "batch96", "density", "large", "det", "jastrow", "cusp"],
                     help="medium: one 80-atom molecule; batch96: 96 molecules of uneven sizes; "
                          "density: electron density of a 1114-AO molecule on a 100^3 grid; "
                          "large: 7500-AO system, dense vs screened contraction; "
@@ -582,6 +582,84 @@ def main_jastrow(a):
     print(json.dumps(line))
 
 
+def main_cusp(a):
+    """MO cusp correction (Section 3.3) on the medium workload (512 walkers,
+    radii 0.25 bohr on C and 0.2 bohr on H): one step is set_point (fresh
+    device coordinates), the AO stage, the forward contraction and the
+    in-place cusp kernel.  The same steps without the correction are timed
+    beside it.  The cusp kernel reads every point's coordinates and reads and
+    writes the mo_vgl row of every point inside a sphere."""
+    import torch
+    import oracle
+    import synth
+    import paper_2512_16677_amd as qmk
+    s = synth.medium(walkers=a.walkers)
+    z = s.nucl_charge.astype(np.float64)
+    rc = np.where(z > 1, 0.25, 0.2)
+    dev = torch.device("cuda:0")
+    coords = [np.ascontiguousarray(s.elec_coord), np.ascontiguousarray(s.elec_coord + 1e-3)]
+    r = [torch.from_numpy(c).to(dev) for c in coords]
+    ctx = qmk.Context.from_system(s)
+    out = torch.empty((s.walk_num, s.elec_num, 5, s.mo_num), dtype=torch.float64, device=dev)
+
+    def run(cusp):
+        if cusp:
+            ctx.set_mo_cusp(z, rc)
+        else:
+            ctx.set_mo_cusp(None)
+        for i in range(1 + a.warmup):
+            ctx.set_point(r[i % 2])
+            ctx.get_mo_vgl(out=out)
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for i in range(a.steps):
+            ctx.set_point(r[i % 2])
+            ctx.get_mo_vgl(out=out)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / a.steps, ctx.timing()
+
+    ms_off, _ = run(False)
+    ms, tm = run(True)
+    ctx.close()
+    P, K, N = s.point_num, s.ao_num, s.mo_num
+
+    def inside(c):
+        d2 = ((c.reshape(-1, 1, 3) - s.nucl_coord[None]) ** 2).sum(-1)
+        return int((d2 < rc[None] ** 2).any(axis=1).sum())
+
+    n_in = sum(inside(coords[i % 2]) for i in range(a.steps)) / a.steps
+    cusp_ms = tm["cusp"]["ms"] / tm["cusp"]["launches"]
+    cusp_bytes = 24.0 * P + n_in * 2 * 5 * N * 8
+    mo_ms = tm["mo"]["ms"] / tm["mo"]["launches"]
+    tf = 2.0 * 5 * P * K * N / (mo_ms * 1e-3) / 1e12
+    line = {"metric": "cusp-corrected mo_vgl electron-evals/s (forward)", "value": P / (ms * 1e-3),
+            "unit": "e-evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"ch80_800ao with MO cusp correction: 40 C + 40 H, {K} AOs, {N} MOs, "
+                                   f"{s.walk_num} walkers x {s.elec_num} electrons, r_c 0.25 (C) / 0.2 (H) bohr"},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAKS["fp64_TFLOPs"], "unit": "TFLOP/s",
+                         "frac": tf / PEAKS["fp64_TFLOPs"], "traffic": None,
+                         "kernel": "gemm_kernel (forward product, the largest share of the step)"},
+            "cusp_kernel": {"avg_ms": cusp_ms, "points_inside": n_in, "bytes": cusp_bytes,
+                            "GBps": cusp_bytes / (cusp_ms * 1e-3) / 1e9,
+                            "frac_hbm": cusp_bytes / (cusp_ms * 1e-3) / 1e9 / PEAKS["hbm_GBps"]},
+            "without_cusp_ms_per_step": ms_off,
+            "kernels_ms_per_step": {k: tm[k]["ms"] / a.steps for k in ("ao", "mo", "cusp")}}
+    if not a.no_cpu_baseline:
+        n = max(1, min(a.cpu_walkers, s.walk_num))
+        sub = synth.medium(walkers=n)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        oracle.mo_vgl_cusp(sub, z, rc, points=np.ascontiguousarray(s.elec_coord[:n]).reshape(-1, 3))
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": n * s.elec_num / dt, "unit": "e-evals/s", "cores": threads,
+                                "kind": "oracle", "sample": f"{n} walkers of the same workload (forward)"}
+    print(json.dumps(line))
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: under a hardware-counter
     profile its FETCH_SIZE / WRITE_SIZE give the factor that turns those
@@ -606,6 +684,12 @@ def main():
             print(json.dumps({"error": "one GPU only"}))
             sys.exit(2)
         main_jastrow(a)
+        return
+    if a.workload == "cusp":
+        if a.gpus != 1:
+            print(json.dumps({"error": "one GPU only"}))
+            sys.exit(2)
+        main_cusp(a)
         return
     if a.workload == "det":
         if a.gpus != 1:

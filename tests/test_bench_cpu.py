@@ -10,7 +10,7 @@ sys.path.insert(0, ROOT)
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
-    for workload in ("medium", "jastrow", "density"):
+    for workload in ("medium", "jastrow", "density", "cusp", "det", "large", "batch96"):
         r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--workload", workload],
                            capture_output=True, text=True, timeout=120)
         assert r.returncode == 2, (workload, r.stderr[-500:])
