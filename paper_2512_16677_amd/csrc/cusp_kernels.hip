@@ -9,8 +9,9 @@
 //
 // One lane per point finds the sphere (if any; the spheres do not overlap)
 // that contains its point.  Such points are rare, so the wave then serves
-// them one at a time: every lane evaluates the same radial s functions of
-// that point and updates 64 MOs per pass of the point's mo_vgl row.
+// them one at a time: one lane per s shell of the nucleus evaluates that
+// shell's radial sums at the point, and every lane takes them by shuffle to
+// update 64 MOs per pass of the point's mo_vgl row.
 #include "qmk_internal.h"
 
 namespace qmk {
@@ -50,26 +51,47 @@ __global__ __launch_bounds__(256) void cusp_kernel(CuspArgs c, PointArgs pts, TD
     const double r = sqrt(u);
     const double ir = 1.0 / r;  // a point exactly on the nucleus: the cusp diverges
     TD* row = mo + q * 5 * N;
-    for (int64_t i = lane; i < N; i += 64) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;  // phi^s and its first two radial derivatives
-      for (int j = nu.s_begin; j < nu.s_end; ++j) {
-        const CuspS sj = c.s[j];
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-        for (int k = sj.p_begin; k < sj.p_end; ++k) {
-          const PrimDev pr = c.prim[k];
-          const double x = pr.gamma * u;
-          if (x >= c.T) break;  // ascending exponents, as in the AO stage
-          const double e = pr.coef * exp(-x);
-          g0 += e;
-          g1 -= pr.gamma * e;
-          g2 += pr.gamma * pr.gamma * e;
-        }
-        // chi = M g0(u), chi' = 2 r M g1, chi'' = M (2 g1 + 4 u g2)
-        const double w = c.cs[static_cast<int64_t>(j) * N + i] * sj.m;
-        s0 += w * g0;
-        s1 += w * 2.0 * r * g1;
-        s2 += w * (2.0 * g1 + 4.0 * u * g2);
+    const int ns = nu.s_end - nu.s_begin;
+    // The radial sums of the point's s shells do not depend on the MO: lane
+    // t forms those of shell j0 + t, and every lane takes them by shuffle.
+    // The first 64 shells are formed once per point, any further ones per
+    // pass.
+    auto radial = [&](int j0, double& m, double& g0, double& g1, double& g2) {
+      m = g0 = g1 = g2 = 0.0;
+      if (j0 + lane >= ns) return;
+      const CuspS sj = c.s[nu.s_begin + j0 + lane];
+      m = sj.m;
+      for (int k = sj.p_begin; k < sj.p_end; ++k) {
+        const PrimDev pr = c.prim[k];
+        const double x = pr.gamma * u;
+        if (x >= c.T) break;  // ascending exponents, as in the AO stage
+        const double e = pr.coef * exp(-x);
+        g0 += e;
+        g1 -= pr.gamma * e;
+        g2 += pr.gamma * pr.gamma * e;
       }
+    };
+    double m_first, g0_first, g1_first, g2_first;
+    radial(0, m_first, g0_first, g1_first, g2_first);
+    for (int64_t i0 = 0; i0 < N; i0 += 64) {
+      const int64_t i = i0 + lane;
+      const bool on = i < N;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;  // phi^s and its first two radial derivatives
+      for (int j0 = 0; j0 < ns; j0 += 64) {
+        double m = m_first, g0 = g0_first, g1 = g1_first, g2 = g2_first;
+        if (j0 > 0) radial(j0, m, g0, g1, g2);
+        const int nj = min(64, ns - j0);
+        for (int t = 0; t < nj; ++t) {
+          const double mt = __shfl(m, t, 64), h0 = __shfl(g0, t, 64);
+          const double h1 = __shfl(g1, t, 64), h2 = __shfl(g2, t, 64);
+          // chi = M g0(u), chi' = 2 r M g1, chi'' = M (2 g1 + 4 u g2)
+          const double w = on ? c.cs[static_cast<int64_t>(nu.s_begin + j0 + t) * N + i] * mt : 0.0;
+          s0 += w * h0;
+          s1 += w * 2.0 * r * h1;
+          s2 += w * (2.0 * h1 + 4.0 * u * h2);
+        }
+      }
+      if (!on) continue;
       const double* f = c.f + static_cast<int64_t>(a) * 4 * N;
       const double f0 = f[i], f1 = f[N + i], f2 = f[2 * N + i], f3 = f[3 * N + i];
       const double h0 = f0 + r * (f1 + r * (f2 + r * f3)) - s0;
