@@ -721,8 +721,11 @@ qmk_status apply_cusp(qmk_ctx ctx, void* out, int o32, hipStream_t s) {
   if (!ctx->cusp_on) return QMK_OK;
   qmk_status st = ensure_cusp(ctx, s);
   if (st != QMK_OK) return st;
+  QMK_HIP(ctx, ctx->d_cusp_list.ensure(static_cast<size_t>(2 * ctx->P() + 4) * sizeof(int32_t)),
+          "alloc cusp point list");
+  int32_t* const cl = ctx->d_cusp_list.as<int32_t>();
   LaunchTimer lt(ctx, QMK_KERNEL_CUSP, s);
-  QMK_HIP(ctx, launch_cusp(ctx->cusp, point_args(ctx), out, o32, ctx->mo_num, s), "cusp correction");
+  QMK_HIP(ctx, launch_cusp(ctx->cusp, point_args(ctx), out, o32, ctx->mo_num, cl, cl + 4, s), "cusp correction");
   return QMK_OK;
 }
 

@@ -133,6 +133,7 @@ struct qmk_ctx_s {
   int64_t cusp_version = 0, geom_version = 0;
   int64_t cusp_key[4] = {-1, -1, -1, -1};  // geom, coef, cusp versions, mode
   DevBuf d_cusp_nuc, d_cusp_s, d_cusp_prim, d_cusp_cs, d_cusp_f, d_cusp_pts, d_cusp_ao;
+  DevBuf d_cusp_list;  // [0]: count of points inside a sphere; from [4]: (point, nucleus) pairs
   qmk::CuspArgs cusp{};
 
   // three-body Jastrow: operands of the product, rescaled e-n distances,

@@ -217,8 +217,10 @@ hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& o
 hipError_t launch_ao_value(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                            hipStream_t s);
 // Adds the cusp correction to mo_vgl[P][5][N] (FP64 or FP32) in place.
+// Scratch: *count (cleared here) and list[2 P] for the (point, nucleus)
+// pairs inside a sphere.
 hipError_t launch_cusp(const CuspArgs& c, const PointArgs& pts, void* mo, int out_is_f32, int64_t N,
-                       hipStream_t s);
+                       int32_t* count, int32_t* list, hipStream_t s);
 // GEMM tile shape: WGM x WGN wavefronts of TM x TN 16x16 MFMA blocks, K step BK.
 struct TileCfg {
   int wgm, wgn, tm, tn, bk;
