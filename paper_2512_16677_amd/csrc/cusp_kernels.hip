@@ -22,23 +22,43 @@ __global__ void cusp_clear_kernel(int32_t* count) {
 }
 
 // One lane per point: the sphere (if any) that contains it goes to the list
-// as the pair (point, nucleus).
+// as the pair (point, nucleus).  The spheres (centre, squared radius) are
+// staged in LDS 256 at a time.
 __global__ __launch_bounds__(256) void cusp_find_kernel(CuspArgs c, PointArgs pts, int32_t* count,
                                                         int32_t* list) {
+  __shared__ double4 sph[256];
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= pts.P) return;
-  const double rx = pts.coord[p * pts.s_pt];
-  const double ry = pts.coord[p * pts.s_pt + pts.s_ax];
-  const double rz = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
-  for (int a = 0; a < c.n_nuc; ++a) {
-    const CuspNuc nu = c.nuc[a];
-    const double dx = rx - nu.x, dy = ry - nu.y, dz = rz - nu.z;
-    if (dx * dx + dy * dy + dz * dz < nu.rc * nu.rc) {
-      const int32_t k = atomicAdd(count, 1);  // at most once per point: k < P
-      list[2 * k] = static_cast<int32_t>(p);
-      list[2 * k + 1] = a;
-      return;
+  const bool valid = p < pts.P;
+  double rx = 0.0, ry = 0.0, rz = 0.0;
+  if (valid) {
+    rx = pts.coord[p * pts.s_pt];
+    ry = pts.coord[p * pts.s_pt + pts.s_ax];
+    rz = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
+  }
+  int hit = -1;
+  for (int a0 = 0; a0 < c.n_nuc; a0 += 256) {
+    const int na = min(256, c.n_nuc - a0);
+    __syncthreads();  // the previous chunk has been read
+    if (static_cast<int>(threadIdx.x) < na) {
+      const CuspNuc nu = c.nuc[a0 + threadIdx.x];
+      sph[threadIdx.x] = make_double4(nu.x, nu.y, nu.z, nu.rc * nu.rc);
     }
+    __syncthreads();
+    if (valid && hit < 0) {
+      for (int t = 0; t < na; ++t) {
+        const double4 q = sph[t];
+        const double dx = rx - q.x, dy = ry - q.y, dz = rz - q.z;
+        if (dx * dx + dy * dy + dz * dz < q.w) {
+          hit = a0 + t;
+          break;
+        }
+      }
+    }
+  }
+  if (hit >= 0) {
+    const int32_t k = atomicAdd(count, 1);  // at most once per point: k < P
+    list[2 * k] = static_cast<int32_t>(p);
+    list[2 * k + 1] = hit;
   }
 }
 
