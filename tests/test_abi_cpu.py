@@ -54,3 +54,45 @@ def test_create_without_gpu_reports_an_error():
     st = lib.qmk_ctx_create(ctypes.byref(h), 0)
     assert st != qmk.QMK_OK
     assert len(lib.qmk_last_error(None)) > 0
+
+
+def test_binding_checks_array_sizes_before_any_library_call():
+    """The library reads and writes caller arrays through plain pointers, so
+    the binding rejects arrays whose sizes do not match before it calls the
+    library at all (here a stand-in library that fails on any call)."""
+    import numpy as np
+
+    class NoCalls:
+        def __getattr__(self, name):
+            raise AssertionError(f"the library was called: {name}")
+
+    c = object.__new__(qmk.Context)
+    c._h = ctypes.c_void_p()  # nothing to destroy
+    c._lib = NoCalls()
+    c.device = 0
+    coord = np.zeros((2, 5, 3))
+    with pytest.raises(ValueError):
+        c.set_point(coord[:, :, :2].copy())                 # not [walk, elec, 3]
+    with pytest.raises(ValueError):
+        c.set_point(coord.reshape(-1)[:-3].copy(), 2, 5)    # 27 values for 30
+    with pytest.raises(ValueError):
+        c.set_point(np.zeros((3, 9)), 2, 5, transp="T")     # 27 values for 30
+    sh_nuc, sh_l = np.zeros(3, np.int64), np.array([0, 1, 2], np.int32)
+    off, ex, co = np.array([0, 2, 3, 5], np.int64), np.ones(5), np.ones(5)
+    for bad in [dict(shell_prim_offset=off[:-1]), dict(coefficient=co[:-1]),
+                dict(shell_nucleus=sh_nuc[:-1]), dict(prim_factor=np.ones(4)),
+                dict(shell_factor=np.ones(4)), dict(ao_factor=np.ones(9))]:
+        args = dict(shell_nucleus=sh_nuc, shell_ang_mom=sh_l, shell_prim_offset=off, exponent=ex,
+                    coefficient=co)
+        args.update(bad)
+        with pytest.raises(ValueError):
+            c.set_basis(**args)
+    with pytest.raises(ValueError):
+        c.set_mo_coef(np.ones(10))
+    with pytest.raises(ValueError):
+        c.set_mo_cusp(np.ones(3), np.ones(2))
+    # consistent arrays get through to the library
+    with pytest.raises(AssertionError, match="qmk_set_basis"):
+        c.set_basis(sh_nuc, sh_l, off, ex, co, ao_factor=np.ones(10))
+    with pytest.raises(AssertionError, match="qmk_set_point"):
+        c.set_point(coord)
