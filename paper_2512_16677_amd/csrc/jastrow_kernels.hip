@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void een_g0_kernel(const double* __restrict__ 
 //   j0[w][i] = sum_{k=1}^{nord-1} (sum_{j != i} rt_ij^k) g0[w][i][k-1]
 // (g0 from een_g0_kernel).
 constexpr int kEeRows = 2, kEeChunk = 512;
-__global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, double kappa, int nord,
+template <int NORD>
+__global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, double kappa,
                                                      const double* __restrict__ g0, double* __restrict__ rt,
                                                      double* __restrict__ j0) {
   __shared__ double cs[3][kEeChunk];
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, 
     yi[r] = pts.coord[p * pts.s_pt + pts.s_ax];
     zi[r] = pts.coord[p * pts.s_pt + 2 * pts.s_ax];
   }
-  double sk[kEeRows][kMaxOrd] = {};
+  double sk[kEeRows][NORD] = {};  // [row][k]: sum_j rt_ij^k, k = 1 .. NORD-1
   for (int64_t c0 = 0; c0 < ne; c0 += kEeChunk) {
     const int cn = static_cast<int>(min<int64_t>(kEeChunk, ne - c0));
     __syncthreads();
@@ -157,8 +158,8 @@ __global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, 
         if (i < ne) rt[(w * ne + i) * ne + j] = diag ? -1.0 : x[r];
         double v = diag ? 0.0 : x[r];
 #pragma unroll
-        for (int k = 1; k < kMaxOrd; ++k) {
-          sk[r][k] += k < nord ? v : 0.0;
+        for (int k = 1; k < NORD; ++k) {
+          sk[r][k] += v;
           v *= x[r];
         }
       }
@@ -170,10 +171,7 @@ __global__ __launch_bounds__(256) void een_ee_kernel(PointArgs pts, int64_t ne, 
     const double* g = g0 + (w * ne + i) * (kMaxOrd - 1);
     double acc = 0.0;
 #pragma unroll
-    for (int k = 1; k < kMaxOrd; ++k) {
-      if (k >= nord) break;
-      acc += wave_sum(sk[r][k]) * g[k - 1];
-    }
+    for (int k = 1; k < NORD; ++k) acc += wave_sum(sk[r][k]) * g[k - 1];
     if (lane == 0 && ib + r < ne) j0[w * ne + ib + r] = acc;
   }
 }
@@ -210,20 +208,19 @@ hipError_t launch_een_ee(const PointArgs& pts, int64_t ne, int64_t nn, double ka
   if (pts.P <= 0) return hipSuccess;
   if (nord < 2 || nord > kMaxOrd) return hipErrorInvalidValue;
   const dim3 gg(static_cast<unsigned>((pts.P + 255) / 256));
-  switch (nord) {
-#define QMK_EEN_G0(n) \
-  case n:             \
-    hipLaunchKernelGGL(een_g0_kernel<n>, gg, dim3(256), 0, s, x, pts.P, ne, nn, q0, g0); \
-    break;
-    QMK_EEN_G0(2) QMK_EEN_G0(3) QMK_EEN_G0(4) QMK_EEN_G0(5) QMK_EEN_G0(6) QMK_EEN_G0(7) QMK_EEN_G0(8)
-#undef QMK_EEN_G0
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const int64_t nw = pts.P / ne, g = nw * ((ne + 4 * kEeRows - 1) / (4 * kEeRows));
   if (g > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(een_ee_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, pts, ne, kappa, nord, g0, rt,
-                     j0);
+  const dim3 ge(static_cast<unsigned>(g));
+  switch (nord) {
+#define QMK_EEN(n)                                                                                \
+  case n:                                                                                         \
+    hipLaunchKernelGGL(een_g0_kernel<n>, gg, dim3(256), 0, s, x, pts.P, ne, nn, q0, g0);          \
+    if (hipPeekAtLastError() != hipSuccess) break;                                                \
+    hipLaunchKernelGGL(een_ee_kernel<n>, ge, dim3(256), 0, s, pts, ne, kappa, g0, rt, j0);        \
+    break;
+    QMK_EEN(2) QMK_EEN(3) QMK_EEN(4) QMK_EEN(5) QMK_EEN(6) QMK_EEN(7) QMK_EEN(8)
+#undef QMK_EEN
+  }
   return hipGetLastError();
 }
 
