@@ -70,12 +70,16 @@ enum {
 /* Element types of caller buffers. */
 enum { QMK_F64 = 0, QMK_F32 = 1 };
 
-/* Status code -> static string ("QMK_OK", ...). Never NULL. */
+/* Status code -> static string ("QMK_OK", ...). Never NULL.  Errors cross
+ * the boundary as plain integer codes and C strings, the simple portable
+ * types of the C ABI (Section 2.3, cross-language interface). */
 const char* qmk_status_string(qmk_status status);
 
 /* Last error message of a context ("" if none); valid until the next call on
  * the context.  qmk_last_error(NULL) returns the last error of a failed
- * qmk_ctx_create on this thread. */
+ * qmk_ctx_create on this thread.  A plain C string, as every value crossing
+ * the C ABI (Section 2.3); the message lives in the context, which holds
+ * all per-calculation state (Section 2.2). */
 const char* qmk_last_error(qmk_ctx ctx);
 
 /* Create a context bound to HIP device `hip_device` (Section 2.2: one
@@ -95,8 +99,10 @@ qmk_status qmk_ctx_destroy(qmk_ctx ctx);
 qmk_status qmk_set_precision(qmk_ctx ctx, int32_t bits, int32_t mode);
 
 /* Nuclear coordinates coord[nucl_num][3] (host memory).  nucl_num >= 1.
- * Invalidates cached results.  The number of nuclei may only change while no
- * basis is set. */
+ * The nuclei are the centres R_A of the AOs (Section 3.1, radial and angular
+ * parts), part of the wave function data a context is filled with before
+ * points are set (Section 5.1, usage example).  Invalidates cached results.
+ * The number of nuclei may only change while no basis is set. */
 qmk_status qmk_set_nucleus(qmk_ctx ctx, int64_t nucl_num, const double* coord);
 
 /* Contracted Cartesian Gaussian basis (Section 3.1, radial part with p = 2,
@@ -140,14 +146,19 @@ qmk_status qmk_set_mo_coef(qmk_ctx ctx, int64_t mo_num, int64_t ao_num, const do
 qmk_status qmk_set_point(qmk_ctx ctx, char transp, int64_t walk_num, int64_t elec_num,
                          const double* coord, int32_t coord_on_device);
 
-/* Dimensions; any pointer may be NULL.  point_num = walk_num * elec_num. */
+/* Dimensions; any pointer may be NULL.  point_num = walk_num * elec_num.
+ * The caller sizes its result buffers from these, as the usage example of
+ * Section 5.1 reads the number of MOs before evaluating them (its
+ * get_mo_basis_mo_num call). */
 qmk_status qmk_get_dims(qmk_ctx ctx, int64_t* nucl_num, int64_t* ao_num, int64_t* mo_num,
                         int64_t* walk_num, int64_t* elec_num);
 
 /* AO values, gradients, Laplacians into out[walk][elec][5][ao] (device
- * buffer of size_max elements of type dtype, QMK_F64 or QMK_F32).
- * Intended for inspection and tests: the contraction consumes the AOs in
- * the library's own layout. */
+ * buffer of size_max elements of type dtype, QMK_F64 or QMK_F32):
+ * chi_n = M_n R(r) P(r) with its gradient and Laplacian with respect to the
+ * electron coordinates (Section 3.1, AO, radial-part, cutoff and
+ * angular-part equations).  Intended for inspection and tests: the
+ * contraction consumes the AOs in the library's own layout. */
 qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                           void* hip_stream);
 

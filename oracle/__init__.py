@@ -187,6 +187,71 @@ def adjoint(sys_, w: np.ndarray, points: Optional[np.ndarray] = None, B: float =
     return out
 
 
+def _ao_nucleus(sys_) -> np.ndarray:
+    """Nucleus index of every AO (AOs numbered shell by shell)."""
+    return np.repeat(np.asarray(sys_.shell_nucleus, dtype=np.int64),
+                     [(int(l) + 1) * (int(l) + 2) // 2 for l in sys_.shell_ang_mom])
+
+
+# (i, j) -> AO derivative quantity of the Hessian component d_i d_j chi
+_HESS_Q = ((5, 6, 7), (6, 8, 9), (7, 9, 10))
+
+
+def adjoint_products(sys_, w: np.ndarray, points: Optional[np.ndarray] = None, B: float = 53.0,
+                     coef: Optional[np.ndarray] = None, with_mo: bool = False,
+                     chunk: Optional[int] = None):
+    """The gradients of `adjoint` (same definitions, same dict keys with the
+    *_abs sums), for workloads too large for its literal loops.
+
+    The two sums over an index that runs over thousands of values are taken
+    as matrix products with numpy (a library step), chunk by chunk of points,
+    on the oracle's AO derivatives up to third order:
+      Gbar[p,c,:] = W[p,c,:] C            (sum over MOs)
+      dC         += W_chunk^T ao_chunk    (sum over points and components)
+    and the electron and nuclear terms follow the definitions of `adjoint`:
+      t[p,k,i] = Gbar[p,0,k] d_i chi_k + sum_j Gbar[p,1+j,k] d_i d_j chi_k
+                 + Gbar[p,4,k] d_i lap chi_k,
+      dR_elec[p,i] = sum_k t[p,k,i],  dR_nucl[A,i] = -sum_p sum_{k on A} t[p,k,i].
+    With with_mo, also returns "mo" [P, 5, mo] = ao C^T (Section 3.2)."""
+    pts = _c(sys_.points() if points is None else points, np.float64).reshape(-1, 3)
+    C = _c(sys_.mo_coef if coef is None else coef, np.float64)
+    N, K = C.shape
+    P = pts.shape[0]
+    W = np.asarray(w, dtype=np.float64).reshape(P, 5, N)
+    if chunk is None:  # keep one chunk's AO derivatives near 512 MB
+        chunk = max(16, int(512e6 // (NQ_FULL * K * 8)))
+    own = _ao_nucleus(sys_)
+    n_nucl = int(np.asarray(sys_.nucl_coord).reshape(-1, 3).shape[0])
+    out = {"d_coef": np.zeros((N, K)), "d_coef_abs": np.zeros((N, K)),
+           "d_elec": np.empty((P, 3)), "d_elec_abs": np.empty((P, 3)),
+           "d_nucl": np.zeros((n_nucl, 3)), "d_nucl_abs": np.zeros((n_nucl, 3))}
+    if with_mo:
+        out["mo"] = np.empty((P, 5, N))
+    for a in range(0, P, chunk):
+        b = min(a + chunk, P)
+        ao = ao_derivs(sys_, pts[a:b], B, NQ_FULL)          # [c, 14, K]
+        Wc = W[a:b]                                         # [c, 5, N]
+        gbar = np.matmul(Wc, C)                             # [c, 5, K]
+        for i in range(3):
+            terms = [gbar[:, 0] * ao[:, 1 + i]] + \
+                    [gbar[:, 1 + j] * ao[:, _HESS_Q[i][j]] for j in range(3)] + \
+                    [gbar[:, 4] * ao[:, 11 + i]]
+            t = terms[0] + terms[1] + terms[2] + terms[3] + terms[4]           # [c, K]
+            ta = (np.abs(terms[0]) + np.abs(terms[1]) + np.abs(terms[2]) + np.abs(terms[3])
+                  + np.abs(terms[4]))
+            out["d_elec"][a:b, i] = t.sum(axis=1)
+            out["d_elec_abs"][a:b, i] = ta.sum(axis=1)
+            np.subtract.at(out["d_nucl"][:, i], own, t.sum(axis=0))
+            np.add.at(out["d_nucl_abs"][:, i], own, ta.sum(axis=0))
+        a5 = np.ascontiguousarray(ao[:, :5]).reshape(-1, K)  # rows (point, component)
+        w5 = Wc.reshape(-1, N)
+        out["d_coef"] += w5.T @ a5
+        out["d_coef_abs"] += np.abs(w5).T @ np.abs(a5)
+        if with_mo:
+            out["mo"][a:b] = (a5 @ C.T).reshape(b - a, 5, N)
+    return out
+
+
 def mo_value(sys_, points: Optional[np.ndarray] = None, B: float = 53.0,
              coef: Optional[np.ndarray] = None) -> np.ndarray:
     """MO values [P, mo] (the value rows of mo_vgl)."""

@@ -147,6 +147,9 @@ def _stream(stream=None):
 class Context:
     """One QMCkl-style context (not thread-safe; one per host thread)."""
 
+    _in_version = 0
+    _cfg_version = 0
+
     def __init__(self, device: int = 0):
         self._lib = load_library()
         h = ctypes.c_void_p()
@@ -156,6 +159,11 @@ class Context:
         self._h = h
         self.device = int(device)
         self._keep = None  # device coordinates the library points into
+        # bumped by every set_* call: the autograd function compares them
+        # between forward and backward (inputs: nuclei, C, points; config:
+        # precision, basis, cusp, screening)
+        self._in_version = 0
+        self._cfg_version = 0
 
     # ------------------------------------------------------------------ util
     def _check(self, st: int):
@@ -185,10 +193,12 @@ class Context:
 
     # ------------------------------------------------------------------- set
     def set_precision(self, bits: int = 53, mode: str = "fp64"):
+        self._cfg_version += 1
         self._check(self._lib.qmk_set_precision(self._h, int(bits), MODES[mode]))
 
     def set_nucleus(self, coord):
         c = _np(coord, np.float64).reshape(-1, 3)
+        self._in_version += 1
         self._check(self._lib.qmk_set_nucleus(self._h, c.shape[0], _ptr(c)))
 
     def set_basis(self, shell_nucleus, shell_ang_mom, shell_prim_offset, exponent, coefficient,
@@ -210,6 +220,7 @@ class Context:
                            ("shell_factor", sf, n_sh), ("ao_factor", af, n_ao)]:
             if a is not None and a.size != n:
                 raise ValueError(f"{name} holds {a.size} values, {n} expected")
+        self._cfg_version += 1
         self._check(self._lib.qmk_set_basis(self._h, sl.shape[0], ex.shape[0], _ptr(sn), _ptr(sl),
                                             _ptr(so), _ptr(ex), _ptr(co), _ptr(pf), _ptr(sf),
                                             _ptr(af)))
@@ -218,6 +229,7 @@ class Context:
         c = _np(coef, np.float64)
         if c.ndim != 2:
             raise ValueError("coef must have shape [mo_num, ao_num]")
+        self._in_version += 1
         self._check(self._lib.qmk_set_mo_coef(self._h, c.shape[0], c.shape[1], _ptr(c)))
 
     def set_point(self, coord, walk_num: Optional[int] = None, elec_num: Optional[int] = None,
@@ -236,6 +248,7 @@ class Context:
         if size != 3 * int(walk_num) * int(elec_num):
             raise ValueError(f"coordinates hold {size} values, 3 * walk_num * elec_num = "
                              f"{3 * int(walk_num) * int(elec_num)} expected")
+        self._in_version += 1
         if isinstance(coord, np.ndarray):
             c = _np(coord, np.float64)
             self._check(self._lib.qmk_set_point(self._h, transp.encode(), int(walk_num),
@@ -308,6 +321,7 @@ class Context:
     def set_mo_cusp(self, charge=None, r_cusp=None):
         """Switch the MO cusp correction on (charges and radii per nucleus) or
         off (r_cusp None)."""
+        self._cfg_version += 1
         if r_cusp is None:
             self._check(self._lib.qmk_set_mo_cusp(self._h, 0, None, None))
             return
@@ -319,6 +333,7 @@ class Context:
 
     def set_screening(self, enable: bool = True):
         """Screened (block-sparse) forward contraction on or off."""
+        self._cfg_version += 1
         self._check(self._lib.qmk_set_screening(self._h, 1 if enable else 0))
 
     def screening_density(self) -> float:
@@ -454,23 +469,54 @@ class Batch:
         """outs: list of CUDA tensors [walk, elec, 5, mo] (allocated if None);
         ws: optional list of weight tensors (same shapes and dtype);
         grads: optional list of dicts with 'd_coef', 'd_elec', 'd_nucl'
-        tensors (allocated when ws is given and grads is None)."""
+        tensors (allocated when ws is given and grads is None).
+
+        The library takes plain pointers without sizes here, so every tensor
+        is checked (device, contiguity, element type, element count) before
+        the call; a mismatch raises ValueError and nothing is launched."""
         import torch
         dtype = dtype or (outs[0].dtype if outs else torch.float64)
+        if dtype not in (torch.float64, torch.float32):
+            raise ValueError("dtype must be torch.float64 or torch.float32")
         dims = [c.dims() for c in self.contexts]
+        n = len(self.contexts)
         if outs is None:
             outs = [torch.empty((d["walk_num"], d["elec_num"], 5, d["mo_num"]), dtype=dtype,
                                 device=f"cuda:{c.device}") for d, c in zip(dims, self.contexts)]
-        n = len(self.contexts)
+
+        def need(t, what, numel, dt):
+            if t is None or not (t.is_cuda and t.is_contiguous() and t.dtype == dt):
+                raise ValueError(f"{what} must be a contiguous CUDA tensor of dtype {dt}")
+            if t.numel() != numel:
+                raise ValueError(f"{what} holds {t.numel()} values, {numel} expected")
+
+        if len(outs) != n:
+            raise ValueError(f"outs holds {len(outs)} tensors for {n} contexts")
+        for i, (t, d) in enumerate(zip(outs, dims)):
+            need(t, f"outs[{i}]", d["walk_num"] * d["elec_num"] * 5 * d["mo_num"], dtype)
         P = ctypes.c_void_p
         o = (P * n)(*[t.data_ptr() for t in outs])
         w_arr = dc = de = dn = None
         if ws is not None:
+            if len(ws) != n:
+                raise ValueError(f"ws holds {len(ws)} tensors for {n} contexts")
+            for i, (t, d) in enumerate(zip(ws, dims)):
+                need(t, f"ws[{i}]", d["walk_num"] * d["elec_num"] * 5 * d["mo_num"], dtype)
             if grads is None:
                 grads = [{"d_coef": torch.empty((d["mo_num"], d["ao_num"]), dtype=torch.float64, device=t.device),
                           "d_elec": torch.empty((d["walk_num"], d["elec_num"], 3), dtype=torch.float64, device=t.device),
                           "d_nucl": torch.empty((d["nucl_num"], 3), dtype=torch.float64, device=t.device)}
                          for d, t in zip(dims, outs)]
+            if len(grads) != n:
+                raise ValueError(f"grads holds {len(grads)} entries for {n} contexts")
+            for i, (g, d) in enumerate(zip(grads, dims)):
+                sizes = {"d_coef": d["mo_num"] * d["ao_num"], "d_elec": d["walk_num"] * d["elec_num"] * 3,
+                         "d_nucl": d["nucl_num"] * 3}
+                for k, t in g.items():
+                    if k not in sizes:
+                        raise ValueError(f"grads[{i}]: unknown output {k!r}")
+                    if t is not None:
+                        need(t, f"grads[{i}][{k!r}]", sizes[k], torch.float64)
             w_arr = (P * n)(*[t.data_ptr() for t in ws])
 
             def col(k):
@@ -502,24 +548,47 @@ def _autograd():
         -> [walk, elec, 5, mo].  C and R_nucl are copied to the context (host
         round trip, small arrays); R_elec stays on the device.  backward
         calls the library's adjoint, which recomputes AO derivatives up to
-        third order instead of storing them."""
+        third order instead of storing them.
+
+        One context may serve several graphs: forward keeps host copies of C
+        and R_nucl and the device coordinates, and backward puts them back
+        into the context when another forward (or any set_* call of the
+        inputs) ran in between, so every graph gets the gradients of its own
+        inputs.  A change of precision, basis, cusp or screening settings in
+        between is an error."""
 
         @staticmethod
         def forward(ctx, qctx: Context, C, R_nucl, R_elec):
-            qctx.set_nucleus(R_nucl.detach().double().cpu().numpy())
-            qctx.set_mo_coef(C.detach().double().cpu().numpy())
+            nucl = R_nucl.detach().double().cpu().numpy().copy()
+            coef = C.detach().double().cpu().numpy().copy()
+            qctx.set_nucleus(nucl)
+            qctx.set_mo_coef(coef)
             r = R_elec.detach().to(torch.float64).contiguous()
             qctx.set_point(r)
             mo = qctx.get_mo_vgl()
             ctx.qctx = qctx
             ctx.devices = (C.device, R_nucl.device, R_elec.device)
+            ctx.host_inputs = (nucl, coef)
+            ctx.versions = (qctx._in_version, qctx._cfg_version)
             ctx.save_for_backward(r)
             return mo
 
         @staticmethod
         def backward(ctx, grad):
-            g = ctx.qctx.adjoint(grad.contiguous(), d_coef=ctx.needs_input_grad[1],
-                                 d_elec=ctx.needs_input_grad[3], d_nucl=ctx.needs_input_grad[2])
+            qctx = ctx.qctx
+            in_v, cfg_v = ctx.versions
+            if qctx._cfg_version != cfg_v:
+                raise RuntimeError("the context's precision, basis, cusp or screening settings changed "
+                                   "between forward and backward")
+            if qctx._in_version != in_v:
+                (r,) = ctx.saved_tensors
+                nucl, coef = ctx.host_inputs
+                qctx.set_nucleus(nucl)
+                qctx.set_mo_coef(coef)
+                qctx.set_point(r)
+                ctx.versions = (qctx._in_version, qctx._cfg_version)
+            g = qctx.adjoint(grad.contiguous(), d_coef=ctx.needs_input_grad[1],
+                             d_elec=ctx.needs_input_grad[3], d_nucl=ctx.needs_input_grad[2])
             dc, dn, de = g.get("d_coef"), g.get("d_nucl"), g.get("d_elec")
             dc = None if dc is None else dc.to(ctx.devices[0])
             dn = None if dn is None else dn.to(ctx.devices[1])

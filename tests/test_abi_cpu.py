@@ -96,3 +96,70 @@ def test_binding_checks_array_sizes_before_any_library_call():
         c.set_basis(sh_nuc, sh_l, off, ex, co, ao_factor=np.ones(10))
     with pytest.raises(AssertionError, match="qmk_set_point"):
         c.set_point(coord)
+
+
+def test_batch_run_checks_every_tensor_before_the_library_call():
+    """qmk_batch_run takes plain pointers without sizes, so Batch.run checks
+    each output, weight and gradient tensor (device, contiguity, element type,
+    element count) and raises before calling the library (a stand-in library
+    that fails on any call)."""
+    import torch
+
+    class NoCalls:
+        def __getattr__(self, name):
+            raise AssertionError(f"the library was called: {name}")
+
+    class FakeCtx:
+        device = 0
+
+        def __init__(self, walk, elec, mo, ao, nucl):
+            self._d = dict(walk_num=walk, elec_num=elec, mo_num=mo, ao_num=ao, nucl_num=nucl)
+
+        def dims(self):
+            return dict(self._d)
+
+    class FakeTensor:
+        """Stands for a CUDA tensor (no GPU here)."""
+
+        def __init__(self, numel, dtype=torch.float64, cuda=True, contiguous=True):
+            self._n, self.dtype, self.is_cuda, self._c = numel, dtype, cuda, contiguous
+            self.device = "cuda:0"
+
+        def numel(self):
+            return self._n
+
+        def is_contiguous(self):
+            return self._c
+
+        def data_ptr(self):
+            return 4096
+
+    b = object.__new__(qmk.Batch)
+    b._h = ctypes.c_void_p()
+    b._lib = NoCalls()
+    b.contexts = [FakeCtx(2, 3, 4, 6, 2), FakeCtx(1, 5, 2, 3, 1)]
+    f64, f32 = torch.float64, torch.float32
+    outs = [FakeTensor(2 * 3 * 5 * 4), FakeTensor(1 * 5 * 5 * 2)]
+    ws = [FakeTensor(2 * 3 * 5 * 4), FakeTensor(1 * 5 * 5 * 2)]
+    grads = [{"d_coef": FakeTensor(24), "d_elec": FakeTensor(18), "d_nucl": FakeTensor(6)},
+             {"d_coef": FakeTensor(6), "d_elec": FakeTensor(15), "d_nucl": FakeTensor(3)}]
+    bad_cases = [
+        dict(outs=[outs[0]]),                                            # one tensor short
+        dict(outs=[outs[0], FakeTensor(49)]),                            # wrong size
+        dict(outs=[outs[0], FakeTensor(50, dtype=f32)], dtype=f64),      # wrong element type
+        dict(outs=[outs[0], FakeTensor(50, cuda=False)]),                # host tensor
+        dict(outs=[outs[0], FakeTensor(50, contiguous=False)]),          # strided view
+        dict(outs=outs, ws=[ws[0], FakeTensor(50, dtype=f32)]),          # weights of another type
+        dict(outs=outs, ws=[ws[0], FakeTensor(51)]),                     # weights of another size
+        dict(outs=outs, ws=ws, grads=[grads[0], dict(grads[1], d_coef=FakeTensor(7))]),
+        dict(outs=outs, ws=ws, grads=[grads[0], dict(grads[1], d_elec=FakeTensor(15, dtype=f32))]),
+        dict(outs=outs, ws=ws, grads=[grads[0], dict(grads[1], d_nucl=FakeTensor(4))]),
+        dict(outs=outs, ws=ws, grads=[grads[0], dict(grads[1], d_other=FakeTensor(3))]),
+        dict(outs=outs, ws=ws, grads=[grads[0]]),
+    ]
+    for kw in bad_cases:
+        with pytest.raises(ValueError):
+            b.run(**kw)
+    # consistent tensors (and a skipped gradient) get through to the library
+    with pytest.raises(AssertionError, match="qmk_batch_run"):
+        b.run(outs=outs, ws=ws, grads=[grads[0], dict(grads[1], d_nucl=None)])

@@ -39,8 +39,9 @@ def test_term_count_matches_oracle():
         assert q.jastrow_een_terms(nord) == len(oracle.een_terms(nord))
 
 
-@pytest.mark.parametrize("system,nord", [("water_like", 3), ("water_like", 5), ("water_like", 8),
-                                         ("medium", 5)])
+@pytest.mark.parametrize("system,nord", [("water_like", 2), ("water_like", 3), ("water_like", 4),
+                                         ("water_like", 5), ("water_like", 6), ("water_like", 7),
+                                         ("water_like", 8), ("medium", 5)])
 def test_jastrow_een_matches_oracle(system, nord):
     q = qmk()
     s = synth.water_like(walkers=7) if system == "water_like" else synth.medium(walkers=2)

@@ -1,5 +1,7 @@
 """HIP path vs the FP64 oracle, element by element on the same seeded inputs,
 through the C ABI (FP64 mode: row-normwise relative error <= 1e-12)."""
+import copy
+
 import numpy as np
 import pytest
 
@@ -292,6 +294,47 @@ def test_autograd_function():
     assert grad_err(C.grad.cpu().numpy(), r["d_coef"], r["d_coef_abs"]) <= 1e-11
     assert grad_err(Rn.grad.cpu().numpy(), r["d_nucl"], r["d_nucl_abs"]) <= 1e-11
     assert grad_err(Re.grad.cpu().numpy().reshape(-1, 3), r["d_elec"], r["d_elec_abs"]) <= 1e-11
+
+
+def test_autograd_two_graphs_on_one_context():
+    """Two forwards with different C, nuclei and electrons on one context,
+    then the backward passes in reverse order and again in forward order:
+    each graph gets the oracle gradients of its own inputs (the binding puts
+    a graph's inputs back into the context when another forward ran in
+    between).  A precision change between forward and backward is an
+    error."""
+    q = qmk()
+    s = synth.water_like(walkers=3)
+    ctx = q.Context.from_system(s)
+    rng = np.random.default_rng(31)
+    inputs, outs = [], []
+    for g in range(2):
+        C0 = s.mo_coef + (0.1 * g) * rng.normal(size=s.mo_coef.shape)
+        R0 = s.nucl_coord + (0.05 * g) * rng.normal(size=s.nucl_coord.shape)
+        E0 = s.elec_coord + (0.2 * g) * rng.normal(size=s.elec_coord.shape)
+        C = torch.tensor(C0, requires_grad=True)
+        Rn = torch.tensor(R0, requires_grad=True)
+        Re = torch.tensor(E0, device="cuda", requires_grad=True)
+        inputs.append((C0, R0, E0, C, Rn, Re))
+        outs.append(q.mo_vgl(ctx, C, Rn, Re))
+    ws = [torch.from_numpy(synth.adjoint_weights(s, seed=40 + g)).cuda() for g in range(2)]
+    for order in ((1, 0), (0, 1)):
+        for g in order:
+            C0, R0, E0, C, Rn, Re = inputs[g]
+            for t in (C, Rn, Re):
+                t.grad = None
+            (outs[g] * ws[g]).sum().backward(retain_graph=True)
+            sg = copy.copy(s)
+            sg.nucl_coord, sg.mo_coef, sg.elec_coord = R0, C0, E0
+            r = oracle.adjoint(sg, ws[g].cpu().numpy())
+            assert grad_err(C.grad.cpu().numpy(), r["d_coef"], r["d_coef_abs"]) <= 1e-11, (order, g)
+            assert grad_err(Rn.grad.cpu().numpy(), r["d_nucl"], r["d_nucl_abs"]) <= 1e-11, (order, g)
+            assert grad_err(Re.grad.cpu().numpy().reshape(-1, 3), r["d_elec"], r["d_elec_abs"]) <= 1e-11, \
+                (order, g)
+    ctx.set_precision(53, "mixed_f32")
+    with pytest.raises(RuntimeError, match="changed between forward and backward"):
+        (outs[0] * ws[0]).sum().backward()
+    ctx.close()
 
 
 def test_every_tile_shape_matches_oracle():
