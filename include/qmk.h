@@ -170,6 +170,29 @@ qmk_status qmk_get_ao_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
 qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
                           void* hip_stream);
 
+/* qmk_get_mo_vgl without any allocation in the call, for callers that
+ * cannot allocate device or host memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same arguments,
+ * same result as qmk_get_mo_vgl up to rounding (the product's tile comes
+ * from earlier tuning decisions or the least-padded-work rule, never from
+ * timing).  The AO array is placed in a 64 MiB device array of the library
+ * (one per GPU, held from the first call on that GPU until the process
+ * ends) instead of the context's own buffer, so one call covers at most
+ * Kp * 5 * Pp * s <= 64 MiB, with Kp = ao_num rounded up to a multiple of
+ * 128, Pp = walk_num * elec_num rounded up to a multiple of 256 and s = 8
+ * (QMK_FP64 mode) or 4 (mixed modes); larger calls return QMK_SIZE.
+ * Requires the device copies of the basis tables and MO coefficients for
+ * the current precision mode, which the first qmk_get_mo_vgl after the last
+ * set_nucleus / set_basis / set_mo_coef / set_precision builds: without
+ * them QMK_NOT_SET.  Always the dense product (the screening switch is not
+ * used; the screened product gives the same values); with the cusp
+ * correction on, QMK_UNSUPPORTED.  Kernel timing does not cover this call.
+ * Every call on a GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other host threads) race and give wrong
+ * results.  The padding of the array is cleared on every call. */
+qmk_status qmk_get_mo_vgl_noalloc(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtype,
+                                  void* hip_stream);
+
 /* MO values only (the value rows of Section 3.2's product; the orbital
  * evaluation on grids of Section 5.4): mo_value[walk][elec][mo] =
  * sum_k C[mo][k] chi_k(r), into a device buffer of size_max >=

@@ -45,7 +45,7 @@ QMK_F64, QMK_F32 = 0, 1
 EXPORTED = [
     "qmk_status_string", "qmk_last_error", "qmk_ctx_create", "qmk_ctx_destroy",
     "qmk_set_precision", "qmk_set_nucleus", "qmk_set_basis", "qmk_set_mo_coef",
-    "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl",
+    "qmk_set_point", "qmk_get_dims", "qmk_get_ao_vgl", "qmk_get_mo_vgl", "qmk_get_mo_vgl_noalloc",
     "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp", "qmk_set_screening",
     "qmk_get_screening_density", "qmk_det_adj", "qmk_jastrow_een_terms", "qmk_jastrow_een",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_dims": ([P, P, P, P, P, P], I32),
         "qmk_get_ao_vgl": ([P, P, I64, I32, P], I32),
         "qmk_get_mo_vgl": ([P, P, I64, I32, P], I32),
+        "qmk_get_mo_vgl_noalloc": ([P, P, I64, I32, P], I32),
         "qmk_get_mo_value": ([P, P, I64, I32, P], I32),
         "qmk_get_density": ([P, P, I64, P, I64, P], I32),
         "qmk_set_mo_cusp": ([P, I64, P, P], I32),
@@ -316,6 +317,17 @@ class Context:
         d = self.dims()
         out, dt = self._out(out, (d["walk_num"], d["elec_num"], 5, d["mo_num"]), dtype or torch.float64)
         self._check(self._lib.qmk_get_mo_vgl(self._h, _ptr(out), out.numel(), dt, _stream(stream)))
+        return out
+
+    def get_mo_vgl_noalloc(self, out, stream=None):
+        """mo_vgl into the caller's tensor `out` through the entry point that
+        allocates nothing (its AO array lives in the library's fixed 64 MiB
+        per-GPU scratch; see qmk_get_mo_vgl_noalloc)."""
+        if out is None:
+            raise ValueError("the no-allocation call writes into a caller tensor: pass out")
+        d = self.dims()
+        out, dt = self._out(out, (d["walk_num"], d["elec_num"], 5, d["mo_num"]), None)
+        self._check(self._lib.qmk_get_mo_vgl_noalloc(self._h, _ptr(out), out.numel(), dt, _stream(stream)))
         return out
 
     def set_mo_cusp(self, charge=None, r_cusp=None):

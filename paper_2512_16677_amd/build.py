@@ -36,6 +36,7 @@ SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [],
            ("ao_kernels.hip", [], None), ("adjoint_kernels.hip", [], None),
            ("cusp_kernels.hip", [], None), ("sort_kernels.hip", [], None),
            ("det_kernels.hip", [], None), ("jastrow_kernels.hip", [], None), ("convert_kernels.hip", [], None),
+           ("noalloc.hip", [], None),
            ("gemm_kernels.hip", [], None), ("gemm_bf16.hip", [], None)]
 SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"] + UNIT_FLAGS.get(u, []), f"gemm_kernels_u{u}")
             for u in range(1, 11)]

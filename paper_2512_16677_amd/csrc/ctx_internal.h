@@ -187,6 +187,8 @@ namespace qmk {
 
 // Helpers of context.cpp used by the batch executor.
 qmk_status fail(qmk_ctx ctx, qmk_status st, const std::string& msg);
+qmk_status bad_arg(qmk_ctx ctx, int k, const std::string& msg);
+qmk_status check_dev_arg(qmk_ctx ctx, int k, const void* p);
 qmk_status hip_fail(qmk_ctx ctx, hipError_t e, const char* what);
 bool valid_ctx(qmk_ctx ctx);
 qmk_status ensure_tables(qmk_ctx ctx);

@@ -291,6 +291,9 @@ int default_tile(const GemmProblem& p);
 // stream s the first time p is seen.  *err receives a HIP error, if any.
 int choose_tile(const GemmProblem& p, int device, hipStream_t s,
                 const std::function<hipError_t(int)>& enqueue, hipError_t* err);
+// The tile an earlier decision recorded for p (this process, or the
+// persisted tables), else the least-padded-work tile; never times anything.
+int cached_tile(const GemmProblem& p, int device);
 void forget_tuning();
 // Raw access to the tile cache (batch executor): -1 if absent.
 int tune_cache_get(const std::string& key);

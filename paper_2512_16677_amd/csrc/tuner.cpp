@@ -175,6 +175,17 @@ int choose_tile(const GemmProblem& p, int device, hipStream_t s,
   return best;
 }
 
+int cached_tile(const GemmProblem& p, int device) {
+  const std::string key = key_of(p, device);
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_cache_locked();
+  auto it = g_cache.find(key);
+  if (it != g_cache.end() && it->second >= 0 && it->second < gemm_num_tiles(p.prec) &&
+      tile_feasible(p.prec, it->second))
+    return it->second;
+  return default_tile(p);
+}
+
 int tune_cache_get(const std::string& key) {
   std::lock_guard<std::mutex> lk(g_mu);
   load_cache_locked();
