@@ -34,6 +34,12 @@ PEAKS = {  # MI355X published dense peaks
     "bf16_TFLOPs": 2500.0,
 }
 MODE_DTYPE = {"fp64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3"}
+# precision modes whose contraction has a screened (block-sparse) form
+SCREENED_MODES = {"fp64": True, "mixed_f32": True, "mixed_bf16x3": False}
+# useful-flop ceiling of each mode's contraction: the dense MFMA peak of its
+# datatype (BF16x3 issues three bf16 products per useful one)
+MODE_PEAK_TF = {"fp64": PEAKS["fp64_TFLOPs"], "mixed_f32": PEAKS["fp32_TFLOPs"],
+                "mixed_bf16x3": PEAKS["bf16_TFLOPs"] / 3.0}
 
 
 def parse():
@@ -60,6 +66,10 @@ def parse():
                     help="walkers in the oracle's timed sample")
     ap.add_argument("--cpu-points", type=int, default=1000000,
                     help="grid points in the oracle's timed sample (density workload)")
+    ap.add_argument("--cpu-walkers-1t", type=int, default=4,
+                    help="walkers in the oracle's one-thread timed sample")
+    ap.add_argument("--quick", action="store_true",
+                    help="default workload only: skip the batch and 7500-AO workloads of the default line")
     return ap.parse_args()
 
 
@@ -122,7 +132,7 @@ def run_gpu(s, mode: str, steps: int, warmup: int, bits: int, keep_outputs: bool
     return ms, timing, outs
 
 
-def errors_vs(ref, got):
+def errors_vs(ref, got, quantile=True):
     """Mixed vs FP64 GPU results over the whole workload: row-normwise relative
     error of mo_vgl per component (max over points of max_n|diff| / max_n|ref|)
     and normwise error of each gradient (max|diff| / max|ref|)."""
@@ -134,7 +144,8 @@ def errors_vs(ref, got):
     e["value"] = float(r[:, 0].max())
     e["gradient"] = float(r[:, 1:4].max())
     e["laplacian"] = float(r[:, 4].max())
-    e["laplacian_p999"] = float(torch.quantile(r[:, 4].float(), 0.999))
+    if quantile:
+        e["laplacian_p999"] = float(torch.quantile(r[:, 4].float(), 0.999))
     for k in ("d_coef", "d_elec", "d_nucl"):
         e[k] = float((got[k] - ref[k]).abs().max() / ref[k].abs().max().clamp_min(1e-300))
     return e
@@ -205,16 +216,24 @@ def kernel_roofline(s, mode, timing):
     if timing["reduce"]["launches"]:
         out["reduce"] = {"avg_ms": timing["reduce"]["ms"] / timing["reduce"]["launches"],
                          "launches": timing["reduce"]["launches"]}
+    t = timing.get("convert", {"launches": 0})
+    if t["launches"]:  # W read in FP64, written as FP32 or as two bf16 planes: 12 B per element
+        avg = t["ms"] / t["launches"]
+        nbytes = 12.0 * P * 5 * N
+        out["convert"] = {"avg_ms": avg, "launches": t["launches"], "bytes": nbytes,
+                          "GBps": nbytes / (avg * 1e-3) / 1e9}
     return out
 
 
-def dominant_roofline(mode, kr):
-    """Roofline entry for the kernel class with the largest share of step time."""
+def dominant_roofline(mode, kr, traffic_lookup=True):
+    """Roofline entry for the kernel class with the largest share of step time
+    (the committed HBM counter figures belong to the medium workload, so other
+    workloads pass traffic_lookup=False)."""
     peak_key = {"fp64": "fp64_TFLOPs", "mixed_f32": "fp32_TFLOPs", "mixed_bf16x3": "bf16_TFLOPs"}[mode]
-    cands = {k: v for k, v in kr.items() if k != "reduce"}
+    cands = {k: v for k, v in kr.items() if k not in ("reduce", "convert")}
     name = max(cands, key=lambda k: cands[k]["avg_ms"] * cands[k]["launches"])
     d = cands[name]
-    traffic = measured_traffic(mode, name)
+    traffic = measured_traffic(mode, name) if traffic_lookup else None
     if "TFLOPs" in d:
         # BF16x3 issues three products per element; the algorithmic rate counts one
         roof = {"bound": "mfma", "achieved": d["TFLOPs"], "peak": PEAKS[peak_key], "unit": "TFLOP/s",
@@ -228,24 +247,44 @@ def dominant_roofline(mode, kr):
     return roof
 
 
-def cpu_baseline(walkers: int):
-    """The FP64 oracle, forward + adjoint, on a bounded sample of the workload."""
+def cpu_baseline(walkers: int, threads: int = 0):
+    """The FP64 oracle, forward + adjoint, on a bounded sample of the workload.
+    threads = 0: the oracle's default (all host cores); otherwise the sample
+    runs in a child process limited to that many OpenMP threads."""
     import oracle
     import synth
+    if threads:
+        import subprocess
+        code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+                "print(json.dumps(bench.cpu_baseline(%d)))" % (ROOT, walkers))
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                             timeout=900, check=True).stdout
+        res = json.loads(out.strip().splitlines()[-1])
+        res["cores"] = threads
+        return res
     s = synth.medium(walkers=walkers)
     w = synth.adjoint_weights(s, seed=1)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n_threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     oracle.mo_vgl(s)
     oracle.adjoint(s, w, with_abs=False)
     dt = time.perf_counter() - t0
-    return {"value": s.point_num / dt, "unit": "e-evals/s", "cores": threads, "kind": "oracle",
+    return {"value": s.point_num / dt, "unit": "e-evals/s", "cores": n_threads, "kind": "oracle",
             "sample": f"{walkers} walkers x {s.elec_num} electrons of the same 800-AO/400-MO "
                       f"system (forward + adjoint), {dt:.1f} s", "cpu_model": cpu_model()}
 
 
 def cpu_model() -> str:
-    """Model name of the host CPU (Linux), or an empty string."""
+    """Model name of the host CPU (lscpu, else /proc/cpuinfo), or an empty string."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for ln in out.splitlines():
+            if ln.strip().startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for ln in f:
@@ -256,9 +295,11 @@ def cpu_model() -> str:
     return ""
 
 
-def run_batch(mols, mode, steps, warmup, bits, batched=True):
+def run_batch(mols, mode, steps, warmup, bits, batched=True, keep_outputs=False):
     """Forward + adjoint of every molecule per step, as one batch (one graph
-    launch) or as a loop of single-context calls."""
+    launch) or as a loop of single-context calls.  Returns ms per step and,
+    with keep_outputs, the outputs of one more step on the first coordinates
+    (mo_vgl widened to FP64 and the three gradients, per molecule)."""
     import torch
     import paper_2512_16677_amd as qmk
     dev = torch.device("cuda:0")
@@ -269,7 +310,8 @@ def run_batch(mols, mode, steps, warmup, bits, batched=True):
         x.append((x[0] + 1e-3).contiguous())
     g = torch.Generator(device=dev)
     g.manual_seed(99)
-    ws = [torch.randn((m.walk_num, m.elec_num, 5, m.mo_num), generator=g, device=dev, dtype=dt) for m in mols]
+    ws = [torch.randn((m.walk_num, m.elec_num, 5, m.mo_num), generator=g, device=dev, dtype=torch.float64).to(dt)
+          for m in mols]
     outs = [torch.empty_like(w) for w in ws]
     grads = [{"d_coef": torch.empty((m.mo_num, m.ao_num), dtype=torch.float64, device=dev),
               "d_elec": torch.empty((m.walk_num, m.elec_num, 3), dtype=torch.float64, device=dev),
@@ -294,32 +336,99 @@ def run_batch(mols, mode, steps, warmup, bits, batched=True):
         step(i)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    kept = None
+    if keep_outputs:
+        step(0)
+        torch.cuda.synchronize()
+        kept = [{"mo": o.double(), **{k: v.clone() for k, v in gr.items()}} for o, gr in zip(outs, grads)]
     if b:
         b.close()
     for c in ctxs:
         c.close()
-    return ms
+    return (ms, kept) if keep_outputs else ms
+
+
+def batch_errors(ref, got):
+    """Mixed vs FP64 batch outputs: the largest row-normwise error of mo_vgl
+    per component over every molecule's points, and the largest normwise
+    error of each gradient over the molecules."""
+    e = {}
+    for rm, gm in zip(ref, got):
+        one = errors_vs(rm, gm, quantile=False)
+        for k, v in one.items():
+            e[k] = max(e.get(k, 0.0), v)
+    return e
+
+
+def batch_oracle_sample(mols, bits, outs, n_points=8):
+    """Row-normwise error of sampled mo_vgl rows of three molecules (first,
+    middle, last) against the oracle at the same B."""
+    import oracle
+    from tests.helpers import component_errors
+    worst = {}
+    for m in (0, len(mols) // 2, len(mols) - 1):
+        s = mols[m]
+        idx = np.linspace(0, s.point_num - 1, n_points).astype(np.int64)
+        rows = outs[m]["mo"].reshape(s.point_num, 5, s.mo_num)[idx].cpu().numpy()
+        e = component_errors(rows, oracle.mo_vgl(s, points=s.points()[idx], B=bits))
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    return worst
+
+
+def batch_workload(a, modes):
+    """The 96-molecule batch: e-evals/s per mode, the fraction of the summed
+    per-molecule MFMA ceilings, the speedup over a loop of single-context
+    calls, and the mixed forms' errors against the FP64 batch and the oracle."""
+    import synth
+    import torch
+    mols = synth.molecule_batch(96, seed=0)
+    pts = sum(m.point_num for m in mols)
+    flop = sum(3 * 2.0 * 5 * m.point_num * m.ao_num * m.mo_num for m in mols)  # fwd + 2 adjoint products
+    res = {}
+    ref = None
+    for mode in modes:
+        bits = 53 if mode == "fp64" else a.mixed_bits
+        ms_b, kept = run_batch(mols, mode, a.steps, a.warmup, bits, batched=True, keep_outputs=True)
+        ms_l = run_batch(mols, mode, max(2, a.steps // 4), 1, bits, batched=False)
+        peak = MODE_PEAK_TF[mode] * 1e12
+        res[mode] = {"value": pts / (ms_b * 1e-3), "unit": "e-evals/s", "ms_per_step": ms_b, "bits": bits,
+                     "ceiling_frac": (flop / peak) / (ms_b * 1e-3),
+                     "unbatched_ms_per_step": ms_l, "batching_speedup": ms_l / ms_b}
+        if mode == "fp64":
+            ref = kept
+            res[mode]["oracle_sample_error"] = batch_oracle_sample(mols, bits, kept)
+        else:
+            if ref is not None:
+                res[mode]["error_vs_fp64_gpu"] = batch_errors(ref, kept)
+            res[mode]["oracle_sample_error"] = batch_oracle_sample(mols, bits, kept)
+            res[mode]["speedup_vs_fp64_batch"] = res["fp64"]["ms_per_step"] / ms_b if "fp64" in res else None
+        del kept
+        torch.cuda.empty_cache()
+    del ref
+    torch.cuda.empty_cache()
+    return {"workload": "batch96: 96 C/H molecules, 4-60 atoms, 8-128 walkers each, one persistent-kernel "
+                        "HIP graph per step; forward + adjoint",
+            "points_per_step": pts, "molecules": len(mols),
+            "ao_range": [min(m.ao_num for m in mols), max(m.ao_num for m in mols)],
+            "ceiling_definition": "sum over molecules of 3 x 2 x 5 x P x K x N flop at the mode's dense MFMA "
+                                  "peak (BF16x3: a third of the bf16 peak), divided by the measured step",
+            "modes": res}
 
 
 def main_batch(a):
-    import synth
-    mols = synth.molecule_batch(96, seed=0)
-    pts = sum(m.point_num for m in mols)
-    res = {}
-    for mode in ["fp64"] + [v for v in a.variants.split(",") if v]:
-        bits = 53 if mode == "fp64" else a.mixed_bits
-        ms_b = run_batch(mols, mode, a.steps, a.warmup, bits, batched=True)
-        ms_l = run_batch(mols, mode, max(2, a.steps // 2), 1, bits, batched=False)
-        res[mode] = {"value": pts / (ms_b * 1e-3), "ms_per_step": ms_b,
-                     "unbatched_ms_per_step": ms_l, "batching_speedup": ms_l / ms_b}
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    modes = ["fp64"] + [v for v in a.variants.split(",") if v]
+    bw = batch_workload(a, modes)
+    res = bw["modes"]
     line = {"metric": METRIC, "value": res["fp64"]["value"], "unit": "e-evals/s", "n_gpus": 1,
             "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["fp64"]["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
-            "config": {"workload": "batch96: 96 C/H molecules, 4-60 atoms, 8-128 walkers each, "
-                                   "one persistent-kernel HIP graph per step; forward + adjoint",
-                       "points_per_step": pts, "molecules": len(mols),
-                       "ao_range": [min(m.ao_num for m in mols), max(m.ao_num for m in mols)]},
+            "config": {k: v for k, v in bw.items() if k != "modes"},
             "modes": res}
     print(json.dumps(line))
 
@@ -404,12 +513,17 @@ def main_density(a):
     print(json.dumps(line))
 
 
-def main_large(a):
-    """The 7500-AO / 1050-MO system at 64 walkers: forward (dense and screened
-    contraction) and forward + adjoint, per precision mode."""
+def large_workload(a):
+    """The 7500-AO / 1050-MO system at 64 walkers: forward + adjoint with the
+    dense and the screened contraction, per precision mode (FP64 at B = 53,
+    the mixed modes at B = 24), each with the roofline of its dominant kernel
+    class; the mixed forms' errors against the FP64 GPU path and, on sampled
+    rows, against the oracle at their own B."""
     import torch
+    import oracle
     import synth
     import paper_2512_16677_amd as qmk
+    from tests.helpers import component_errors
     s = synth.large(walkers=64)
     P, K, N = s.point_num, s.ao_num, s.mo_num
     dev = torch.device("cuda:0")
@@ -417,72 +531,90 @@ def main_large(a):
     r1 = (r0 + 1e-3).contiguous()
     g = torch.Generator(device=dev)
     g.manual_seed(5)
+    w64 = torch.randn((s.walk_num, s.elec_num, 5, N), generator=g, device=dev, dtype=torch.float64)
+    idx = np.linspace(0, P - 1, 8).astype(np.int64)
+    steps, warmup = max(2, a.steps // 4), max(1, a.warmup // 2)
     res = {}
+    ref = None
     for mode, bits in (("fp64", 53), ("mixed_f32", 24), ("mixed_bf16x3", 24)):
         ctx = qmk.Context.from_system(s, bits=bits, mode=mode)
         dt = torch.float64 if mode == "fp64" else torch.float32
+        w = w64.to(dt)
         mo = torch.empty((s.walk_num, s.elec_num, 5, N), dtype=dt, device=dev)
+        grads = {"d_coef": torch.empty((N, K), dtype=torch.float64, device=dev),
+                 "d_elec": torch.empty((s.walk_num, s.elec_num, 3), dtype=torch.float64, device=dev),
+                 "d_nucl": torch.empty((s.nucl_num, 3), dtype=torch.float64, device=dev)}
         out = {}
         for screened in (False, True):
-            if screened and mode == "mixed_bf16x3":
+            if screened and not SCREENED_MODES.get(mode, False):
+                out["screened"] = None  # this mode has no screened product; the dense one runs
                 continue
             ctx.set_screening(screened)
-            for i in range(a.warmup):
-                ctx.set_point(r0 if i % 2 == 0 else r1)
-                ctx.get_mo_vgl(out=mo)
-            torch.cuda.synchronize()
-            ctx.set_timing(True)
-            t0 = time.perf_counter()
-            for i in range(a.steps):
-                ctx.set_point(r0 if i % 2 == 0 else r1)
-                ctx.get_mo_vgl(out=mo)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / a.steps
-            t = ctx.timing()
             key = "screened" if screened else "dense"
-            out[key] = {"forward_ms": ms, "e_evals_per_s": P / (ms * 1e-3),
-                        "mo_ms": t["mo"]["ms"] / max(1, t["mo"]["launches"]),
-                        "ao_ms": t["ao"]["ms"] / max(1, t["ao"]["launches"])}
-            if screened:
-                out[key]["sort_ms"] = t["sort"]["ms"] / max(1, t["sort"]["launches"])
-                out[key]["screening_density"] = ctx.screening_density()
-            # forward + adjoint of sum(W * mo_vgl)
-            w = torch.randn((s.walk_num, s.elec_num, 5, N), generator=g, device=dev, dtype=dt)
-            for i in range(a.warmup):
+
+            def step(i):
                 ctx.set_point(r0 if i % 2 == 0 else r1)
                 ctx.get_mo_vgl(out=mo)
-                ctx.adjoint(w)
+                ctx.adjoint(w, out=grads)
+
+            for i in range(warmup):
+                step(i)
             torch.cuda.synchronize()
             ctx.set_timing(True)
             t0 = time.perf_counter()
-            for i in range(a.steps):
-                ctx.set_point(r0 if i % 2 == 0 else r1)
-                ctx.get_mo_vgl(out=mo)
-                ctx.adjoint(w)
+            for i in range(steps):
+                step(i)
             torch.cuda.synchronize()
-            ms2 = (time.perf_counter() - t0) * 1e3 / a.steps
+            ms = (time.perf_counter() - t0) * 1e3 / steps
             t = ctx.timing()
-            out[key]["fwd_adjoint_ms"] = ms2
-            out[key]["fwd_adjoint_e_evals_per_s"] = P / (ms2 * 1e-3)
-            out[key]["per_kernel_ms"] = {k: v["ms"] / v["launches"] for k, v in t.items() if v["launches"]}
-            del w
-            torch.cuda.empty_cache()
-        if "screened" in out:
-            out["forward_speedup"] = out["dense"]["forward_ms"] / out["screened"]["forward_ms"]
-            out["fwd_adjoint_speedup"] = out["dense"]["fwd_adjoint_ms"] / out["screened"]["fwd_adjoint_ms"]
-        out["mo_dense_TFLOPs"] = 2.0 * 5 * P * K * N / (out["dense"]["mo_ms"] * 1e-3) / 1e12
+            ctx.set_timing(False)
+            kr = kernel_roofline(s, mode, t)
+            out[key] = {"fwd_adjoint_ms": ms, "value": P / (ms * 1e-3), "unit": "e-evals/s",
+                        "roofline": dominant_roofline(mode, kr, traffic_lookup=False)}
+            if screened:
+                out[key]["screening_density"] = ctx.screening_density()
+                out[key]["roofline"]["note"] = ("achieved counts the dense product's flops; the screened "
+                                                "product skips all-zero AO chunks")
+            if not screened:
+                step(0)
+                torch.cuda.synchronize()
+                got = {"mo": mo.double().clone(), **{k: v.clone() for k, v in grads.items()}}
+                rows = got["mo"].reshape(P, 5, N)[torch.from_numpy(idx).to(dev)].cpu().numpy()
+                out["oracle_sample_error"] = component_errors(rows, oracle.mo_vgl(s, points=s.points()[idx],
+                                                                                  B=bits))
+                if mode == "fp64":
+                    ref = got
+                else:
+                    out["error_vs_fp64_gpu"] = errors_vs(ref, got)
+                    out["error_vs_fp64_gpu"]["note"] = "FP64 at B = 53, this mode at B = 24 (cutoff included)"
+                    del got
+        out["bits"] = bits
+        if out.get("screened"):
+            out["screened_speedup"] = out["dense"]["fwd_adjoint_ms"] / out["screened"]["fwd_adjoint_ms"]
         ctx.close()
-        del mo
+        del mo, w, grads
         torch.cuda.empty_cache()
         res[mode] = out
+    del ref, w64
+    torch.cuda.empty_cache()
+    return {"workload": f"ch300_7500ao: 150 C + 150 H in a 35-bohr cube, {K} AOs, {N} MOs, "
+                        f"{s.elec_num} electrons, 64 walkers; forward + adjoint",
+            "points_per_step": P, "steps": steps, "warmup": warmup, "modes": res}
+
+
+def main_large(a):
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    lw = large_workload(a)
+    res = lw["modes"]
     line = {"metric": "mo_vgl electron-evals/s (fwd+adjoint), dense vs screened contraction",
-            "value": res["fp64"]["screened"]["fwd_adjoint_e_evals_per_s"], "unit": "e-evals/s", "n_gpus": 1,
-            "steps": a.steps, "warmup": a.warmup, "ms_per_step": res["fp64"]["screened"]["fwd_adjoint_ms"],
+            "value": res["fp64"]["screened"]["value"], "unit": "e-evals/s", "n_gpus": 1,
+            "steps": lw["steps"], "warmup": lw["warmup"], "ms_per_step": res["fp64"]["screened"]["fwd_adjoint_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
-            "config": {"workload": f"ch300_7500ao: 150 C + 150 H in a 35-bohr cube, {K} AOs, {N} MOs, "
-                                   f"{s.elec_num} electrons, 64 walkers; forward + adjoint",
-                       "points_per_step": P},
+            "config": {"workload": lw["workload"], "points_per_step": lw["points_per_step"]},
             "modes": res}
     print(json.dumps(line))
 
@@ -739,7 +871,10 @@ def main():
         "config": {"workload": f"ch80_800ao: 40 C + 40 H in a 20-bohr cube, {s.ao_num} AOs, "
                                f"{s.mo_num} MOs, {s.elec_num} electrons, {s.walk_num} walkers; "
                                "forward + adjoint", "points_per_step": s.point_num,
-                   "bits": bits, "mode": a.mode},
+                   "bits": bits, "mode": a.mode,
+                   "ao_values": "retained from the forward pass for dL/dC (memoised AO array of the "
+                                "current points); AO derivatives up to third order recomputed for "
+                                "dL/dR_elec and dL/dR_nucl"},
         "roofline": roof,
         "step_ms_spread": timing.get("_step_ms"),
     }
@@ -756,13 +891,48 @@ def main():
                        "roofline": dominant_roofline(m, kv)}
         if vout is not None:
             variants[m]["error_vs_fp64_gpu"] = errors_vs(ref_out, vout)
+            variants[m]["oracle_sample_error"] = oracle_sample(s, vout, a.mixed_bits)
         del vout
         torch.cuda.empty_cache()
     if variants:
         line["variants"] = variants
+    if ref_out is not None:
+        line["oracle_sample_error"] = oracle_sample(s, ref_out, bits)
+    del ref_out
+    torch.cuda.empty_cache()
+    if not a.quick:
+        line["workloads"] = {
+            "batch96": batch_workload(a, ["fp64"] + variants_list),
+            "ch300_7500ao": large_workload(a),
+        }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(a.cpu_walkers)
+        line["cpu_baseline_1thread"] = cpu_baseline(a.cpu_walkers_1t, threads=1)
     print(json.dumps(line))
+
+
+def oracle_sample(s, out, bits, n_points=16):
+    """Errors of sampled rows against the oracle at the same B: row-normwise
+    mo_vgl per component, and dLoss/dR_elec of those points relative to the
+    sum of |terms| (the weights of those rows are regenerated from the
+    benchmark's seed)."""
+    import torch
+    import oracle
+    from tests.helpers import component_errors, grad_err
+    P, N = s.point_num, s.mo_num
+    idx = np.linspace(0, P - 1, n_points).astype(np.int64)
+    it = torch.from_numpy(idx).to(out["mo"].device)
+    rows = out["mo"].reshape(P, 5, N)[it].double().cpu().numpy()
+    e = component_errors(rows, oracle.mo_vgl(s, points=s.points()[idx], B=bits))
+    g = torch.Generator(device=out["mo"].device)
+    g.manual_seed(1234)
+    w = torch.randn((s.walk_num, s.elec_num, 5, N), generator=g, device=out["mo"].device, dtype=torch.float64)
+    w_rows = w.reshape(P, 5, N)[it].cpu().numpy()
+    del w
+    r = oracle.adjoint(s, w_rows, points=s.points()[idx], B=bits)
+    e["d_elec_rows"] = grad_err(out["d_elec"].reshape(P, 3)[it].cpu().numpy(), r["d_elec"], r["d_elec_abs"])
+    e["points"] = int(n_points)
+    return e
 
 
 if __name__ == "__main__":

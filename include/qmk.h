@@ -334,7 +334,9 @@ enum {
   QMK_KERNEL_DET = 9,        /* determinants and adjugates             */
   QMK_KERNEL_JASTROW = 10,   /* Jastrow: rescaled distances, final sum */
   QMK_KERNEL_JASTROW_P = 11, /* Jastrow: the P product on MFMA         */
-  QMK_KERNEL_CLASSES = 12
+  QMK_KERNEL_CONVERT = 12,   /* adjoint: W rounded to FP32 or split into
+                                bf16 hi / lo planes (mixed modes)       */
+  QMK_KERNEL_CLASSES = 13
 };
 qmk_status qmk_set_timing(qmk_ctx ctx, int32_t enable);
 qmk_status qmk_get_timing(qmk_ctx ctx, int32_t kernel_class, double* total_ms, int64_t* launches);

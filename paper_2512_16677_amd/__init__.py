@@ -54,7 +54,7 @@ EXPORTED = [
 ]
 
 KERNEL_CLASSES = ["ao", "mo", "gbar", "ao_adjoint", "dcoef", "reduce", "density", "cusp", "sort", "det",
-                  "jastrow", "jastrow_p"]
+                  "jastrow", "jastrow_p", "convert"]
 
 _lib = None
 

@@ -41,6 +41,8 @@ SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [],
 SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"] + UNIT_FLAGS.get(u, []), f"gemm_kernels_u{u}")
             for u in range(1, 11)]
 SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"] + VGPR_ACC, f"gemm_bf16_u{u}") for u in range(1, 4)]
+SOURCES += [("gemm_bf16p.hip", [], None)]
+SOURCES += [("gemm_bf16p.hip", [f"-DQMK_GEMM_UNIT={u}"] + VGPR_ACC, f"gemm_bf16p_u{u}") for u in range(1, 4)]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

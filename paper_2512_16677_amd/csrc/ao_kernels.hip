@@ -17,13 +17,42 @@
 // The value-only form (VAL = true) serves the MO values and the density on a
 // grid (Section 5.4, orbital visualisation): it accumulates only g0 and stores
 // one [ao][point] plane.
+#include <type_traits>
+
 #include "qmk_internal.h"
 
 namespace qmk {
 namespace {
 
 template <typename T>
-__device__ __forceinline__ void st(T* p, double v) { *p = static_cast<T>(v); }
+__device__ __forceinline__ void st(T* p, double v, int64_t) { *p = static_cast<T>(v); }
+
+// BF16x3 mode: the AO array is stored as two bf16 planes, hi = bf16(x) and
+// lo = bf16(x - hi) of the FP32-rounded value x, the lo plane `plane`
+// elements after the hi plane.  The two lanes of each even/odd pair swap one
+// half, so that every lane writes one 32-bit word: the even lane the hi
+// values of its point and the next, the odd lane the lo values of the
+// previous point and its own.  A wave's store therefore covers 128 bytes of
+// each plane, and both lanes of every pair must take part.
+struct Bf16Pair {
+  uint16_t bits;
+};
+__device__ __forceinline__ void st(Bf16Pair* p, double v, int64_t plane) {
+  const float f = static_cast<float>(v);
+  const __bf16 h = static_cast<__bf16>(f);
+  const __bf16 l = static_cast<__bf16>(f - static_cast<float>(h));
+  const uint32_t hb = __builtin_bit_cast(uint16_t, h), lb = __builtin_bit_cast(uint16_t, l);
+  const bool odd = (threadIdx.x & 1) != 0;
+  // quad_perm [1, 0, 3, 2]: exchange with the neighbouring lane
+  const uint32_t recv = static_cast<uint32_t>(
+      __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? hb : lb), 0xB1, 0xF, 0xF, true));
+  // one store instruction for the whole wave: the address and the word are
+  // selected per lane
+  uint16_t* q = reinterpret_cast<uint16_t*>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(odd ? q - 1 + plane : q);
+  const uint32_t word = odd ? ((recv & 0xffffu) | (lb << 16)) : (hb | (recv << 16));
+  *dst = word;
+}
 
 // Stores value, gradient and Laplacian of the (l+1)(l+2)/2 Cartesian AOs of
 // one shell for this lane's point.  l is wave-uniform; the components run in
@@ -35,7 +64,7 @@ template <typename OutT>
 __device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz, double u,
                                           double g0, double g1, double g2,
                                           const double* __restrict__ M, OutT* __restrict__ o,
-                                          int64_t sK, int64_t sC) {
+                                          int64_t sK, int64_t sC, int64_t plane) {
   const double lapr = (4.0 * l + 6.0) * g1 + 4.0 * u * g2;
   const double tg1 = 2.0 * g1;
   const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
@@ -56,11 +85,11 @@ __device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz
       const double m = M[idx];
       const double tp = P * tg1;
       OutT* q = o + idx * sK;
-      st(q, m * P * g0);
-      st(q + sC, m * (X.v1 * yz * g0 + dx * tp));
-      st(q + 2 * sC, m * (X.v0 * Y.v1 * Z.v0 * g0 + dy * tp));
-      st(q + 3 * sC, m * (X.v0 * Y.v0 * Z.v1 * g0 + dz * tp));
-      st(q + 4 * sC, m * (lapP * g0 + P * lapr));
+      st(q, m * P * g0, plane);
+      st(q + sC, m * (X.v1 * yz * g0 + dx * tp), plane);
+      st(q + 2 * sC, m * (X.v0 * Y.v1 * Z.v0 * g0 + dy * tp), plane);
+      st(q + 3 * sC, m * (X.v0 * Y.v0 * Z.v1 * g0 + dz * tp), plane);
+      st(q + 4 * sC, m * (lapP * g0 + P * lapr), plane);
     }
     if (b > 0) {
       --b;
@@ -87,20 +116,20 @@ __device__ __forceinline__ void shell_value(int l, double dx, double dy, double 
       const double px = a == 0 ? 1.0 : (a == 1 ? dx : (a == 2 ? dx2 : dx3));
       const double py = b == 0 ? 1.0 : (b == 1 ? dy : (b == 2 ? dy2 : dy3));
       const double pz = c == 0 ? 1.0 : (c == 1 ? dz : (c == 2 ? dz2 : dz3));
-      st(o + idx * sK, M[idx] * (px * py * pz) * g0);
+      st(o + idx * sK, M[idx] * (px * py * pz) * g0, 0);
     }
   }
 }
 
 template <typename OutT, bool VAL>
 __device__ __forceinline__ void shell_zero(int l, OutT* __restrict__ o, int64_t sK, int64_t sC,
-                                           bool store) {
+                                           int64_t plane, bool store) {
   if (!store) return;
   const int n = (l + 1) * (l + 2) / 2;
   for (int i = 0; i < n; ++i) {
     OutT* q = o + i * sK;
 #pragma unroll
-    for (int c = 0; c < (VAL ? 1 : 5); ++c) q[c * sC] = OutT(0);
+    for (int c = 0; c < (VAL ? 1 : 5); ++c) st(q + c * sC, 0.0, plane);
   }
 }
 
@@ -129,6 +158,7 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
   }
   OutT* const obase = static_cast<OutT*>(out.out) + p * out.sP;
   const double T = t.T;
+  constexpr bool kPairs = std::is_same<OutT, Bf16Pair>::value;
 
   for (int a = 0; a < nn; ++a) {
     const NucDev nu = s_nuc[a];
@@ -138,7 +168,7 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
     if (!__any(near)) {
       for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
         const ShellDev sh = s_shell[s];
-        shell_zero<OutT, VAL>(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, valid);
+        shell_zero<OutT, VAL>(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, out.plane, valid || kPairs);
       }
       continue;
     }
@@ -166,20 +196,22 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
         const int c1 = (sh.ao_off + (sh.l + 1) * (sh.l + 2) / 2 - 1) / kSparseChunk;
         for (int c = c0; c <= c1; ++c) atomicOr(w + (c >> 5), 1u << (c & 31));
       }
-      if (valid) {
+      // (the split-plane store needs both lanes of every pair: lanes past the
+      // last point store the zeros their empty sums give)
+      if (valid || kPairs) {
         if (VAL)
           shell_value(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, g0,
                       t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK);
         else
           shell_vgl(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2,
-                    t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK, out.sC);
+                    t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK, out.sC, out.plane);
       }
     }
   }
 }
 
 template <typename OutT, bool VAL>
-__global__ __launch_bounds__(256) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
+__global__ __launch_bounds__(256, 4) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
   extern __shared__ __align__(16) unsigned char smem[];
   ao_vgl_body<OutT, VAL>(t, pts, out, blockIdx.x, blockIdx.y, smem);
 }
@@ -223,7 +255,9 @@ hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& o
   if (pts.P <= 0 || t.n_groups <= 0) return hipSuccess;
   const size_t smem = static_cast<size_t>(t.smem_bytes);
   dim3 grid(static_cast<unsigned>((pts.P + 255) / 256), static_cast<unsigned>(t.n_groups));
-  if (out_is_f32)
+  if (out_is_f32 == 2)
+    hipLaunchKernelGGL((ao_vgl_kernel<Bf16Pair, false>), grid, dim3(256), smem, s, t, pts, out);
+  else if (out_is_f32)
     hipLaunchKernelGGL((ao_vgl_kernel<float, false>), grid, dim3(256), smem, s, t, pts, out);
   else
     hipLaunchKernelGGL((ao_vgl_kernel<double, false>), grid, dim3(256), smem, s, t, pts, out);

@@ -354,7 +354,8 @@ qmk_status check_ready(qmk_ctx ctx, bool need_coef) {
 qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
   qmk_status st = ensure_tables(ctx);
   if (st != QMK_OK) return st;
-  const int f32 = ctx->f32_storage() ? 1 : 0;
+  // 0: FP64; 1: FP32; 2: bf16 hi and lo planes (BF16x3 mode), same bytes as FP32
+  const int f32 = ctx->ao_format();
   const int64_t Pp = round_up(ctx->P(), kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
   if (ctx->ao_date == ctx->date && ctx->ao_f32 == f32 && ctx->ao_Pp == Pp && ctx->ao_Kp == Kp)
     return QMK_OK;
@@ -369,6 +370,7 @@ qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
     ctx->ao_f32 = f32;
   }
   AoOut o{ctx->ao.p, 5 * Pp, Pp, 1};
+  o.plane = Kp * 5 * Pp;
   {
     LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
     QMK_HIP(ctx, launch_ao_vgl(ctx->tab, point_args(ctx), o, f32, f32, s), "AO kernel");
@@ -634,7 +636,7 @@ qmk_status ensure_cusp(qmk_ctx ctx, hipStream_t s) {
 Prec product_prec(qmk_ctx ctx, GemmKind kind) {
   if (kind == GemmKind::kJastrow) return Prec::kF64;
   const Prec p = gemm_prec(ctx);
-  return kind == GemmKind::kDensity && p == Prec::kBF16x3 ? Prec::kF32 : p;
+  return kind == GemmKind::kDensity && (p == Prec::kBF16x3 || p == Prec::kBF16P) ? Prec::kF32 : p;
 }
 
 qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
@@ -660,7 +662,7 @@ bool w_vec_ok(const void* w, int64_t N, int w32) {
 }
 
 Prec gemm_prec(qmk_ctx ctx) {
-  return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16x3);
+  return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16P);
 }
 
 GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void* Ct_hi,
@@ -670,7 +672,7 @@ GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void*
   g.L = g.Lchunk = N;
   g.nsplit = 1;
   g.nbatch = 5;
-  if (prec == Prec::kBF16x3) {
+  if (prec == Prec::kBF16x3 || prec == Prec::kBF16P) {
     // rows k, columns p (as below, so that Gbar is stored in full lines);
     // both operands are read along the reduction index n, as this kernel
     // needs
@@ -1331,11 +1333,12 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   ga.sAl = 5 * Pp;
   ga.oAc = Pp;
   if (ctx->mode == QMK_MIXED_BF16X3) {
-    ga.B = ctx->d_Cb_hi.p;  // C [n][k]: reduction index contiguous
+    // AO array as bf16 hi / lo planes, C [n][k] split (reduction index contiguous)
+    ga.A2 = static_cast<const uint16_t*>(ctx->ao.p) + ctx->ao_Kp * 5 * Pp;
+    ga.B = ctx->d_Cb_hi.p;
     ga.B2 = ctx->d_Cb_lo.p;
     ga.sBl = 1;
     ga.sBj = ctx->Kp;
-    ga.vec_ok = 3;
   } else {
     ga.B = ctx->d_Ct.p;
     ga.sBl = ctx->Np;
@@ -1562,10 +1565,24 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     // does the same rounding and halves the bytes both products read
     const int64_t n = P * 5 * N;
     QMK_HIP(ctx, ctx->w_f32.ensure(static_cast<size_t>(n) * 4), "alloc FP32 W");
-    LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
+    LaunchTimer lt(ctx, QMK_KERNEL_CONVERT, s);
     QMK_HIP(ctx, launch_f64_to_f32(static_cast<const double*>(w), ctx->w_f32.as<float>(), n, s), "convert W");
     w = ctx->w_f32.p;
     w32 = 1;
+  }
+  // BF16x3 mode: W split once into bf16 hi / lo planes [Pp][5][Nw], read by
+  // both products (the W C product along n, the W^T ao product along p)
+  const bool planes = prec == Prec::kBF16P;
+  const int64_t Nw = round_up(N, 32);
+  const uint16_t *w_hi = nullptr, *w_lo = nullptr;
+  if (planes) {
+    const size_t plane = static_cast<size_t>(Pp) * 5 * static_cast<size_t>(Nw);
+    QMK_HIP(ctx, ctx->w_split.ensure(plane * 4), "alloc split W");
+    w_hi = ctx->w_split.as<uint16_t>();
+    w_lo = w_hi + plane;
+    LaunchTimer lt(ctx, QMK_KERNEL_CONVERT, s);
+    QMK_HIP(ctx, launch_split_w(w, w32, P, N, Pp, Nw, const_cast<uint16_t*>(w_hi), const_cast<uint16_t*>(w_lo), s),
+            "split W");
   }
   if (scr) {
     // W in the sorted point order, once, so that both products read it with
@@ -1587,8 +1604,13 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ctx->gbar_Kp = Kp;
       ctx->gbar_f32 = f32;
     }
-    GemmArgs ga = gbar_args(prec, w, w32, ctx->d_C.p, ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p, ctx->gbar.p, P,
-                            Pp, K, Kp, N, Np);
+    GemmArgs ga = gbar_args(prec, planes ? static_cast<const void*>(w_hi) : w, w32, ctx->d_C.p,
+                            ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p, ctx->gbar.p, P, Pp, K, Kp, N, Np);
+    if (planes) {
+      ga.B2 = w_lo;
+      ga.sBj = 5 * Nw;
+      ga.oBc = Nw;
+    }
     if (scr) screen(ga);
     GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
     pb.sparse = scr ? 1 : 0;
@@ -1674,6 +1696,14 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ga.sBj = 5 * Pp;
       ga.oBc = Pp;
       ga.oBs = chunk;
+      if (planes) {  // W and the AO array as bf16 hi / lo planes
+        ga.A = w_hi;
+        ga.A2 = w_lo;
+        ga.sAl = 5 * Nw;
+        ga.oAc = Nw;
+        ga.oAs = chunk * 5 * Nw;
+        ga.B2 = static_cast<const uint16_t*>(ao_arr) + ctx->ao_Kp * 5 * Pp;
+      }
       ga.D = ctx->ws_dc.p;
       ga.sDi = Kp;
       ga.sDj = 1;

@@ -1,4 +1,5 @@
-// FP64 -> FP32 conversion of the adjoint's weights in the FP32 mode.
+// Conversions of the adjoint's weights W: FP64 -> FP32 in the FP32 mode, and
+// the split into bf16 hi / lo planes in the BF16x3 mode.
 //
 // The FP32 products round each FP64 weight to FP32 as they load it; doing
 // that once per call in a streaming pass (round to nearest, as the loaders
@@ -21,7 +22,72 @@ __global__ __launch_bounds__(256) void f64_to_f32_kernel(const double* __restric
   }
 }
 
+// W[p][c][n] -> hi, lo planes [Pp][5][Nw]: hi = bf16(x), lo = bf16(x - hi) of
+// the FP32-rounded weight x (round to nearest even); zeros beyond P and N.
+// One thread per eight consecutive n of one (p, c) row.
+template <typename T>
+__global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, int64_t P, int64_t N, int64_t Pp,
+                                                      int64_t Nw, int vec, __bf16* __restrict__ hi,
+                                                      __bf16* __restrict__ lo) {
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  const int64_t cpr = Nw / 8;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= Pp * 5 * cpr) return;
+  const int64_t row = idx / cpr, n0 = (idx - row * cpr) * 8;
+  float x[8];
+  if (row < P * 5 && vec && n0 + 8 <= N) {
+    const T* src = w + row * N + n0;
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = *reinterpret_cast<const double2*>(src + 2 * q);
+        x[2 * q] = static_cast<float>(v.x);
+        x[2 * q + 1] = static_cast<float>(v.y);
+      }
+    } else {
+      const float4 a = *reinterpret_cast<const float4*>(src);
+      const float4 b = *reinterpret_cast<const float4*>(src + 4);
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+      x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      x[e] = (row < P * 5 && n0 + e < N) ? static_cast<float>(w[row * N + n0 + e]) : 0.0f;
+  }
+  bf16x8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 hh = static_cast<__bf16>(x[e]);
+    h[e] = hh;
+    l[e] = static_cast<__bf16>(x[e] - static_cast<float>(hh));
+  }
+  *reinterpret_cast<bf16x8*>(hi + row * Nw + n0) = h;
+  *reinterpret_cast<bf16x8*>(lo + row * Nw + n0) = l;
+}
+
 }  // namespace
+
+hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw, void* hi,
+                          void* lo, hipStream_t s) {
+  if (Pp <= 0 || Nw <= 0) return hipSuccess;
+  if (Nw % 8 != 0 || Pp < P || Nw < N) return hipErrorInvalidValue;
+  const int64_t n = Pp * 5 * (Nw / 8);
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t esz = w_is_f32 ? 4 : 8;
+  // vector loads need every group of eight weights to start 16-byte aligned
+  const int vec = reinterpret_cast<uintptr_t>(w) % 16 == 0 && (N * esz) % 16 == 0;
+  if (w_is_f32)
+    hipLaunchKernelGGL(split_w_kernel<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<const float*>(w), P, N, Pp, Nw, vec, static_cast<__bf16*>(hi),
+                       static_cast<__bf16*>(lo));
+  else
+    hipLaunchKernelGGL(split_w_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<const double*>(w), P, N, Pp, Nw, vec, static_cast<__bf16*>(hi),
+                       static_cast<__bf16*>(lo));
+  return hipGetLastError();
+}
 
 hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

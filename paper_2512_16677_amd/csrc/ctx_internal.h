@@ -144,6 +144,7 @@ struct qmk_ctx_s {
 
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
   DevBuf w_f32;  // FP32 copy of FP64 adjoint weights (FP32 mode)
+  DevBuf w_split;  // adjoint weights as bf16 hi and lo planes [Pp][5][Nw] (BF16x3 mode)
   int64_t gbar_Pp = 0, gbar_Kp = 0;
   int gbar_f32 = -1;
 
@@ -170,6 +171,9 @@ struct qmk_ctx_s {
 
   int64_t P() const { return walk_num * elec_num; }
   bool f32_storage() const { return mode != QMK_FP64; }
+  // layout of the context's AO array: 0 FP64, 1 FP32, 2 bf16 hi and lo
+  // planes (the BF16x3 products read pre-split operands)
+  int ao_format() const { return mode == QMK_FP64 ? 0 : (mode == QMK_MIXED_F32 ? 1 : 2); }
 };
 
 

@@ -1,0 +1,430 @@
+// BF16x3 contraction on pre-split operands (mixed precision mode).
+//
+// Every operand arrives as two bf16 planes, hi = bf16(x) and lo = bf16(x - hi)
+// (x rounded to FP32 first), written once by its producer: the AO kernel
+// writes the AO array as two planes, a streaming pass splits the adjoint
+// weights W, and C is split when it is set.  A product is then
+//   a b  ~  a_lo b_hi + a_hi b_lo + a_hi b_hi
+// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the dropped lo*lo term
+// is ~2^-18 |a b|), and the loop does no arithmetic on the operands: global
+// loads go straight to LDS through registers, 16 bytes per lane.
+//
+// Layouts.  B is always reduction-major ("K-major": eight consecutive
+// reduction indices are contiguous) and is staged as [row][k], 64 bytes per
+// row with its 16-byte chunks XOR-permuted by row bits (see kswz), so that
+// the 16-byte fragment reads and the stores of the lanes served in one LDS
+// cycle hit different bank groups.  A is either K-major (the
+// W C product reads C^T) or row-major ("MN-major": the AO array in the forward
+// product and W in the W^T ao product have their points / MOs contiguous);
+// an MN-major A is staged as [k][row] and its MFMA fragments are read with
+// gfx950's transposing LDS load (ds_read_b64_tr_b16), which hands lane i of
+// each 16-lane group four consecutive k of row i.  Its row pitch is padded to
+// 32 or 96 bytes modulo 128, so the four k-rows one 16-lane group touches lie
+// in four different 32-byte bank windows.
+//
+// Loads are unguarded along the reduction index: every operand buffer is
+// zero-padded to a multiple of 32 there.  Rows past the operand's row count
+// are staged as zeros (their chunks are loaded from the last row in range, so
+// every load stays in bounds).  Stores are guarded on both indices.
+#include <algorithm>
+
+#include "qmk_internal.h"
+
+namespace qmk {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+constexpr int BK = 32;
+// K-major staging: rows of BK elements (64 bytes, no padding); 16-byte chunk
+// c of row r sits at chunk c ^ kswz(r).  Eight consecutive rows read at one
+// chunk then cover all eight 16-byte bank groups of 128 bytes, and sixteen
+// rows all sixteen of 256 bytes; a thread's stores (four chunks of a row,
+// rows in order) are permutations of contiguous runs.
+constexpr int KLD = BK;
+// Only bits 1..3 of the row enter, so a 16-row fragment block (rows r0 + i,
+// r0 a multiple of 16) has the swizzle of i.
+__device__ __forceinline__ int kswz(int r) { return ((r >> 1) & 3) ^ (((r >> 3) & 1) * 3); }
+
+// MN-major staging pitch (elements) for R rows: R*2 bytes made 32 or 96 mod 128.
+constexpr int mn_pitch(int R) { return ((R * 2) % 128 == 32 || (R * 2) % 128 == 96) ? R : R + 16; }
+
+template <int BM, int BN, bool A_MN>
+struct PSmem {
+  static constexpr int A_ELEMS = A_MN ? BK * mn_pitch(BM) : BM * KLD;
+  static constexpr int B_ELEMS = BN * KLD;
+  __bf16 A[2][2][A_ELEMS];  // [buffer][hi, lo]
+  __bf16 B[2][2][B_ELEMS];
+};
+
+// One operand tile (R rows x BK reduction indices, both planes) in flight:
+// 16-byte chunks spread over NT threads, the same chunks of both planes per
+// thread.  Element (row, l) of a plane is at plane[row * s_row + l * s_l];
+// MN: s_row = 1 (chunks of 8 rows at one l), else s_l = 1 (chunks of 8 l of
+// one row).  The byte offset of every chunk from the tile's base and its
+// staging offset are computed once per tile; a K step only moves the two
+// (wave-uniform) plane pointers.  When NT does not divide the chunk count,
+// the surplus threads load and store a chunk again (the same bytes to the
+// same place); a chunk past the last row in range is loaded from that last
+// row and stored as zeros, so every load is in bounds and unconditional.
+template <int R, int NT, bool MN>
+struct PTile {
+  static constexpr int CH = MN ? BK * (R / 8) : R * (BK / 8);  // chunks per plane
+  static constexpr int PER = (CH + NT - 1) / NT;
+  uint32_t goff[PER];  // byte offset from the tile's plane base
+  int32_t loff[PER];   // element offset in one plane's staging buffer
+  bool ok[PER];
+  u32x4 v[2][PER];
+
+  __device__ __forceinline__ void init(int64_t s_row, int64_t s_l, int64_t rows_left, int tid) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      int q = tid + NT * u;
+      if (CH % NT != 0) q %= CH;
+      int64_t row, off;
+      if constexpr (MN) {
+        const int l = q / (R / 8);
+        row = static_cast<int64_t>(q % (R / 8)) * 8;
+        const int64_t rr = row < rows_left ? row : ((rows_left - 1) & ~int64_t(7));
+        off = rr + l * s_l;
+        loff[u] = l * mn_pitch(R) + static_cast<int>(row);
+      } else {
+        row = q / (BK / 8);
+        const int kq = q % (BK / 8);
+        const int64_t rr = row < rows_left ? row : rows_left - 1;
+        off = rr * s_row + kq * 8;
+        loff[u] = static_cast<int>(row) * KLD + (kq ^ kswz(static_cast<int>(row))) * 8;
+      }
+      goff[u] = static_cast<uint32_t>(off * 2);
+      ok[u] = row < rows_left;
+    }
+  }
+
+  __device__ __forceinline__ void load(const __bf16* hi, const __bf16* lo) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      v[0][u] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(hi) + goff[u]);
+      v[1][u] = *reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(lo) + goff[u]);
+    }
+  }
+
+  template <bool FULL>
+  __device__ __forceinline__ void stash(__bf16* hi, __bf16* lo) const {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      *reinterpret_cast<u32x4*>(hi + loff[u]) = (FULL || ok[u]) ? v[0][u] : u32x4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u32x4*>(lo + loff[u]) = (FULL || ok[u]) ? v[1][u] : u32x4{0u, 0u, 0u, 0u};
+    }
+  }
+};
+
+// MFMA fragment of rows r0 .. r0+15 of an MN-major staged tile: lane 16g + i
+// receives k = 8g .. 8g+7 of row r0 + i (two transposing 8-byte reads).
+template <int PITCH>
+__device__ __forceinline__ bf16x8 frag_mn(const __bf16* t, int r0, int lane) {
+  const int g = lane >> 4, q = lane & 15;
+  const __bf16* p0 = t + (8 * g + (q >> 2)) * PITCH + r0 + 4 * (q & 3);
+  const __bf16* p1 = p0 + 4 * PITCH;
+  const s16x4 x0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_s16x4*)((__attribute__((address_space(3))) char*)(p0)));
+  const s16x4 x1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_s16x4*)((__attribute__((address_space(3))) char*)(p1)));
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  const s16x8 x = __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, x);
+}
+
+// Fragment of a K-major staged tile: lane 16g + i receives k = 8g .. 8g+7 of
+// row r0 + i.
+__device__ __forceinline__ bf16x8 frag_k(const __bf16* t, int r0, int lane) {
+  // r0 is a multiple of 16, so the swizzle of row r0 + i is that of i
+  const int i = lane & 15;
+  return *reinterpret_cast<const bf16x8*>(t + (r0 + i) * KLD + ((lane >> 4) ^ kswz(i)) * 8);
+}
+
+// The K loop of one tile.  FULL: every row of both operand tiles is in
+// range (no zero fill).  The loop is unrolled by two so that both staging
+// buffers are compile-time constants.
+template <bool A_MN, bool FULL, int WGM, int WGN, int TM, int TN, int DEPTH>
+__device__ __forceinline__ void bf16p_loop(PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>& sm,
+                                           PTile<16 * WGM * TM, 64 * WGM * WGN, A_MN> (&la)[DEPTH],
+                                           PTile<16 * WGN * TN, 64 * WGM * WGN, false> (&lb)[DEPTH],
+                                           const __bf16* Ah, const __bf16* Al, const __bf16* Bh,
+                                           const __bf16* Bl, int64_t stepA, int64_t stepB, int64_t nk,
+                                           f32x4 (&acc)[TM][TN]) {
+  constexpr int BM = 16 * WGM * TM;
+  constexpr int AP = mn_pitch(BM);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w / WGN, wn = w % WGN;
+  auto load = [&](int r, int64_t kt) {
+    la[r].load(Ah + kt * stepA, Al + kt * stepA);
+    lb[r].load(Bh + kt * stepB, Bl + kt * stepB);
+  };
+  auto stash = [&](int r, int buf) {
+    la[r].template stash<FULL>(sm.A[buf][0], sm.A[buf][1]);
+    lb[r].template stash<FULL>(sm.B[buf][0], sm.B[buf][1]);
+  };
+  auto compute = [&](int buf) {
+    bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int r0 = (wm * TM + a) * 16;
+      if constexpr (A_MN) {
+        ah[a] = frag_mn<AP>(sm.A[buf][0], r0, lane);
+        al[a] = frag_mn<AP>(sm.A[buf][1], r0, lane);
+      } else {
+        ah[a] = frag_k(sm.A[buf][0], r0, lane);
+        al[a] = frag_k(sm.A[buf][1], r0, lane);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int r0 = (wn * TN + b) * 16;
+      bh[b] = frag_k(sm.B[buf][0], r0, lane);
+      bl[b] = frag_k(sm.B[buf][1], r0, lane);
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+      }
+  };
+
+  if (nk <= 0) return;
+  if constexpr (DEPTH == 1) {
+    load(0, 0);
+    stash(0, 0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      if (kt + 1 < nk) load(0, kt + 1);
+      compute(0);
+      if (kt + 1 < nk) stash(0, 1);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      if (kt + 2 < nk) load(0, kt + 2);
+      compute(1);
+      if (kt + 2 < nk) stash(0, 0);
+      __syncthreads();
+    }
+  } else {
+    load(0, 0);
+    stash(0, 0);
+    if (nk > 1) load(1, 1);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      // step kt from LDS buffer 0; registers 1 hold step kt+1
+      if (kt + 2 < nk) load(0, kt + 2);
+      compute(0);
+      if (kt + 1 < nk) stash(1, 1);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      // step kt+1 from LDS buffer 1; registers 0 hold step kt+2
+      if (kt + 3 < nk) load(1, kt + 3);
+      compute(1);
+      if (kt + 2 < nk) stash(0, 0);
+      __syncthreads();
+    }
+  }
+}
+
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+__device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, int z,
+                                           PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>& sm) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+  const int c = z / g.nsplit, s = z - c * g.nsplit;
+  const int64_t i0 = static_cast<int64_t>(mt) * BM, j0 = static_cast<int64_t>(nt) * BN;
+  const int64_t oa = c * g.oAc + s * g.oAs + i0 * g.sAi, ob = c * g.oBc + s * g.oBs + j0 * g.sBj;
+  const __bf16* Ah = static_cast<const __bf16*>(g.A) + oa;
+  const __bf16* Al = static_cast<const __bf16*>(g.A2) + oa;
+  const __bf16* Bh = static_cast<const __bf16*>(g.B) + ob;
+  const __bf16* Bl = static_cast<const __bf16*>(g.B2) + ob;
+  TD* __restrict__ Dp = static_cast<TD*>(g.D) + z * g.oDz;
+  const int64_t Ls = min(g.Lchunk, g.L - s * g.Lchunk);
+  const int tid = threadIdx.x;
+  const int64_t rows_a = g.M - i0, rows_b = g.N - j0;
+
+  // DEPTH register stages: the global loads of K step k + DEPTH are issued
+  // before the MFMAs of step k, so each load has DEPTH steps of MFMA work to
+  // arrive (DEPTH 2 costs one more operand tile of registers per thread).
+  PTile<BM, NT, A_MN> la[DEPTH];
+  PTile<BN, NT, false> lb[DEPTH];
+#pragma unroll
+  for (int r = 0; r < DEPTH; ++r) {
+    la[r].init(g.sAi, g.sAl, rows_a, tid);
+    lb[r].init(g.sBj, g.sBl, rows_b, tid);
+  }
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = (Ls + BK - 1) / BK;
+  const int64_t stepA = BK * g.sAl, stepB = BK * g.sBl;
+  if (rows_a >= BM && rows_b >= BN)
+    bf16p_loop<A_MN, true, WGM, WGN, TM, TN, DEPTH>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, acc);
+  else
+    bf16p_loop<A_MN, false, WGM, WGN, TM, TN, DEPTH>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, acc);
+
+  // accumulator element r of lane l: row 4 (l / 16) + r, column l % 16
+  const int lane = tid & 63, w = tid >> 6;
+  const int wm = w / WGN, wn = w % WGN;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + (wm * TM + a) * 16 + 4 * (lane >> 4) + r;
+        const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
+        if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+      }
+}
+
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(GemmArgs g, int nM, int nN) {
+  __shared__ __align__(16) PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN> sm;
+  int mt, nt, z;
+  if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
+  bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH>(g, mt, nt, z, sm);
+}
+
+// {WGM, WGN, TM, TN, DEPTH}; the reduction step is always 32.
+#define QMK_BF16P_TILE_LIST(X) \
+  X(0, 2, 2, 4, 4, 1)          \
+  X(1, 2, 2, 4, 4, 2)          \
+  X(2, 4, 2, 4, 4, 1)          \
+  X(3, 2, 4, 4, 4, 1)          \
+  X(4, 4, 1, 2, 5, 1)          \
+  X(5, 4, 1, 2, 5, 2)          \
+  X(6, 2, 2, 4, 2, 1)          \
+  X(7, 2, 2, 4, 2, 2)          \
+  X(8, 2, 2, 2, 4, 2)          \
+  X(9, 4, 2, 2, 4, 2)          \
+  X(10, 2, 2, 5, 5, 1)         \
+  X(11, 2, 1, 5, 5, 1)         \
+  X(12, 1, 2, 5, 5, 1)         \
+  X(13, 4, 1, 4, 5, 1)         \
+  X(14, 2, 4, 4, 2, 2)         \
+  X(15, 2, 2, 4, 5, 1)
+
+[[maybe_unused]] constexpr TileCfg kBfpTiles[] = {
+#define QMK_BFP_ENTRY(id, wgm, wgn, tm, tn, depth) {wgm, wgn, tm, tn, BK},
+    QMK_BF16P_TILE_LIST(QMK_BFP_ENTRY)
+#undef QMK_BFP_ENTRY
+};
+
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+hipError_t run_bfp_tile(const GemmArgs& g, hipStream_t s) {
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+  const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
+  if (nM <= 0 || nN <= 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH>), grid_of(g, nM, nN), dim3(64 * WGM * WGN),
+                     0, s, g, nM, nN);
+  return hipGetLastError();
+}
+
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+int bfp_occupancy() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH>, 64 * WGM * WGN, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+template <bool A_MN, typename TD>
+int occupancy_of(int cfg) {
+  switch (cfg) {
+#define QMK_BFP_OCC(id, wgm, wgn, tm, tn, depth) \
+  case id:                                       \
+    return bfp_occupancy<A_MN, TD, wgm, wgn, tm, tn, depth>();
+    QMK_BF16P_TILE_LIST(QMK_BFP_OCC)
+#undef QMK_BFP_OCC
+    default:
+      return 1;
+  }
+}
+
+template <bool A_MN, typename TD>
+hipError_t run_bfp(int cfg, const GemmArgs& g, hipStream_t s) {
+  switch (cfg) {
+#define QMK_BFP_CASE(id, wgm, wgn, tm, tn, depth) \
+  case id:                                        \
+    return run_bfp_tile<A_MN, TD, wgm, wgn, tm, tn, depth>(g, s);
+    QMK_BF16P_TILE_LIST(QMK_BFP_CASE)
+#undef QMK_BFP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+#ifdef QMK_GEMM_UNIT
+#if QMK_GEMM_UNIT == 1
+hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, hipStream_t s) {
+  return o32 ? run_bfp<true, float>(cfg, g, s) : run_bfp<true, double>(cfg, g, s);
+}
+#endif
+#if QMK_GEMM_UNIT == 2
+hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, hipStream_t s) { return run_bfp<false, float>(cfg, g, s); }
+#endif
+#if QMK_GEMM_UNIT == 3
+hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, hipStream_t s) { return run_bfp<true, double>(cfg, g, s); }
+int bf16p_unit_dc_occupancy(int cfg) { return occupancy_of<true, double>(cfg); }
+#endif
+#else
+// The three products are instantiated in their own translation units (this
+// file compiled with QMK_GEMM_UNIT = 1..3); the unit without it holds the
+// tile table and the dispatch.
+hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, hipStream_t s);
+hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, hipStream_t s);
+hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, hipStream_t s);
+int bf16p_unit_dc_occupancy(int cfg);
+
+int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg) {
+  if (kind != GemmKind::kDcoef || cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return 1;
+  return bf16p_unit_dc_occupancy(cfg);
+}
+
+int gemm_bf16p_num_tiles() { return sizeof(kBfpTiles) / sizeof(kBfpTiles[0]); }
+TileCfg gemm_bf16p_tile(int cfg) { return kBfpTiles[cfg]; }
+size_t gemm_bf16p_tile_lds_bytes(int cfg) {
+  const TileCfg& t = kBfpTiles[cfg];
+  const int bm = 16 * t.wgm * t.tm, bn = 16 * t.wgn * t.tn;
+  // the larger of the two staging layouts of A (MN-major for the forward and
+  // W^T ao products, K-major for the W C product)
+  const size_t a = std::max<size_t>(static_cast<size_t>(BK) * mn_pitch(bm), static_cast<size_t>(bm) * KLD);
+  return 2 * 2 * (a + static_cast<size_t>(bn) * KLD) * 2;
+}
+
+// forward: A = AO planes (MN-major), B = C planes [n][k]
+// Gbar:    A = C^T planes [k][n] (K-major), B = W planes [p][c][n]
+// dC:      A = W planes (MN-major over n), B = AO planes (K-major over p)
+hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s) {
+  if (cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return hipErrorInvalidValue;
+  // the loaders address a tile's chunks by 32-bit byte offsets from the
+  // tile's base: (rows - 1) * row stride + (BK - 1) * reduction stride + 8
+  const TileCfg& t = kBfpTiles[cfg];
+  const int64_t ea = (16 * t.wgm * t.tm - 1) * g.sAi + (BK - 1) * g.sAl + 8;
+  const int64_t eb = (16 * t.wgn * t.tn - 1) * g.sBj + (BK - 1) * g.sBl + 8;
+  if (ea < 0 || eb < 0 || 2 * ea > 0x7fffffffLL || 2 * eb > 0x7fffffffLL) return hipErrorInvalidValue;
+  switch (kind) {
+    case GemmKind::kForward: return bf16p_unit_fwd(cfg, g, out_is_f32, s);
+    case GemmKind::kGbar: return bf16p_unit_gbar(cfg, g, s);
+    case GemmKind::kDcoef: return bf16p_unit_dc(cfg, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#endif  // QMK_GEMM_UNIT
+
+}  // namespace qmk

@@ -86,9 +86,9 @@ extern "C" qmk_status qmk_get_mo_vgl_noalloc(qmk_ctx ctx, void* out, int64_t siz
                 "the device copies of the basis tables and MO coefficients for this precision mode are "
                 "not built: call qmk_get_mo_vgl once after the last set_nucleus, set_basis, set_mo_coef "
                 "or set_precision (that call allocates them)");
-  const int f32 = ctx->f32_storage() ? 1 : 0;
+  const int fmt = ctx->ao_format();  // 0 FP64, 1 FP32, 2 bf16 hi and lo planes
   const int64_t Pp = round_up(P, kPointPad), Kp = round_up(K, kAoPad);
-  const size_t need = static_cast<size_t>(Kp) * 5 * static_cast<size_t>(Pp) * (f32 ? 4 : 8);
+  const size_t need = static_cast<size_t>(Kp) * 5 * static_cast<size_t>(Pp) * (fmt ? 4 : 8);
   if (need > kScratchBytes)
     return fail(ctx, QMK_SIZE,
                 "the AO array of " + std::to_string(K) + " AOs at " + std::to_string(P) + " points needs " +
@@ -104,17 +104,24 @@ extern "C" qmk_status qmk_get_mo_vgl_noalloc(qmk_ctx ctx, void* out, int64_t siz
   const int64_t n_pad = rows * (Pp - P) + (total_rows - rows) * Pp;
   if (n_pad > 0) {
     const int blocks = static_cast<int>(std::min<int64_t>((n_pad + 255) / 256, 2048));
-    if (f32)
+    if (fmt == 2) {
+      uint16_t* hi = static_cast<uint16_t*>(ao);
+      for (uint16_t* plane : {hi, hi + total_rows * Pp})
+        hipLaunchKernelGGL(clear_ao_padding<uint16_t>, dim3(blocks), dim3(256), 0, s, plane, rows, P, Pp,
+                           total_rows);
+    } else if (fmt == 1) {
       hipLaunchKernelGGL(clear_ao_padding<float>, dim3(blocks), dim3(256), 0, s, static_cast<float*>(ao), rows,
                          P, Pp, total_rows);
-    else
+    } else {
       hipLaunchKernelGGL(clear_ao_padding<double>, dim3(blocks), dim3(256), 0, s, static_cast<double*>(ao),
                          rows, P, Pp, total_rows);
+    }
     QMK_HIP(ctx, hipGetLastError(), "clear AO padding");
     ++ctx->launches;
   }
-  const AoOut o{ao, 5 * Pp, Pp, 1};
-  QMK_HIP(ctx, launch_ao_vgl(ctx->tab, point_args(ctx), o, f32, f32, s), "AO kernel");
+  AoOut o{ao, 5 * Pp, Pp, 1};
+  o.plane = total_rows * Pp;
+  QMK_HIP(ctx, launch_ao_vgl(ctx->tab, point_args(ctx), o, fmt, fmt, s), "AO kernel");
   ++ctx->launches;
 
   GemmArgs ga{};
@@ -122,12 +129,12 @@ extern "C" qmk_status qmk_get_mo_vgl_noalloc(qmk_ctx ctx, void* out, int64_t siz
   ga.sAi = 1;
   ga.sAl = 5 * Pp;
   ga.oAc = Pp;
-  if (ctx->mode == QMK_MIXED_BF16X3) {
+  if (fmt == 2) {
+    ga.A2 = static_cast<const uint16_t*>(ao) + total_rows * Pp;
     ga.B = ctx->d_Cb_hi.p;
     ga.B2 = ctx->d_Cb_lo.p;
     ga.sBl = 1;
     ga.sBj = ctx->Kp;
-    ga.vec_ok = 3;
   } else {
     ga.B = ctx->d_Ct.p;
     ga.sBl = ctx->Np;

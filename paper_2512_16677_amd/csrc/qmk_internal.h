@@ -81,6 +81,10 @@ struct AoOut {
   // of the 64-point block of p has a non-zero AO in chunk c (16 AOs)
   uint32_t* act;
   int64_t act_words;
+  // split bf16 output (launch_ao_vgl with out_is_f32 = 2): elements from the
+  // hi plane at `out` to the lo plane; P must be padded to a multiple of 256
+  // and every point offset even
+  int64_t plane;
 };
 
 // Cusp correction tables (see cusp_kernels.hip).  One entry per nucleus
@@ -208,9 +212,13 @@ __device__ __forceinline__ AxisD axis_derivs(int e, double t, double t2, double 
 }
 
 enum class GemmKind { kForward, kGbar, kDcoef, kDensity, kJastrow };
-enum class Prec { kF64, kF32, kBF16x3 };
+// kBF16x3: BF16x3 products that split FP32/FP64 operands as they load them
+// (batch executor); kBF16P: BF16x3 products on operands pre-split into bf16
+// planes (a context's own products in the BF16x3 mode).
+enum class Prec { kF64, kF32, kBF16x3, kBF16P };
 
 // Launchers (return hipError_t of the launch).
+// out_is_f32: 0 FP64, 1 FP32, 2 split bf16 planes (hi, lo; see AoOut::plane).
 hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                          int fp32_compute, hipStream_t s);
 // Values only, one plane: element (k, p) at out.out[k*out.sK + p*out.sP].
@@ -269,6 +277,18 @@ hipError_t launch_gather_rows(const void* src, const int32_t* perm, int64_t rows
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s);
+// BF16x3 kernel on pre-split bf16 planes (gemm_bf16p.hip): g.A / g.A2 and
+// g.B / g.B2 are the hi / lo planes; reached through launch_gemm_typed with
+// Prec::kBF16P.
+int gemm_bf16p_num_tiles();
+TileCfg gemm_bf16p_tile(int cfg);
+size_t gemm_bf16p_tile_lds_bytes(int cfg);
+hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s);
+int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg);
+// W[p][c][n] (P x 5 x N, FP64 or FP32) split into bf16 planes hi / lo laid
+// out [Pp][5][Nw] (Nw a multiple of 8), zero beyond P and N.
+hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw,
+                          void* hi, void* lo, hipStream_t s);
 // BF16x3 kernel (gemm_bf16.hip); reached through launch_gemm_typed.
 int gemm_bf16_num_tiles();
 TileCfg gemm_bf16_tile(int cfg);
