@@ -35,7 +35,7 @@ PEAKS = {  # MI355X published dense peaks
 }
 MODE_DTYPE = {"fp64": "f64", "mixed_f32": "f32", "mixed_bf16x3": "bf16x3"}
 # precision modes whose contraction has a screened (block-sparse) form
-SCREENED_MODES = {"fp64": True, "mixed_f32": True, "mixed_bf16x3": False}
+SCREENED_MODES = {"fp64": True, "mixed_f32": True, "mixed_bf16x3": True}
 # useful-flop ceiling of each mode's contraction: the dense MFMA peak of its
 # datatype (BF16x3 issues three bf16 products per useful one)
 MODE_PEAK_TF = {"fp64": PEAKS["fp64_TFLOPs"], "mixed_f32": PEAKS["fp32_TFLOPs"],
@@ -66,7 +66,7 @@ def parse():
                     help="walkers in the oracle's timed sample")
     ap.add_argument("--cpu-points", type=int, default=1000000,
                     help="grid points in the oracle's timed sample (density workload)")
-    ap.add_argument("--cpu-walkers-1t", type=int, default=4,
+    ap.add_argument("--cpu-walkers-1t", type=int, default=8,
                     help="walkers in the oracle's one-thread timed sample")
     ap.add_argument("--quick", action="store_true",
                     help="default workload only: skip the batch and 7500-AO workloads of the default line")

@@ -385,7 +385,7 @@ qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
 qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s) {
   qmk_status st = ensure_tables(ctx);
   if (st != QMK_OK) return st;
-  const int f32 = ctx->f32_storage() ? 1 : 0;
+  const int f32 = ctx->ao_format();  // 0 FP64, 1 FP32, 2 bf16 hi and lo planes
   const int64_t P = ctx->P(), Pp = round_up(P, kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
   if (ctx->aos_date == ctx->date && ctx->aos_f32 == f32 && ctx->aos_Pp == Pp && ctx->aos_Kp == Kp)
     return QMK_OK;
@@ -425,6 +425,7 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s) {
   }
   pa.perm = ctx->d_perm.as<int32_t>();
   AoOut o{ctx->aos.p, 5 * Pp, Pp, 1, ctx->d_act.as<uint32_t>(), ctx->act_words};
+  o.plane = Kp * 5 * Pp;
   {
     LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
     QMK_HIP(ctx, launch_ao_vgl(ctx->tab, pa, o, f32, f32, s), "AO kernel (sorted points)");
@@ -747,9 +748,18 @@ qmk_status get_mo_vgl_screened(qmk_ctx ctx, void* out, int32_t dtype, hipStream_
   ga.sAi = 1;
   ga.sAl = 5 * Pp;
   ga.oAc = Pp;
-  ga.B = ctx->d_Ct.p;
-  ga.sBl = ctx->Np;
-  ga.sBj = 1;
+  const bool planes = ctx->mode == QMK_MIXED_BF16X3;
+  if (planes) {  // sorted AO array as bf16 hi / lo planes, C [n][k] split
+    ga.A2 = static_cast<const uint16_t*>(ctx->aos.p) + ctx->aos_Kp * 5 * Pp;
+    ga.B = ctx->d_Cb_hi.p;
+    ga.B2 = ctx->d_Cb_lo.p;
+    ga.sBl = 1;
+    ga.sBj = ctx->Kp;
+  } else {
+    ga.B = ctx->d_Ct.p;
+    ga.sBl = ctx->Np;
+    ga.sBj = 1;
+  }
   ga.D = out;
   ga.sDi = 5 * N;
   ga.sDj = 1;
@@ -767,11 +777,12 @@ qmk_status get_mo_vgl_screened(qmk_ctx ctx, void* out, int32_t dtype, hipStream_
   GemmProblem pb{GemmKind::kForward, prec, 0, o32, P, N, K};
   pb.sparse = 1;
   int cfg = 0;
-  if ((st = pick_tile(ctx, pb, s, [&](int c) { return launch_gemm_sparse(prec, c, ga, o32, s); }, &cfg)) !=
-      QMK_OK)
-    return st;
+  auto launch = [&](int c) {
+    return planes ? launch_gemm_bf16p(GemmKind::kForward, c, ga, o32, 1, s) : launch_gemm_sparse(prec, c, ga, o32, s);
+  };
+  if ((st = pick_tile(ctx, pb, s, launch, &cfg)) != QMK_OK) return st;
   LaunchTimer lt(ctx, QMK_KERNEL_MO, s);
-  QMK_HIP(ctx, launch_gemm_sparse(prec, cfg, ga, o32, s), "screened MO contraction");
+  QMK_HIP(ctx, launch(cfg), "screened MO contraction");
   return QMK_OK;
 }
 
@@ -1321,7 +1332,7 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   DeviceGuard g(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
-  if (ctx->sparse && ctx->mode != QMK_MIXED_BF16X3) {
+  if (ctx->sparse) {
     if ((st = get_mo_vgl_screened(ctx, out, dtype, s)) != QMK_OK) return st;
     return apply_cusp(ctx, out, dtype == QMK_F32, s);
   }
@@ -1548,7 +1559,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
   // screened adjoint: every product in sorted point order (Section 3.2)
-  const bool scr = ctx->sparse && ctx->mode != QMK_MIXED_BF16X3;
+  const bool scr = ctx->sparse;
   if ((st = scr ? provide_ao_sorted(ctx, s) : provide_ao(ctx, s)) != QMK_OK) return st;
   const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
   const int64_t Pp = scr ? ctx->aos_Pp : ctx->ao_Pp, Kp = ctx->Kp, Np = ctx->Np;
@@ -1581,10 +1592,12 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     w_hi = ctx->w_split.as<uint16_t>();
     w_lo = w_hi + plane;
     LaunchTimer lt(ctx, QMK_KERNEL_CONVERT, s);
-    QMK_HIP(ctx, launch_split_w(w, w32, P, N, Pp, Nw, const_cast<uint16_t*>(w_hi), const_cast<uint16_t*>(w_lo), s),
+    // screened: the planes hold W in the sorted point order
+    QMK_HIP(ctx, launch_split_w(w, w32, P, N, Pp, Nw, scr ? ctx->d_perm.as<int32_t>() : nullptr,
+                                const_cast<uint16_t*>(w_hi), const_cast<uint16_t*>(w_lo), s),
             "split W");
   }
-  if (scr) {
+  if (scr && !planes) {
     // W in the sorted point order, once, so that both products read it with
     // their ordinary loaders
     const int64_t row_bytes = 5 * N * (w32 ? 4 : 8);
@@ -1615,6 +1628,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
     GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
     pb.sparse = scr ? 1 : 0;
     auto launch = [&](int c) {
+      if (planes) return launch_gemm_bf16p(GemmKind::kGbar, c, ga, f32, scr ? 1 : 0, s);
       return scr ? launch_gemm_screened_adj(GemmKind::kGbar, prec, c, ga, w32, s)
                  : launch_gemm_typed(GemmKind::kGbar, prec, c, ga, w32, f32, s);
     };
@@ -1673,6 +1687,11 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       int64_t ns = std::max<int64_t>(1, 4 * resident / (tiles * 5));
       ns = std::min<int64_t>(ns, std::max<int64_t>(1, (P + 255) / 256));
       int64_t chunk = round_up((P + ns - 1) / ns, 32);
+      if (planes && scr) {
+        // screened BF16x3: whole 64-point blocks per split, at most
+        // kSparseMaxStages K steps of 32 points each
+        chunk = std::min<int64_t>(round_up(chunk, 64), static_cast<int64_t>(kSparseMaxStages) * 32);
+      }
       *chunk_out = chunk;
       return (P + chunk - 1) / chunk;
     };
@@ -1702,7 +1721,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
         ga.sAl = 5 * Nw;
         ga.oAc = Nw;
         ga.oAs = chunk * 5 * Nw;
-        ga.B2 = static_cast<const uint16_t*>(ao_arr) + ctx->ao_Kp * 5 * Pp;
+        ga.B2 = static_cast<const uint16_t*>(ao_arr) + Kp * 5 * Pp;
       }
       ga.D = ctx->ws_dc.p;
       ga.sDi = Kp;
@@ -1720,7 +1739,8 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       hipError_t e;
       {
         LaunchTimer lt(ctx, QMK_KERNEL_DCOEF, s);
-        e = scr ? launch_gemm_screened_adj(GemmKind::kDcoef, prec, cfg, ga, w32, s)
+        e = planes ? launch_gemm_bf16p(GemmKind::kDcoef, cfg, ga, 0, scr ? 1 : 0, s)
+            : scr  ? launch_gemm_screened_adj(GemmKind::kDcoef, prec, cfg, ga, w32, s)
                 : launch_gemm_typed(GemmKind::kDcoef, prec, cfg, ga, w32, 0, s);
       }
       if (e != hipSuccess) return e;

@@ -27,16 +27,19 @@ __global__ __launch_bounds__(256) void f64_to_f32_kernel(const double* __restric
 // One thread per eight consecutive n of one (p, c) row.
 template <typename T>
 __global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, int64_t P, int64_t N, int64_t Pp,
-                                                      int64_t Nw, int vec, __bf16* __restrict__ hi,
-                                                      __bf16* __restrict__ lo) {
+                                                      int64_t Nw, int vec, const int32_t* __restrict__ perm,
+                                                      __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
   typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
   const int64_t cpr = Nw / 8;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= Pp * 5 * cpr) return;
   const int64_t row = idx / cpr, n0 = (idx - row * cpr) * 8;
+  // source row: point perm[p] (or p), same component
+  const int64_t p = row / 5;
+  const int64_t srow = (perm && p < P) ? static_cast<int64_t>(perm[p]) * 5 + (row - p * 5) : row;
   float x[8];
   if (row < P * 5 && vec && n0 + 8 <= N) {
-    const T* src = w + row * N + n0;
+    const T* src = w + srow * N + n0;
     if constexpr (sizeof(T) == 8) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, i
   } else {
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      x[e] = (row < P * 5 && n0 + e < N) ? static_cast<float>(w[row * N + n0 + e]) : 0.0f;
+      x[e] = (row < P * 5 && n0 + e < N) ? static_cast<float>(w[srow * N + n0 + e]) : 0.0f;
   }
   bf16x8 h, l;
 #pragma unroll
@@ -68,8 +71,8 @@ __global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, i
 
 }  // namespace
 
-hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw, void* hi,
-                          void* lo, hipStream_t s) {
+hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw,
+                          const int32_t* perm, void* hi, void* lo, hipStream_t s) {
   if (Pp <= 0 || Nw <= 0) return hipSuccess;
   if (Nw % 8 != 0 || Pp < P || Nw < N) return hipErrorInvalidValue;
   const int64_t n = Pp * 5 * (Nw / 8);
@@ -80,11 +83,11 @@ hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int
   const int vec = reinterpret_cast<uintptr_t>(w) % 16 == 0 && (N * esz) % 16 == 0;
   if (w_is_f32)
     hipLaunchKernelGGL(split_w_kernel<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<const float*>(w), P, N, Pp, Nw, vec, static_cast<__bf16*>(hi),
+                       static_cast<const float*>(w), P, N, Pp, Nw, vec, perm, static_cast<__bf16*>(hi),
                        static_cast<__bf16*>(lo));
   else
     hipLaunchKernelGGL(split_w_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<const double*>(w), P, N, Pp, Nw, vec, static_cast<__bf16*>(hi),
+                       static_cast<const double*>(w), P, N, Pp, Nw, vec, perm, static_cast<__bf16*>(hi),
                        static_cast<__bf16*>(lo));
   return hipGetLastError();
 }

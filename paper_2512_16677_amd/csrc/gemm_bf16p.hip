@@ -149,20 +149,23 @@ __device__ __forceinline__ bf16x8 frag_k(const __bf16* t, int r0, int lane) {
 // The K loop of one tile.  FULL: every row of both operand tiles is in
 // range (no zero fill).  The loop is unrolled by two so that both staging
 // buffers are compile-time constants.
-template <bool A_MN, bool FULL, int WGM, int WGN, int TM, int TN, int DEPTH>
+// list (screened products): the K steps to visit, nk of them; otherwise
+// steps 0 .. nk-1.
+template <bool A_MN, bool FULL, int WGM, int WGN, int TM, int TN, int DEPTH, bool LIST>
 __device__ __forceinline__ void bf16p_loop(PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>& sm,
                                            PTile<16 * WGM * TM, 64 * WGM * WGN, A_MN> (&la)[DEPTH],
                                            PTile<16 * WGN * TN, 64 * WGM * WGN, false> (&lb)[DEPTH],
                                            const __bf16* Ah, const __bf16* Al, const __bf16* Bh,
                                            const __bf16* Bl, int64_t stepA, int64_t stepB, int64_t nk,
-                                           f32x4 (&acc)[TM][TN]) {
+                                           const int16_t* list, f32x4 (&acc)[TM][TN]) {
   constexpr int BM = 16 * WGM * TM;
   constexpr int AP = mn_pitch(BM);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WGN, wn = w % WGN;
   auto load = [&](int r, int64_t kt) {
-    la[r].load(Ah + kt * stepA, Al + kt * stepA);
-    lb[r].load(Bh + kt * stepB, Bl + kt * stepB);
+    const int64_t t = LIST ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[kt])) : kt;
+    la[r].load(Ah + t * stepA, Al + t * stepA);
+    lb[r].load(Bh + t * stepB, Bl + t * stepB);
   };
   auto stash = [&](int r, int buf) {
     la[r].template stash<FULL>(sm.A[buf][0], sm.A[buf][1]);
@@ -234,9 +237,22 @@ __device__ __forceinline__ void bf16p_loop(PSmem<16 * WGM * TM, 16 * WGN * TN, A
   }
 }
 
-template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+// SCR: 0 dense; the screened products on points sorted by nearest nucleus
+// (g.act: bit c of word (block * act_words + c / 32) set if the 64-point
+// block has a non-zero AO in 16-AO chunk c):
+//   2 forward: the K steps (32 AOs) with an active chunk in some 64-point
+//     block of the tile's rows are listed and visited; row i of D is stored
+//     at row perm[i];
+//   3 W C product (rows AOs, columns sorted points): a tile with no active
+//     (block, chunk) pair is not computed (its zeros are stored);
+//   4 W^T ao product (K over the sorted points of split s): the K steps whose
+//     64-point block has an active chunk among the tile's AO columns.
+// Skipped steps and tiles hold exact zeros of the AO operand, so every
+// output is a sum of the same non-zero terms as in the dense product.
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR>
 __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, int z,
-                                           PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>& sm) {
+                                           PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>& sm,
+                                           int16_t* s_list, int* s_n) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   const int c = z / g.nsplit, s = z - c * g.nsplit;
@@ -267,12 +283,66 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int64_t nk = (Ls + BK - 1) / BK;
+  int64_t nk = (Ls + BK - 1) / BK;
+  if constexpr (SCR == 2 || SCR == 4) {
+    // wave 0 lists the active K steps (at most kSparseMaxStages; the host
+    // sizes the reduction ranges accordingly)
+    if (tid < 64) {
+      int count = 0;
+      int64_t cb0 = 0, cb1 = 0, w0 = 0, w1 = 0;
+      uint32_t m0 = 0, m1 = 0;
+      if constexpr (SCR == 2) {
+        cb0 = i0 >> 6;
+        cb1 = (min(i0 + BM, g.M) - 1) >> 6;
+      } else {
+        const int64_t c0 = j0 / kSparseChunk, c1 = (min(j0 + BN, g.N) - 1) / kSparseChunk;
+        w0 = c0 >> 5;
+        w1 = c1 >> 5;
+        m0 = (~0u << (c0 & 31)) & (w1 == w0 ? (~0u >> (31 - (c1 & 31))) : ~0u);
+        m1 = w1 == w0 ? 0u : (~0u >> (31 - (c1 & 31)));
+      }
+      const int64_t nchunk = (g.L + kSparseChunk - 1) / kSparseChunk;
+      const int64_t p0 = static_cast<int64_t>(s) * g.Lchunk;
+      for (int64_t base = 0; base < nk; base += 64) {
+        const int64_t t = base + tid;
+        bool on = false;
+        if (t < nk) {
+          if constexpr (SCR == 2) {
+            const int64_t c1 = min((t + 1) * BK / kSparseChunk, nchunk);
+            for (int64_t c = t * BK / kSparseChunk; c < c1 && !on; ++c)
+              for (int64_t b = cb0; b <= cb1 && !on; ++b)
+                on = (g.act[b * g.act_words + (c >> 5)] >> (c & 31)) & 1u;
+          } else {
+            const uint32_t* wd = g.act + ((p0 + t * BK) >> 6) * g.act_words;
+            on = ((wd[w0] & m0) | (w1 != w0 ? (wd[w1] & m1) : 0u)) != 0u;
+          }
+        }
+        const uint64_t mask = __ballot(on);
+        if (on) s_list[count + __popcll(mask & ((1ull << tid) - 1))] = static_cast<int16_t>(t);
+        count += __popcll(mask);
+      }
+      if (tid == 0) *s_n = count;
+    }
+    __syncthreads();
+    nk = *s_n;
+  }
+  if constexpr (SCR == 3) {
+    // output tile (AO rows [i0, i0 + BM), sorted points [j0, j0 + BN))
+    const int64_t c0 = i0 / kSparseChunk, c1 = (min(i0 + BM, g.M) - 1) / kSparseChunk;
+    const int64_t b0 = j0 >> 6, b1 = (min(j0 + BN, g.N) - 1) >> 6;
+    bool on = false;
+    for (int64_t b = b0; b <= b1 && !on; ++b)
+      for (int64_t c = c0; c <= c1 && !on; ++c) on = (g.act[b * g.act_words + (c >> 5)] >> (c & 31)) & 1u;
+    if (!on) nk = 0;
+  }
+  constexpr bool LIST = SCR == 2 || SCR == 4;
   const int64_t stepA = BK * g.sAl, stepB = BK * g.sBl;
   if (rows_a >= BM && rows_b >= BN)
-    bf16p_loop<A_MN, true, WGM, WGN, TM, TN, DEPTH>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, acc);
+    bf16p_loop<A_MN, true, WGM, WGN, TM, TN, DEPTH, LIST>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, s_list,
+                                                          acc);
   else
-    bf16p_loop<A_MN, false, WGM, WGN, TM, TN, DEPTH>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, acc);
+    bf16p_loop<A_MN, false, WGM, WGN, TM, TN, DEPTH, LIST>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, s_list,
+                                                           acc);
 
   // accumulator element r of lane l: row 4 (l / 16) + r, column l % 16
   const int lane = tid & 63, w = tid >> 6;
@@ -285,16 +355,21 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + (wm * TM + a) * 16 + 4 * (lane >> 4) + r;
         const int64_t gj = j0 + (wn * TN + b) * 16 + (lane & 15);
-        if (gi < g.M && gj < g.N) Dp[gi * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+        if (gi < g.M && gj < g.N) {
+          const int64_t row = SCR == 2 ? static_cast<int64_t>(g.perm[gi]) : gi;
+          Dp[row * g.sDi + gj * g.sDj] = static_cast<TD>(acc[a][b][r]);
+        }
       }
 }
 
-template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(GemmArgs g, int nM, int nN) {
   __shared__ __align__(16) PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN> sm;
+  __shared__ int16_t s_list[(SCR == 2 || SCR == 4) ? kSparseMaxStages : 1];
+  __shared__ int s_n;
   int mt, nt, z;
   if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
-  bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH>(g, mt, nt, z, sm);
+  bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR>(g, mt, nt, z, sm, s_list, &s_n);
 }
 
 // {WGM, WGN, TM, TN, DEPTH}; the reduction step is always 32.
@@ -322,30 +397,31 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(GemmArgs g, 
 #undef QMK_BFP_ENTRY
 };
 
-template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+template <bool A_MN, typename TD, int SCR, int WGM, int WGN, int TM, int TN, int DEPTH>
 hipError_t run_bfp_tile(const GemmArgs& g, hipStream_t s) {
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   const int nM = static_cast<int>((g.M + BM - 1) / BM), nN = static_cast<int>((g.N + BN - 1) / BN);
   if (nM <= 0 || nN <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH>), grid_of(g, nM, nN), dim3(64 * WGM * WGN),
+  hipLaunchKernelGGL((gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR>), grid_of(g, nM, nN),
+                     dim3(64 * WGM * WGN),
                      0, s, g, nM, nN);
   return hipGetLastError();
 }
 
-template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+template <bool A_MN, typename TD, int SCR, int WGM, int WGN, int TM, int TN, int DEPTH>
 int bfp_occupancy() {
   int n = 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &n, gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH>, 64 * WGM * WGN, 0);
+      &n, gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR>, 64 * WGM * WGN, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-template <bool A_MN, typename TD>
+template <bool A_MN, typename TD, int SCR>
 int occupancy_of(int cfg) {
   switch (cfg) {
 #define QMK_BFP_OCC(id, wgm, wgn, tm, tn, depth) \
   case id:                                       \
-    return bfp_occupancy<A_MN, TD, wgm, wgn, tm, tn, depth>();
+    return bfp_occupancy<A_MN, TD, SCR, wgm, wgn, tm, tn, depth>();
     QMK_BF16P_TILE_LIST(QMK_BFP_OCC)
 #undef QMK_BFP_OCC
     default:
@@ -353,12 +429,12 @@ int occupancy_of(int cfg) {
   }
 }
 
-template <bool A_MN, typename TD>
+template <bool A_MN, typename TD, int SCR>
 hipError_t run_bfp(int cfg, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
 #define QMK_BFP_CASE(id, wgm, wgn, tm, tn, depth) \
   case id:                                        \
-    return run_bfp_tile<A_MN, TD, wgm, wgn, tm, tn, depth>(g, s);
+    return run_bfp_tile<A_MN, TD, SCR, wgm, wgn, tm, tn, depth>(g, s);
     QMK_BF16P_TILE_LIST(QMK_BFP_CASE)
 #undef QMK_BFP_CASE
     default:
@@ -370,24 +446,29 @@ hipError_t run_bfp(int cfg, const GemmArgs& g, hipStream_t s) {
 
 #ifdef QMK_GEMM_UNIT
 #if QMK_GEMM_UNIT == 1
-hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, hipStream_t s) {
-  return o32 ? run_bfp<true, float>(cfg, g, s) : run_bfp<true, double>(cfg, g, s);
+hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, int scr, hipStream_t s) {
+  if (scr) return o32 ? run_bfp<true, float, 2>(cfg, g, s) : run_bfp<true, double, 2>(cfg, g, s);
+  return o32 ? run_bfp<true, float, 0>(cfg, g, s) : run_bfp<true, double, 0>(cfg, g, s);
 }
 #endif
 #if QMK_GEMM_UNIT == 2
-hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, hipStream_t s) { return run_bfp<false, float>(cfg, g, s); }
+hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, int scr, hipStream_t s) {
+  return scr ? run_bfp<false, float, 3>(cfg, g, s) : run_bfp<false, float, 0>(cfg, g, s);
+}
 #endif
 #if QMK_GEMM_UNIT == 3
-hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, hipStream_t s) { return run_bfp<true, double>(cfg, g, s); }
-int bf16p_unit_dc_occupancy(int cfg) { return occupancy_of<true, double>(cfg); }
+hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, int scr, hipStream_t s) {
+  return scr ? run_bfp<true, double, 4>(cfg, g, s) : run_bfp<true, double, 0>(cfg, g, s);
+}
+int bf16p_unit_dc_occupancy(int cfg) { return occupancy_of<true, double, 0>(cfg); }
 #endif
 #else
 // The three products are instantiated in their own translation units (this
 // file compiled with QMK_GEMM_UNIT = 1..3); the unit without it holds the
 // tile table and the dispatch.
-hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, hipStream_t s);
-hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, hipStream_t s);
-hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, hipStream_t s);
+hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, int scr, hipStream_t s);
+hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, int scr, hipStream_t s);
+hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, int scr, hipStream_t s);
 int bf16p_unit_dc_occupancy(int cfg);
 
 int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg) {
@@ -409,7 +490,8 @@ size_t gemm_bf16p_tile_lds_bytes(int cfg) {
 // forward: A = AO planes (MN-major), B = C planes [n][k]
 // Gbar:    A = C^T planes [k][n] (K-major), B = W planes [p][c][n]
 // dC:      A = W planes (MN-major over n), B = AO planes (K-major over p)
-hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s) {
+hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, int screened,
+                             hipStream_t s) {
   if (cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return hipErrorInvalidValue;
   // the loaders address a tile's chunks by 32-bit byte offsets from the
   // tile's base: (rows - 1) * row stride + (BK - 1) * reduction stride + 8
@@ -418,9 +500,13 @@ hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_
   const int64_t eb = (16 * t.wgn * t.tn - 1) * g.sBj + (BK - 1) * g.sBl + 8;
   if (ea < 0 || eb < 0 || 2 * ea > 0x7fffffffLL || 2 * eb > 0x7fffffffLL) return hipErrorInvalidValue;
   switch (kind) {
-    case GemmKind::kForward: return bf16p_unit_fwd(cfg, g, out_is_f32, s);
-    case GemmKind::kGbar: return bf16p_unit_gbar(cfg, g, s);
-    case GemmKind::kDcoef: return bf16p_unit_dc(cfg, g, s);
+    case GemmKind::kForward: return bf16p_unit_fwd(cfg, g, out_is_f32, screened, s);
+    case GemmKind::kGbar: return bf16p_unit_gbar(cfg, g, screened, s);
+    case GemmKind::kDcoef:
+      // the screened step list holds at most kSparseMaxStages steps of BK points
+      if (screened && (g.Lchunk > static_cast<int64_t>(kSparseMaxStages) * BK || g.Lchunk % 64 != 0))
+        return hipErrorInvalidValue;
+      return bf16p_unit_dc(cfg, g, screened, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -201,7 +201,7 @@ hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_
 
 hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s) {
-  if (prec == Prec::kBF16P) return launch_gemm_bf16p(kind, cfg, g, out_is_f32, s);
+  if (prec == Prec::kBF16P) return launch_gemm_bf16p(kind, cfg, g, out_is_f32, 0, s);
   if (prec == Prec::kBF16x3) return launch_gemm_bf16x3(kind, cfg, g, w_is_f32, out_is_f32, s);
   if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   return unit_dispatch(kind, prec, cfg, &g, nullptr, w_is_f32, out_is_f32, s);

@@ -283,12 +283,18 @@ hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& 
 int gemm_bf16p_num_tiles();
 TileCfg gemm_bf16p_tile(int cfg);
 size_t gemm_bf16p_tile_lds_bytes(int cfg);
-hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s);
+// screened = 1: the products of the screened contraction (points sorted by
+// nearest nucleus, g.act / g.perm / g.act_words set as for the FP64 and FP32
+// screened products; the W^T ao product needs Lchunk a multiple of 64 and at
+// most kSparseMaxStages * 32).
+hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, int screened,
+                             hipStream_t s);
 int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg);
 // W[p][c][n] (P x 5 x N, FP64 or FP32) split into bf16 planes hi / lo laid
-// out [Pp][5][Nw] (Nw a multiple of 8), zero beyond P and N.
+// out [Pp][5][Nw] (Nw a multiple of 8), zero beyond P and N.  perm != NULL:
+// plane row p holds W row perm[p] (the screened products' point order).
 hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw,
-                          void* hi, void* lo, hipStream_t s);
+                          const int32_t* perm, void* hi, void* lo, hipStream_t s);
 // BF16x3 kernel (gemm_bf16.hip); reached through launch_gemm_typed.
 int gemm_bf16_num_tiles();
 TileCfg gemm_bf16_tile(int cfg);

@@ -173,3 +173,80 @@ def test_screened_adjoint_every_tile_shape():
         for k in ("d_coef", "d_nucl"):
             assert (g[k] - dense[k]).abs().max().item() <= 1e-12 * dense[k].abs().max().item(), (t, k)
     ctx.close()
+
+
+@pytest.mark.parametrize("mode,screened", [("fp64", False), ("fp64", True), ("mixed_bf16x3", False)])
+def test_mo_subset_matches_oracle(mode, screened):
+    """A subset of the MOs (Section 3.2: unoccupied MOs are left out of the
+    product) is computed by setting only those rows of C: mo_vgl and the
+    gradients equal the oracle's with the same rows, for a subset that is not
+    a multiple of any tile width (37 of 400 MOs, every other one among the
+    first 74)."""
+    q = qmk()
+    s = synth.medium(walkers=1)
+    rows = np.arange(0, 74, 2)
+    C_sub = np.ascontiguousarray(s.mo_coef[rows])
+    bits = 53 if mode == "fp64" else 24
+    ctx = q.Context.from_system(s, bits=bits, mode=mode)
+    ctx.set_mo_coef(C_sub)
+    if screened:
+        ctx.set_screening(True)
+    assert ctx.dims()["mo_num"] == len(rows)
+    mo = ctx.get_mo_vgl().cpu().numpy().reshape(-1, 5, len(rows))
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal((s.walk_num, s.elec_num, 5, len(rows)))
+    g = {k: v.cpu().numpy() for k, v in ctx.adjoint(torch.from_numpy(w).cuda()).items()}
+    ctx.close()
+    ref = oracle.mo_vgl(s, coef=C_sub, B=bits)
+    r = oracle.adjoint(s, w, coef=C_sub, B=bits)
+    tol = 1e-12 if mode == "fp64" else 1e-4
+    gtol = 1e-11 if mode == "fp64" else 1e-3
+    for k, v in component_errors(mo, ref).items():
+        assert v <= tol, (k, v)
+    for k in ("d_coef", "d_elec", "d_nucl"):
+        assert grad_err(g[k].reshape(r[k].shape), r[k], r[k + "_abs"]) <= gtol, k
+
+
+@pytest.mark.parametrize("system", ["medium", "large"])
+def test_screened_bf16x3_equals_dense_and_oracle(system):
+    """The BF16x3 screened products: forward rows and electron gradients
+    equal the dense BF16x3 ones bit for bit (the same non-zero terms in the
+    same order), dL/dC and the nuclear gradients agree to FP32 rounding, and
+    both match the oracle at the BF16x3 tolerance."""
+    s = synth.medium(walkers=2) if system == "medium" else synth.large(walkers=1)
+    dense, scr, frac = dense_and_screened(s, bits=24, mode="mixed_bf16x3", dtype=torch.float32)
+    print(json.dumps({"system": system, "bf16x3_screening_density": frac}))
+    assert bool((dense == scr).all())
+    w, gd, gs, gs2 = adjoint_pair(s, mode="mixed_bf16x3", bits=24)
+    assert bool((gs["d_elec"] == gd["d_elec"]).all())
+    for k in ("d_coef", "d_nucl"):
+        num = (gs[k] - gd[k]).abs().max().item()
+        assert num <= 1e-6 * gd[k].abs().max().item(), (k, num)
+    for k in gs:
+        assert torch.equal(gs[k], gs2[k]), k
+    ref_mo = oracle.mo_vgl(s, B=24) if system == "medium" else None
+    if ref_mo is not None:
+        for k, v in component_errors(scr.double().cpu().numpy().reshape(-1, 5, s.mo_num), ref_mo).items():
+            assert v <= 1e-4, (k, v)
+    r = oracle.adjoint_products(s, w.cpu().numpy(), B=24)
+    for k in ("d_coef", "d_elec", "d_nucl"):
+        assert grad_err(gs[k].cpu().numpy().reshape(r[k].shape), r[k], r[k + "_abs"]) <= 1e-3, k
+
+
+def test_screened_bf16x3_every_tile_shape():
+    s = synth.medium(walkers=1)
+    q = qmk()
+    w = torch.from_numpy(synth.adjoint_weights(s, seed=6)).cuda()
+    ctx = q.Context.from_system(s, bits=24, mode="mixed_bf16x3")
+    dense = ctx.get_mo_vgl(dtype=torch.float32).clone()
+    gdense = {k: v.clone() for k, v in ctx.adjoint(w).items()}
+    ctx.set_screening(True)
+    for t in range(ctx.tile_count()):
+        for k in ("mo", "gbar", "dcoef"):
+            ctx.set_tile(k, t)
+        assert bool((ctx.get_mo_vgl(dtype=torch.float32) == dense).all()), t
+        g = ctx.adjoint(w)
+        assert bool((g["d_elec"] == gdense["d_elec"]).all()), t
+        for k in ("d_coef", "d_nucl"):
+            assert (g[k] - gdense[k]).abs().max().item() <= 1e-6 * gdense[k].abs().max().item(), (t, k)
+    ctx.close()
