@@ -234,16 +234,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0];
 }
 
-// Largest j with prefix[j] <= e (prefix[0] = 0, increasing).
-__device__ __forceinline__ int find_job(const int64_t* prefix, int n_jobs, int64_t e) {
-  int lo = 0, hi = n_jobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= e) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __global__ __launch_bounds__(256) void reduce_nuc_batch_kernel(const NucRedJob* __restrict__ jobs,
                                                                const int64_t* __restrict__ prefix,
                                                                int n_jobs) {

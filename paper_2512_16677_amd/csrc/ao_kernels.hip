@@ -235,7 +235,9 @@ __global__ __launch_bounds__(256) void ao_vgl_persist(const AoJob* __restrict__ 
 hipError_t launch_ao_vgl_persist(const AoJob* jobs, const WorkItem* items, int n_items, int grid,
                                  size_t smem, int out_is_f32, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (out_is_f32)
+  if (out_is_f32 == 2)
+    hipLaunchKernelGGL(ao_vgl_persist<Bf16Pair>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
+  else if (out_is_f32)
     hipLaunchKernelGGL(ao_vgl_persist<float>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
   else
     hipLaunchKernelGGL(ao_vgl_persist<double>, dim3(grid), dim3(256), smem, s, jobs, items, n_items);
@@ -244,8 +246,9 @@ hipError_t launch_ao_vgl_persist(const AoJob* jobs, const WorkItem* items, int n
 
 int ao_persist_blocks_per_cu(int f32, size_t smem) {
   int n = 0;
-  hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<float>, 256, smem)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<double>, 256, smem);
+  hipError_t e = f32 == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<Bf16Pair>, 256, smem)
+                 : f32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<float>, 256, smem)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ao_vgl_persist<double>, 256, smem);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

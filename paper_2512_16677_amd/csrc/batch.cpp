@@ -11,7 +11,10 @@
 //     a single hipGraphLaunch per run;
 //   * the MFMA tile shape of each product is chosen for the batch as a whole
 //     by timing every tile shape on the first run (cached like the
-//     per-context choices).
+//     per-context choices);
+//   * in the BF16x3 mode the AO stage writes bf16 hi / lo planes and one
+//     element-wise launch splits every molecule's W into planes, so that
+//     the three products run the pre-split MFMA kernel, as per context.
 // Per-molecule arguments live in device job tables that are rewritten before
 // every launch, so new coordinates (set_point) or new output buffers need no
 // re-capture; a change of any dimension re-plans and re-captures.
@@ -34,10 +37,11 @@ constexpr uint32_t kBatchMagic = 0x514d4b42u;  // "QMKB"
 constexpr int64_t kDcoefChunk = 4096;          // points per split of the W^T ao product
 
 struct MolPlan {
-  int64_t P, K, N, Pp, Kp, Np, nucl_num;
+  int64_t P, K, N, Pp, Kp, Np, Nw, nucl_num;
   int32_t n_groups, nucl_dev;
   size_t ao_off, gbar_off;  // elements of the AO / Gbar arenas
   size_t dc_off;            // doubles of the dC partial arena
+  size_t w_off;             // bf16 elements of the split-W arena (hi plane, then lo)
   int64_t nsplit, chunk;
   size_t nuc_off;           // doubles of the nucleus partial arena
   int64_t n_waves;
@@ -61,12 +65,13 @@ struct qmk_batch_s {
   std::vector<qmk_ctx> ctxs;
   int mode = QMK_FP64;
   Prec prec = Prec::kF64;
-  int esz = 8;
+  int esz = 8;     // bytes per AO / Gbar element (bf16 planes: hi + lo)
+  int ao_fmt = 0;  // AO stage output: 0 FP64, 1 FP32, 2 bf16 hi / lo planes
 
   std::vector<int64_t> dims_key;
   std::vector<MolPlan> plan;
   bool planned = false;
-  DevBuf ao, gbar, ws_dc, ws_nuc, ws_elec, discard;
+  DevBuf ao, gbar, ws_dc, ws_nuc, ws_elec, discard, wsplit;
   size_t max_smem = 0;
   int n_cu = 0;
 
@@ -75,11 +80,12 @@ struct qmk_batch_s {
   int tile[3] = {-1, -1, -1};
   int tile_w32 = -1, tile_o32 = -1;
   std::vector<WorkItem> g_items[3];
+  std::vector<GemmArgs> g_jobs[3];  // host copies of the product job tables
   DevBuf d_ao_items, d_g_items[3];
   DevBuf d_ao_jobs, d_adj_jobs, d_g_jobs[3], d_red_jobs, d_red_prefix, d_nred_jobs,
-      d_nred_prefix;
-  int n_red = 0, n_nred = 0;
-  int64_t red_total = 0, nred_total = 0;
+      d_nred_prefix, d_split_jobs, d_split_prefix;
+  int n_red = 0, n_nred = 0, n_split = 0;
+  int64_t red_total = 0, nred_total = 0, split_total = 0;
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -155,7 +161,8 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
   drop_graph(b);
   b->plan.clear();
   b->tile[0] = b->tile[1] = b->tile[2] = -1;
-  size_t ao = 0, dc = 0, nuc = 0, elec = 0, dis = 0;
+  size_t ao = 0, dc = 0, nuc = 0, elec = 0, dis = 0, wsp = 0;
+  const bool planes = b->prec == Prec::kBF16P;
   b->max_smem = 0;
   std::vector<std::pair<int64_t, WorkItem>> ao_items;
   for (size_t m = 0; m < b->ctxs.size(); ++m) {
@@ -167,6 +174,7 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
     mp.Pp = round_up(mp.P, kPointPad);
     mp.Kp = c->Kp;
     mp.Np = c->Np;
+    mp.Nw = round_up(mp.N, 32);
     mp.nucl_num = c->nucl_num;
     mp.n_groups = c->n_groups;
     mp.nucl_dev = c->nucl_dev;
@@ -177,6 +185,8 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
     mp.nsplit = (mp.P + mp.chunk - 1) / mp.chunk;
     mp.dc_off = dc;
     dc += static_cast<size_t>(5 * mp.nsplit * mp.Np * mp.Kp);
+    mp.w_off = wsp;
+    if (planes) wsp += static_cast<size_t>(2 * mp.Pp * 5 * mp.Nw);
     mp.n_waves = (mp.P + 255) / 256 * 4;
     mp.nuc_off = nuc;
     nuc += static_cast<size_t>(mp.n_waves * mp.nucl_dev * 3);
@@ -209,6 +219,7 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
   QMK_BHIP(b, b->ws_nuc.ensure(std::max<size_t>(nuc, 1) * 8), "alloc batch nucleus partials");
   QMK_BHIP(b, b->ws_elec.ensure(std::max<size_t>(elec, 1) * 8), "alloc batch electron partials");
   QMK_BHIP(b, b->discard.ensure(std::max<size_t>(dis, 1) * 8), "alloc batch discard arena");
+  if (planes) QMK_BHIP(b, b->wsplit.ensure(std::max<size_t>(wsp, 1) * 2), "alloc batch split W");
   QMK_BHIP(b, upload(b->d_ao_items, b->ao_items, s), "upload AO work list");
   b->planned = true;
   return QMK_OK;
@@ -219,7 +230,13 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
   qmk_ctx c = b->ctxs[m];
   const MolPlan& mp = b->plan[m];
   const bool bf = b->prec == Prec::kBF16x3;
+  const bool planes = b->prec == Prec::kBF16P;
   const char* aop = static_cast<const char*>(b->ao.p) + mp.ao_off * b->esz;
+  // bf16 planes: the AO array's lo plane follows its hi plane; W's planes
+  // [Pp][5][Nw] sit in the split-W arena
+  const uint16_t* ao_lo = reinterpret_cast<const uint16_t*>(aop) + mp.Kp * 5 * mp.Pp;
+  const uint16_t* w_hi = b->wsplit.as<uint16_t>() + mp.w_off;
+  const uint16_t* w_lo = w_hi + mp.Pp * 5 * mp.Nw;
   char* gbp = static_cast<char*>(b->gbar.p) + mp.gbar_off * b->esz;
   GemmArgs g{};
   g.nsplit = 1;
@@ -229,7 +246,8 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.sAi = 1;
     g.sAl = 5 * mp.Pp;
     g.oAc = mp.Pp;
-    if (bf) {
+    if (planes) g.A2 = ao_lo;
+    if (bf || planes) {
       g.B = c->d_Cb_hi.p;
       g.B2 = c->d_Cb_lo.p;
       g.sBl = 1;
@@ -248,8 +266,13 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.N = mp.N;
     g.L = g.Lchunk = mp.K;
   } else if (kind == GemmKind::kGbar) {
-    g = gbar_args(b->prec, w, b->tile_w32, c->d_C.p, c->d_Ctb_hi.p, c->d_Ctb_lo.p, gbp, mp.P,
-                  mp.Pp, mp.K, mp.Kp, mp.N, mp.Np);
+    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, b->tile_w32, c->d_C.p, c->d_Ctb_hi.p,
+                  c->d_Ctb_lo.p, gbp, mp.P, mp.Pp, mp.K, mp.Kp, mp.N, mp.Np);
+    if (planes) {
+      g.B2 = w_lo;
+      g.sBj = 5 * mp.Nw;
+      g.oBc = mp.Nw;
+    }
   } else {
     g.A = w;
     g.sAi = 1;
@@ -271,6 +294,14 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.Lchunk = mp.chunk;
     g.nsplit = static_cast<int32_t>(mp.nsplit);
     if (bf) g.vec_ok = (w_vec_ok(w, mp.N, b->tile_w32) ? 1 : 0) | 2;
+    if (planes) {
+      g.A = w_hi;
+      g.A2 = w_lo;
+      g.sAl = 5 * mp.Nw;
+      g.oAc = mp.Nw;
+      g.oAs = mp.chunk * 5 * mp.Nw;
+      g.B2 = ao_lo;
+    }
   }
   return g;
 }
@@ -300,15 +331,24 @@ qmk_status choose_batch_tile(qmk_batch b, GemmKind kind, hipStream_t s) {
   const int k = static_cast<int>(kind);
   if (b->tile[k] >= 0) return QMK_OK;
   const std::string key = batch_key(b, kind);
+  // the pre-split kernel addresses its tiles by 32-bit offsets: every job's
+  // strides must fit the tile
+  auto usable = [&](int cfg) {
+    if (!tile_feasible(b->prec, cfg)) return false;
+    if (b->prec != Prec::kBF16P) return true;
+    for (const GemmArgs& g : b->g_jobs[k])
+      if (!gemm_bf16p_args_ok(cfg, g)) return false;
+    return true;
+  };
   int best = tune_cache_get(key);
-  if (best < 0 || best >= gemm_num_tiles(b->prec) || !tile_feasible(b->prec, best)) {
+  if (best < 0 || best >= gemm_num_tiles(b->prec) || !usable(best)) {
     best = -1;
     float best_ms = -1.0f;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     QMK_BHIP(b, hipEventCreate(&e0), "event");
     QMK_BHIP(b, hipEventCreate(&e1), "event");
     for (int cfg = 0; cfg < gemm_num_tiles(b->prec); ++cfg) {
-      if (!tile_feasible(b->prec, cfg)) continue;
+      if (!usable(cfg)) continue;
       if (best < 0) best = cfg;
       if (!tuning_on()) break;
       std::vector<WorkItem> items = gemm_items(b, kind, cfg);
@@ -334,7 +374,7 @@ qmk_status choose_batch_tile(qmk_batch b, GemmKind kind, hipStream_t s) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (best < 0) return bfail(b, QMK_UNSUPPORTED, "no tile fits in LDS");
+    if (best < 0) return bfail(b, QMK_UNSUPPORTED, "no tile fits in LDS and the operands' strides");
     tune_cache_put(key, best);
   }
   b->tile[k] = best;
@@ -345,10 +385,10 @@ qmk_status choose_batch_tile(qmk_batch b, GemmKind kind, hipStream_t s) {
 
 // Enqueues the whole batch (forward, and the adjoint when with_adj).
 qmk_status enqueue_all(qmk_batch b, bool with_adj, hipStream_t s) {
-  const int f32 = b->esz == 4;
-  const int ao_grid = persist_grid(b, ao_persist_blocks_per_cu(f32, b->max_smem), b->ao_items.size());
+  const int f32 = b->esz == 4;  // Gbar in FP32 (both mixed modes)
+  const int ao_grid = persist_grid(b, ao_persist_blocks_per_cu(b->ao_fmt, b->max_smem), b->ao_items.size());
   QMK_BHIP(b, launch_ao_vgl_persist(b->d_ao_jobs.as<AoJob>(), b->d_ao_items.as<WorkItem>(),
-                                    static_cast<int>(b->ao_items.size()), ao_grid, b->max_smem, f32, s),
+                                    static_cast<int>(b->ao_items.size()), ao_grid, b->max_smem, b->ao_fmt, s),
            "batch AO stage");
   auto gemm = [&](GemmKind kind) -> hipError_t {
     const int k = static_cast<int>(kind);
@@ -362,6 +402,10 @@ qmk_status enqueue_all(qmk_batch b, bool with_adj, hipStream_t s) {
   };
   QMK_BHIP(b, gemm(GemmKind::kForward), "batch contraction");
   if (!with_adj) return QMK_OK;
+  if (b->prec == Prec::kBF16P)
+    QMK_BHIP(b, launch_split_w_batch(b->d_split_jobs.as<SplitJob>(), b->d_split_prefix.as<int64_t>(), b->n_split,
+                                     b->split_total, b->tile_w32, s),
+             "batch W split");
   QMK_BHIP(b, gemm(GemmKind::kGbar), "batch W C product");
   const int adj_grid = persist_grid(b, adj_persist_blocks_per_cu(f32, b->max_smem), b->ao_items.size());
   QMK_BHIP(b, launch_ao_adjoint_persist(b->d_adj_jobs.as<AdjJob>(), b->d_ao_items.as<WorkItem>(),
@@ -459,8 +503,9 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
   key.push_back(mode);
   if (!b->planned || key != b->dims_key || b->mode != mode) {
     b->mode = mode;
-    b->prec = mode == QMK_FP64 ? Prec::kF64 : (mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16x3);
+    b->prec = mode == QMK_FP64 ? Prec::kF64 : (mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16P);
     b->esz = mode == QMK_FP64 ? 8 : 4;
+    b->ao_fmt = mode == QMK_FP64 ? 0 : (mode == QMK_MIXED_F32 ? 1 : 2);
     b->dims_key = key;
     int ncu = 0;
     QMK_BHIP(b, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device), "attr");
@@ -485,6 +530,8 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
   std::vector<int64_t> red_prefix{0};
   std::vector<NucRedJob> nred;
   std::vector<int64_t> nred_prefix{0};
+  std::vector<SplitJob> split;
+  std::vector<int64_t> split_prefix{0};
   for (size_t i = 0; i < n; ++i) {
     qmk_ctx c = b->ctxs[i];
     const MolPlan& mp = b->plan[i];
@@ -493,6 +540,7 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
     const PointArgs pa = point_args(c);
     char* aop = static_cast<char*>(b->ao.p) + mp.ao_off * b->esz;
     ao_jobs[i] = AoJob{t, pa, AoOut{aop, 5 * mp.Pp, mp.Pp, 1}};
+    ao_jobs[i].out.plane = mp.Kp * 5 * mp.Pp;  // bf16 planes: lo plane offset
     gj[0].push_back(gemm_job(b, i, GemmKind::kForward, outs[i], nullptr));
     if (with_adj) {
       double* de = (d_elecs && d_elecs[i]) ? d_elecs[i]
@@ -512,6 +560,14 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
       adj_jobs[i] = AdjJob{t, pa, static_cast<char*>(b->gbar.p) + mp.gbar_off * b->esz, 5 * mp.Pp,
                            mp.Pp, elec_out, gstride,
                            static_cast<double*>(b->ws_nuc.p) + mp.nuc_off};
+      if (b->prec == Prec::kBF16P) {
+        uint16_t* hi = b->wsplit.as<uint16_t>() + mp.w_off;
+        const size_t esz_w = w32 ? 4 : 8;
+        // vector loads need every group of eight weights to start 16-byte aligned
+        const int vec = reinterpret_cast<uintptr_t>(ws[i]) % 16 == 0 && (mp.N * esz_w) % 16 == 0;
+        split.push_back(SplitJob{ws[i], mp.P, mp.N, mp.Pp, mp.Nw, vec, hi, hi + mp.Pp * 5 * mp.Nw});
+        split_prefix.push_back(split_prefix.back() + mp.Pp * 5 * (mp.Nw / 8));
+      }
       gj[1].push_back(gemm_job(b, i, GemmKind::kGbar, nullptr, ws[i]));
       gj[2].push_back(gemm_job(b, i, GemmKind::kDcoef, nullptr, ws[i]));
       red.push_back(RedJob{static_cast<double*>(b->ws_dc.p) + mp.dc_off, 5 * mp.nsplit, mp.N, mp.K,
@@ -533,11 +589,17 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
     QMK_BHIP(b, upload(b->d_red_prefix, red_prefix, s), "upload jobs");
     QMK_BHIP(b, upload(b->d_nred_jobs, nred, s), "upload jobs");
     QMK_BHIP(b, upload(b->d_nred_prefix, nred_prefix, s), "upload jobs");
+    QMK_BHIP(b, upload(b->d_split_jobs, split, s), "upload jobs");
+    QMK_BHIP(b, upload(b->d_split_prefix, split_prefix, s), "upload jobs");
+    b->n_split = static_cast<int>(split.size());
+    b->split_total = split_prefix.back();
     b->n_red = static_cast<int>(red.size());
     b->red_total = red_prefix.back();
     b->n_nred = static_cast<int>(nred.size());
     b->nred_total = nred_prefix.back();
   }
+
+  for (int k = 0; k < 3; ++k) b->g_jobs[k] = gj[k];
 
   // tiles (timed once per batch shape), then one graph per (adjoint, dtype)
   qmk_status st;
@@ -550,6 +612,9 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
   std::vector<const void*> addrs = {b->d_ao_jobs.p, b->d_ao_items.p, b->d_adj_jobs.p,
                                     b->d_red_jobs.p, b->d_red_prefix.p, b->d_nred_jobs.p,
                                     b->d_nred_prefix.p, b->ao.p, b->gbar.p};
+  addrs.push_back(b->d_split_jobs.p);
+  addrs.push_back(b->d_split_prefix.p);
+  addrs.push_back(b->wsplit.p);
   for (int k = 0; k < 3; ++k) {
     addrs.push_back(b->d_g_jobs[k].p);
     addrs.push_back(b->d_g_items[k].p);

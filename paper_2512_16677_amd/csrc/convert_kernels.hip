@@ -24,15 +24,13 @@ __global__ __launch_bounds__(256) void f64_to_f32_kernel(const double* __restric
 
 // W[p][c][n] -> hi, lo planes [Pp][5][Nw]: hi = bf16(x), lo = bf16(x - hi) of
 // the FP32-rounded weight x (round to nearest even); zeros beyond P and N.
-// One thread per eight consecutive n of one (p, c) row.
+// One thread per eight consecutive n of one (p, c) row: idx < Pp * 5 * Nw / 8.
 template <typename T>
-__global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, int64_t P, int64_t N, int64_t Pp,
-                                                      int64_t Nw, int vec, const int32_t* __restrict__ perm,
-                                                      __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+__device__ __forceinline__ void split_w8(const T* __restrict__ w, int64_t P, int64_t N, int64_t Nw, int vec,
+                                         const int32_t* __restrict__ perm, __bf16* __restrict__ hi,
+                                         __bf16* __restrict__ lo, int64_t idx) {
   typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
   const int64_t cpr = Nw / 8;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= Pp * 5 * cpr) return;
   const int64_t row = idx / cpr, n0 = (idx - row * cpr) * 8;
   // source row: point perm[p] (or p), same component
   const int64_t p = row / 5;
@@ -69,6 +67,27 @@ __global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, i
   *reinterpret_cast<bf16x8*>(lo + row * Nw + n0) = l;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, int64_t P, int64_t N, int64_t Pp,
+                                                      int64_t Nw, int vec, const int32_t* __restrict__ perm,
+                                                      __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= Pp * 5 * (Nw / 8)) return;
+  split_w8(w, P, N, Nw, vec, perm, hi, lo, idx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void split_w_batch_kernel(const SplitJob* __restrict__ jobs,
+                                                            const int64_t* __restrict__ prefix, int n_jobs,
+                                                            int64_t total) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int jb = find_job(prefix, n_jobs, e);
+  const SplitJob& j = jobs[jb];
+  split_w8(static_cast<const T*>(j.w), j.P, j.N, j.Nw, j.vec, static_cast<const int32_t*>(nullptr),
+           static_cast<__bf16*>(j.hi), static_cast<__bf16*>(j.lo), e - prefix[jb]);
+}
+
 }  // namespace
 
 hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw,
@@ -89,6 +108,20 @@ hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int
     hipLaunchKernelGGL(split_w_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                        static_cast<const double*>(w), P, N, Pp, Nw, vec, perm, static_cast<__bf16*>(hi),
                        static_cast<__bf16*>(lo));
+  return hipGetLastError();
+}
+
+hipError_t launch_split_w_batch(const SplitJob* jobs, const int64_t* prefix, int n_jobs, int64_t total,
+                                int w_is_f32, hipStream_t s) {
+  if (total <= 0 || n_jobs <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (w_is_f32)
+    hipLaunchKernelGGL(split_w_batch_kernel<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, jobs,
+                       prefix, n_jobs, total);
+  else
+    hipLaunchKernelGGL(split_w_batch_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, jobs,
+                       prefix, n_jobs, total);
   return hipGetLastError();
 }
 

@@ -31,6 +31,14 @@
 #include "qmk_internal.h"
 
 namespace qmk {
+// Launch of the persistent form, shared by the per-product translation units.
+struct BfpPersist {
+  const GemmArgs* jobs;
+  const WorkItem* items;
+  int n_items, grid;
+  int* occupancy;  // != NULL: report resident workgroups per CU, launch nothing
+};
+
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -372,6 +380,22 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(GemmArgs g, 
   bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR>(g, mt, nt, z, sm, s_list, &s_n);
 }
 
+// Persistent form (batch executor): the grid walks a list of (job, M tile,
+// N tile, z) items, each job holding one molecule's arguments.
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmArgs* __restrict__ jobs,
+                                                                    const WorkItem* __restrict__ items,
+                                                                    int n_items) {
+  __shared__ __align__(16) PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN> sm;
+  __shared__ int16_t s_list[1];
+  __shared__ int s_n;
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const WorkItem it = items[i];
+    bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, 0>(jobs[it.job], it.a, it.b, it.c, sm, s_list, &s_n);
+    __syncthreads();  // LDS is restaged by the next item
+  }
+}
+
 // {WGM, WGN, TM, TN, DEPTH}; the reduction step is always 32.
 #define QMK_BF16P_TILE_LIST(X) \
   X(0, 2, 2, 4, 4, 1)          \
@@ -408,24 +432,30 @@ hipError_t run_bfp_tile(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool A_MN, typename TD, int SCR, int WGM, int WGN, int TM, int TN, int DEPTH>
-int bfp_occupancy() {
-  int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &n, gemm_bf16p_kernel<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR>, 64 * WGM * WGN, 0);
-  return (e == hipSuccess && n > 0) ? n : 1;
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
+hipError_t run_bfp_tile_persist(const BfpPersist& pl, hipStream_t s) {
+  auto k = gemm_bf16p_persist<A_MN, TD, WGM, WGN, TM, TN, DEPTH>;
+  if (pl.occupancy) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * WGM * WGN, 0);
+    *pl.occupancy = (e == hipSuccess && n > 0) ? n : 1;
+    return e;
+  }
+  if (pl.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(pl.grid), dim3(64 * WGM * WGN), 0, s, pl.jobs, pl.items, pl.n_items);
+  return hipGetLastError();
 }
 
-template <bool A_MN, typename TD, int SCR>
-int occupancy_of(int cfg) {
+template <bool A_MN, typename TD>
+hipError_t run_bfp_persist(int cfg, const BfpPersist& pl, hipStream_t s) {
   switch (cfg) {
-#define QMK_BFP_OCC(id, wgm, wgn, tm, tn, depth) \
-  case id:                                       \
-    return bfp_occupancy<A_MN, TD, SCR, wgm, wgn, tm, tn, depth>();
-    QMK_BF16P_TILE_LIST(QMK_BFP_OCC)
-#undef QMK_BFP_OCC
+#define QMK_BFP_PCASE(id, wgm, wgn, tm, tn, depth) \
+  case id:                                         \
+    return run_bfp_tile_persist<A_MN, TD, wgm, wgn, tm, tn, depth>(pl, s);
+    QMK_BF16P_TILE_LIST(QMK_BFP_PCASE)
+#undef QMK_BFP_PCASE
     default:
-      return 1;
+      return hipErrorInvalidValue;
   }
 }
 
@@ -450,17 +480,25 @@ hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, int scr, hipStrea
   if (scr) return o32 ? run_bfp<true, float, 2>(cfg, g, s) : run_bfp<true, double, 2>(cfg, g, s);
   return o32 ? run_bfp<true, float, 0>(cfg, g, s) : run_bfp<true, double, 0>(cfg, g, s);
 }
+hipError_t bf16p_unit_fwd_persist(int cfg, const BfpPersist& pl, int o32, hipStream_t s) {
+  return o32 ? run_bfp_persist<true, float>(cfg, pl, s) : run_bfp_persist<true, double>(cfg, pl, s);
+}
 #endif
 #if QMK_GEMM_UNIT == 2
 hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, int scr, hipStream_t s) {
   return scr ? run_bfp<false, float, 3>(cfg, g, s) : run_bfp<false, float, 0>(cfg, g, s);
+}
+hipError_t bf16p_unit_gbar_persist(int cfg, const BfpPersist& pl, hipStream_t s) {
+  return run_bfp_persist<false, float>(cfg, pl, s);
 }
 #endif
 #if QMK_GEMM_UNIT == 3
 hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, int scr, hipStream_t s) {
   return scr ? run_bfp<true, double, 4>(cfg, g, s) : run_bfp<true, double, 0>(cfg, g, s);
 }
-int bf16p_unit_dc_occupancy(int cfg) { return occupancy_of<true, double, 0>(cfg); }
+hipError_t bf16p_unit_dc_persist(int cfg, const BfpPersist& pl, hipStream_t s) {
+  return run_bfp_persist<true, double>(cfg, pl, s);
+}
 #endif
 #else
 // The three products are instantiated in their own translation units (this
@@ -469,11 +507,14 @@ int bf16p_unit_dc_occupancy(int cfg) { return occupancy_of<true, double, 0>(cfg)
 hipError_t bf16p_unit_fwd(int cfg, const GemmArgs& g, int o32, int scr, hipStream_t s);
 hipError_t bf16p_unit_gbar(int cfg, const GemmArgs& g, int scr, hipStream_t s);
 hipError_t bf16p_unit_dc(int cfg, const GemmArgs& g, int scr, hipStream_t s);
-int bf16p_unit_dc_occupancy(int cfg);
+hipError_t bf16p_unit_fwd_persist(int cfg, const BfpPersist& pl, int o32, hipStream_t s);
+hipError_t bf16p_unit_gbar_persist(int cfg, const BfpPersist& pl, hipStream_t s);
+hipError_t bf16p_unit_dc_persist(int cfg, const BfpPersist& pl, hipStream_t s);
 
-int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg) {
-  if (kind != GemmKind::kDcoef || cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return 1;
-  return bf16p_unit_dc_occupancy(cfg);
+int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg, int out_is_f32) {
+  int n = 1;
+  if (launch_gemm_bf16p_persist(kind, cfg, nullptr, nullptr, 0, 0, out_is_f32, &n, nullptr) != hipSuccess) return 1;
+  return n;
 }
 
 int gemm_bf16p_num_tiles() { return sizeof(kBfpTiles) / sizeof(kBfpTiles[0]); }
@@ -490,15 +531,31 @@ size_t gemm_bf16p_tile_lds_bytes(int cfg) {
 // forward: A = AO planes (MN-major), B = C planes [n][k]
 // Gbar:    A = C^T planes [k][n] (K-major), B = W planes [p][c][n]
 // dC:      A = W planes (MN-major over n), B = AO planes (K-major over p)
-hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, int screened,
-                             hipStream_t s) {
-  if (cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return hipErrorInvalidValue;
+bool gemm_bf16p_args_ok(int cfg, const GemmArgs& g) {
+  if (cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return false;
   // the loaders address a tile's chunks by 32-bit byte offsets from the
   // tile's base: (rows - 1) * row stride + (BK - 1) * reduction stride + 8
   const TileCfg& t = kBfpTiles[cfg];
   const int64_t ea = (16 * t.wgm * t.tm - 1) * g.sAi + (BK - 1) * g.sAl + 8;
   const int64_t eb = (16 * t.wgn * t.tn - 1) * g.sBj + (BK - 1) * g.sBl + 8;
-  if (ea < 0 || eb < 0 || 2 * ea > 0x7fffffffLL || 2 * eb > 0x7fffffffLL) return hipErrorInvalidValue;
+  return ea >= 0 && eb >= 0 && 2 * ea <= 0x7fffffffLL && 2 * eb <= 0x7fffffffLL;
+}
+
+hipError_t launch_gemm_bf16p_persist(GemmKind kind, int cfg, const GemmArgs* jobs, const WorkItem* items,
+                                     int n_items, int grid, int out_is_f32, int* occupancy, hipStream_t s) {
+  if (cfg < 0 || cfg >= gemm_bf16p_num_tiles()) return hipErrorInvalidValue;
+  const BfpPersist pl{jobs, items, n_items, grid, occupancy};
+  switch (kind) {
+    case GemmKind::kForward: return bf16p_unit_fwd_persist(cfg, pl, out_is_f32, s);
+    case GemmKind::kGbar: return bf16p_unit_gbar_persist(cfg, pl, s);
+    case GemmKind::kDcoef: return bf16p_unit_dc_persist(cfg, pl, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, int screened,
+                             hipStream_t s) {
+  if (!gemm_bf16p_args_ok(cfg, g)) return hipErrorInvalidValue;
   switch (kind) {
     case GemmKind::kForward: return bf16p_unit_fwd(cfg, g, out_is_f32, screened, s);
     case GemmKind::kGbar: return bf16p_unit_gbar(cfg, g, screened, s);

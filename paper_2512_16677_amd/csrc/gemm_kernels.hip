@@ -210,7 +210,8 @@ hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& 
 hipError_t launch_gemm_persist(GemmKind kind, Prec prec, int cfg, const GemmArgs* jobs,
                                const WorkItem* items, int n_items, int grid, int w_is_f32,
                                int out_is_f32, hipStream_t s) {
-  if (prec == Prec::kBF16P) return hipErrorInvalidValue;  // no persistent form
+  if (prec == Prec::kBF16P)
+    return launch_gemm_bf16p_persist(kind, cfg, jobs, items, n_items, grid, out_is_f32, nullptr, s);
   if (prec == Prec::kBF16x3)
     return launch_gemm_bf16x3_persist(kind, cfg, jobs, items, n_items, grid, w_is_f32, out_is_f32,
                                       nullptr, s);
@@ -221,7 +222,7 @@ hipError_t launch_gemm_persist(GemmKind kind, Prec prec, int cfg, const GemmArgs
 
 int gemm_persist_blocks_per_cu(GemmKind kind, Prec prec, int cfg, int w_is_f32, int out_is_f32) {
   int n = 1;
-  if (prec == Prec::kBF16P) return gemm_bf16p_blocks_per_cu(kind, cfg);
+  if (prec == Prec::kBF16P) return gemm_bf16p_blocks_per_cu(kind, cfg, out_is_f32);
   if (prec == Prec::kBF16x3) {
     (void)launch_gemm_bf16x3_persist(kind, cfg, nullptr, nullptr, 0, 0, w_is_f32, out_is_f32, &n,
                                      nullptr);

@@ -289,7 +289,8 @@ size_t gemm_bf16p_tile_lds_bytes(int cfg);
 // most kSparseMaxStages * 32).
 hipError_t launch_gemm_bf16p(GemmKind kind, int cfg, const GemmArgs& g, int out_is_f32, int screened,
                              hipStream_t s);
-int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg);
+// Resident workgroups per compute unit of the persistent form.
+int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg, int out_is_f32);
 // W[p][c][n] (P x 5 x N, FP64 or FP32) split into bf16 planes hi / lo laid
 // out [Pp][5][Nw] (Nw a multiple of 8), zero beyond P and N.  perm != NULL:
 // plane row p holds W row perm[p] (the screened products' point order).
@@ -366,6 +367,8 @@ struct NucRedJob {
   double* out;
 };
 
+// out_is_f32: 0 FP64, 1 FP32, 2 bf16 hi / lo planes (out.plane apart), as
+// for launch_ao_vgl.
 hipError_t launch_ao_vgl_persist(const AoJob* jobs, const WorkItem* items, int n_items, int grid,
                                  size_t smem, int out_is_f32, hipStream_t s);
 hipError_t launch_ao_adjoint_persist(const AdjJob* jobs, const WorkItem* items, int n_items,
@@ -380,6 +383,35 @@ hipError_t launch_reduce_nuc_batch(const NucRedJob* jobs, const int64_t* prefix,
 hipError_t launch_gemm_bf16x3_persist(GemmKind kind, int cfg, const GemmArgs* jobs,
                                       const WorkItem* items, int n_items, int grid, int w_is_f32,
                                       int out_is_f32, int* occupancy, hipStream_t s);
+// Persistent form of the pre-split BF16x3 kernel (no screening).
+// occupancy != NULL: stores the resident workgroups per compute unit and
+// launches nothing.
+hipError_t launch_gemm_bf16p_persist(GemmKind kind, int cfg, const GemmArgs* jobs, const WorkItem* items,
+                                     int n_items, int grid, int out_is_f32, int* occupancy, hipStream_t s);
+// Whether the strides of g fit the 32-bit tile offsets of the pre-split
+// kernel's loaders for tile cfg.
+bool gemm_bf16p_args_ok(int cfg, const GemmArgs& g);
+// Largest j with prefix[j] <= e (prefix[0] = 0, increasing): the job of
+// flat element e in the batched element-wise kernels.
+__device__ __forceinline__ int find_job(const int64_t* prefix, int n_jobs, int64_t e) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+// Batched W split (batch executor): job j covers elements prefix[j] ..
+// prefix[j+1]-1 of a flat range, one per eight weights of its planes.
+struct SplitJob {
+  const void* w;
+  int64_t P, N, Pp, Nw;
+  int32_t vec;
+  void* hi;
+  void* lo;
+};
+hipError_t launch_split_w_batch(const SplitJob* jobs, const int64_t* prefix, int n_jobs, int64_t total,
+                                int w_is_f32, hipStream_t s);
 // Resident blocks per compute unit of the persistent kernels.
 int ao_persist_blocks_per_cu(int f32, size_t smem);
 int adj_persist_blocks_per_cu(int f32, size_t smem);

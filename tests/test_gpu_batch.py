@@ -139,3 +139,40 @@ def test_batch96_full_size_sampled():
     b.close()
     for c in ctxs:
         c.close()
+
+
+@pytest.mark.parametrize("mode,tol,otol", [("mixed_f32", 1e-6, 4e-6), ("mixed_bf16x3", 1e-5, 1e-4)])
+def test_batch96_mixed_full_size_sampled(mode, tol, otol):
+    """The timed batch workload in the mixed modes (BF16x3: the pre-split
+    planes path of every stage): every molecule's MOs and gradients equal its
+    solo run within the mode's rounding (the solo products split the point
+    range differently), and the first walker of four sampled molecules
+    matches the oracle within the mode's bound (B = 53)."""
+    q = qmk()
+    mols = synth.molecule_batch(96, seed=0)
+    ctxs = contexts(mols, mode=mode)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(98)
+    ws = [torch.randn((m.walk_num, m.elec_num, 5, m.mo_num), generator=g, device="cuda",
+                      dtype=torch.float32) for m in mols]
+    b = q.Batch(ctxs)
+    b.run(dtype=torch.float32, ws=ws)  # tiles timed, graph captured
+    outs, grads = b.run(dtype=torch.float32, ws=ws)  # graph replay, as timed
+    torch.cuda.synchronize()
+    for m, c, o, gr, w in zip(mols, ctxs, outs, grads, ws):
+        ref = c.get_mo_vgl(dtype=torch.float32)
+        rg = c.adjoint(w)
+        e = rownorm_err(o.cpu().numpy().reshape(-1, 5, m.mo_num), ref.cpu().numpy().reshape(-1, 5, m.mo_num))
+        assert e.max() <= tol, (m.name, e.max())
+        for k in ("d_coef", "d_elec", "d_nucl"):
+            assert maxrel(gr[k], rg[k]) <= 10 * tol, (m.name, k, maxrel(gr[k], rg[k]))
+    size = [m.ao_num * m.point_num for m in mols]
+    picks = sorted({int(np.argmin(size)), int(np.argmax(size)), 17, 60})
+    for i in picks:
+        m = mols[i]
+        r = oracle.mo_vgl(m, points=m.points()[: m.elec_num])
+        got = outs[i].cpu().numpy().reshape(-1, 5, m.mo_num)[: m.elec_num]
+        assert rownorm_err(got, r).max() <= otol, (m.name, rownorm_err(got, r).max())
+    b.close()
+    for c in ctxs:
+        c.close()
