@@ -152,7 +152,7 @@ def errors_vs(ref, got, quantile=True):
 
 
 KERNEL_SOURCES = {  # files whose change invalidates a kernel class's counter figures
-    "mo": ["gemm_impl.h", "gemm_kernels.hip", "gemm_bf16.hip", "qmk_internal.h", "context.cpp",
+    "mo": ["gemm_impl.h", "gemm_kernels.hip", "gemm_bf16p.hip", "qmk_internal.h", "context.cpp",
            "tiles_gfx950.json"],
     "ao": ["ao_kernels.hip", "qmk_internal.h", "context.cpp"],
     "ao_adjoint": ["adjoint_kernels.hip", "qmk_internal.h", "context.cpp"],

@@ -37,10 +37,9 @@ SOURCES = [("context.cpp", [], None), ("batch.cpp", [], None), ("tuner.cpp", [],
            ("cusp_kernels.hip", [], None), ("sort_kernels.hip", [], None),
            ("det_kernels.hip", [], None), ("jastrow_kernels.hip", [], None), ("convert_kernels.hip", [], None),
            ("noalloc.hip", [], None),
-           ("gemm_kernels.hip", [], None), ("gemm_bf16.hip", [], None)]
+           ("gemm_kernels.hip", [], None)]
 SOURCES += [("gemm_kernels.hip", [f"-DQMK_GEMM_UNIT={u}"] + UNIT_FLAGS.get(u, []), f"gemm_kernels_u{u}")
             for u in range(1, 11)]
-SOURCES += [("gemm_bf16.hip", [f"-DQMK_GEMM_UNIT={u}"] + VGPR_ACC, f"gemm_bf16_u{u}") for u in range(1, 4)]
 SOURCES += [("gemm_bf16p.hip", [], None)]
 SOURCES += [("gemm_bf16p.hip", [f"-DQMK_GEMM_UNIT={u}"] + VGPR_ACC, f"gemm_bf16p_u{u}") for u in range(1, 4)]
 

@@ -229,7 +229,6 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
 GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w) {
   qmk_ctx c = b->ctxs[m];
   const MolPlan& mp = b->plan[m];
-  const bool bf = b->prec == Prec::kBF16x3;
   const bool planes = b->prec == Prec::kBF16P;
   const char* aop = static_cast<const char*>(b->ao.p) + mp.ao_off * b->esz;
   // bf16 planes: the AO array's lo plane follows its hi plane; W's planes
@@ -246,13 +245,12 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.sAi = 1;
     g.sAl = 5 * mp.Pp;
     g.oAc = mp.Pp;
-    if (planes) g.A2 = ao_lo;
-    if (bf || planes) {
+    if (planes) {
+      g.A2 = ao_lo;
       g.B = c->d_Cb_hi.p;
       g.B2 = c->d_Cb_lo.p;
       g.sBl = 1;
       g.sBj = mp.Kp;
-      g.vec_ok = 3;
     } else {
       g.B = c->d_Ct.p;
       g.sBl = mp.Np;
@@ -266,13 +264,8 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.N = mp.N;
     g.L = g.Lchunk = mp.K;
   } else if (kind == GemmKind::kGbar) {
-    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, b->tile_w32, c->d_C.p, c->d_Ctb_hi.p,
+    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, mp.Nw, c->d_C.p, c->d_Ctb_hi.p,
                   c->d_Ctb_lo.p, gbp, mp.P, mp.Pp, mp.K, mp.Kp, mp.N, mp.Np);
-    if (planes) {
-      g.B2 = w_lo;
-      g.sBj = 5 * mp.Nw;
-      g.oBc = mp.Nw;
-    }
   } else {
     g.A = w;
     g.sAi = 1;
@@ -293,7 +286,6 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.L = mp.P;
     g.Lchunk = mp.chunk;
     g.nsplit = static_cast<int32_t>(mp.nsplit);
-    if (bf) g.vec_ok = (w_vec_ok(w, mp.N, b->tile_w32) ? 1 : 0) | 2;
     if (planes) {
       g.A = w_hi;
       g.A2 = w_lo;

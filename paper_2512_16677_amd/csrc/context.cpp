@@ -637,7 +637,7 @@ qmk_status ensure_cusp(qmk_ctx ctx, hipStream_t s) {
 Prec product_prec(qmk_ctx ctx, GemmKind kind) {
   if (kind == GemmKind::kJastrow) return Prec::kF64;
   const Prec p = gemm_prec(ctx);
-  return kind == GemmKind::kDensity && (p == Prec::kBF16x3 || p == Prec::kBF16P) ? Prec::kF32 : p;
+  return kind == GemmKind::kDensity && p == Prec::kBF16P ? Prec::kF32 : p;
 }
 
 qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
@@ -656,24 +656,18 @@ qmk_status pick_tile(qmk_ctx ctx, const GemmProblem& pb, hipStream_t s,
   return QMK_OK;
 }
 
-// Rows of W ([point][5][mo]) allow 16-byte vector loads in the BF16x3 product.
-bool w_vec_ok(const void* w, int64_t N, int w32) {
-  const uintptr_t a = reinterpret_cast<uintptr_t>(w);
-  return a % 16 == 0 && (w32 ? N % 4 == 0 : N % 2 == 0);
-}
-
 Prec gemm_prec(qmk_ctx ctx) {
   return ctx->mode == QMK_FP64 ? Prec::kF64 : (ctx->mode == QMK_MIXED_F32 ? Prec::kF32 : Prec::kBF16P);
 }
 
-GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void* Ct_hi,
+GemmArgs gbar_args(Prec prec, const void* w, const void* w_lo, int64_t Nw, const void* C, const void* Ct_hi,
                    const void* Ct_lo, void* gbar, int64_t P, int64_t Pp, int64_t K, int64_t Kp,
                    int64_t N, int64_t Np) {
   GemmArgs g{};
   g.L = g.Lchunk = N;
   g.nsplit = 1;
   g.nbatch = 5;
-  if (prec == Prec::kBF16x3 || prec == Prec::kBF16P) {
+  if (prec == Prec::kBF16P) {
     // rows k, columns p (as below, so that Gbar is stored in full lines);
     // both operands are read along the reduction index n, as this kernel
     // needs
@@ -681,11 +675,11 @@ GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void*
     g.A2 = Ct_lo;
     g.sAi = Np;
     g.sAl = 1;
-    g.B = w;  // W [p][c][n]
+    g.B = w;  // W planes [Pp][5][Nw]
+    g.B2 = w_lo;
     g.sBl = 1;
-    g.sBj = 5 * N;
-    g.oBc = N;
-    g.vec_ok = 1 | (w_vec_ok(w, N, w32) ? 2 : 0);
+    g.sBj = 5 * Nw;
+    g.oBc = Nw;
     g.D = gbar;
     g.sDi = 5 * Pp;
     g.sDj = 1;
@@ -1617,13 +1611,8 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ctx->gbar_Kp = Kp;
       ctx->gbar_f32 = f32;
     }
-    GemmArgs ga = gbar_args(prec, planes ? static_cast<const void*>(w_hi) : w, w32, ctx->d_C.p,
+    GemmArgs ga = gbar_args(prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, Nw, ctx->d_C.p,
                             ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p, ctx->gbar.p, P, Pp, K, Kp, N, Np);
-    if (planes) {
-      ga.B2 = w_lo;
-      ga.sBj = 5 * Nw;
-      ga.oBc = Nw;
-    }
     if (scr) screen(ga);
     GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
     pb.sparse = scr ? 1 : 0;
@@ -1733,7 +1722,6 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ga.Lchunk = chunk;
       ga.nsplit = static_cast<int32_t>(nsplit);
       ga.nbatch = 5;
-      ga.vec_ok = (w_vec_ok(w, N, w32) ? 1 : 0) | 2;
       ga.map_slab = 1;
       if (scr) screen(ga);
       hipError_t e;

@@ -201,11 +201,12 @@ qmk_status check_ready(qmk_ctx ctx, bool need_coef);
 PointArgs point_args(qmk_ctx ctx);
 Prec gemm_prec(qmk_ctx ctx);
 Prec product_prec(qmk_ctx ctx, GemmKind kind);
-bool w_vec_ok(const void* w, int64_t N, int w32);
 bool device_accessible(const void* p, int device);
-// Arguments of the product Gbar[k][c][p] = sum_n W[p][c][n] C[n][k] (the
-// FP64 / FP32 kernels take C as the left operand, the BF16x3 kernel W).
-GemmArgs gbar_args(Prec prec, const void* w, int w32, const void* C, const void* Ct_hi,
+// Arguments of the product Gbar[k][c][p] = sum_n W[p][c][n] C[n][k].  Both
+// kernels compute Gbar with rows k and columns p; the FP64 / FP32 kernels read
+// C [n][k] and W, the BF16x3 kernel the split C^T planes (Ct_hi / Ct_lo) and
+// the split W planes (w / w_lo, [Pp][5][Nw]).
+GemmArgs gbar_args(Prec prec, const void* w, const void* w_lo, int64_t Nw, const void* C, const void* Ct_hi,
                    const void* Ct_lo, void* gbar, int64_t P, int64_t Pp, int64_t K, int64_t Kp,
                    int64_t N, int64_t Np);
 

@@ -157,18 +157,15 @@ hipError_t unit_dispatch(GemmKind kind, Prec prec, int cfg, const GemmArgs* g, c
 }  // namespace
 
 int gemm_num_tiles(Prec prec) {
-  if (prec == Prec::kBF16P) return gemm_bf16p_num_tiles();
-  return prec == Prec::kBF16x3 ? gemm_bf16_num_tiles() : kNumTiles;
+  return prec == Prec::kBF16P ? gemm_bf16p_num_tiles() : kNumTiles;
 }
 
 TileCfg gemm_tile(Prec prec, int cfg) {
-  if (prec == Prec::kBF16P) return gemm_bf16p_tile(cfg);
-  return prec == Prec::kBF16x3 ? gemm_bf16_tile(cfg) : kTiles[cfg];
+  return prec == Prec::kBF16P ? gemm_bf16p_tile(cfg) : kTiles[cfg];
 }
 
 size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
   if (prec == Prec::kBF16P) return gemm_bf16p_tile_lds_bytes(cfg);
-  if (prec == Prec::kBF16x3) return gemm_bf16_tile_lds_bytes(cfg);
   const TileCfg& t = kTiles[cfg];
   const size_t esz = prec == Prec::kF64 ? 8 : 4;
   const size_t pad = 16 / esz;
@@ -177,13 +174,13 @@ size_t gemm_tile_lds_bytes(Prec prec, int cfg) {
 }
 
 hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s) {
-  if (prec == Prec::kBF16x3 || prec == Prec::kBF16P || cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
+  if (prec == Prec::kBF16P || cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   return gemm_unit_sparse(cfg, &g, prec, out_is_f32, s);
 }
 
 hipError_t launch_gemm_screened_adj(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                                     hipStream_t s) {
-  if (prec == Prec::kBF16x3 || prec == Prec::kBF16P || cfg < 0 || cfg >= kNumTiles ||
+  if (prec == Prec::kBF16P || cfg < 0 || cfg >= kNumTiles ||
       (kind != GemmKind::kGbar && kind != GemmKind::kDcoef))
     return hipErrorInvalidValue;
   return gemm_unit_screened_adj(kind, cfg, &g, prec, w_is_f32, s);
@@ -195,14 +192,13 @@ hipError_t launch_gemm_jastrow(int cfg, const GemmArgs& g, hipStream_t s) {
 }
 
 hipError_t launch_gemm_density(Prec prec, int cfg, const GemmArgs& g, hipStream_t s) {
-  if (prec == Prec::kBF16x3 || prec == Prec::kBF16P || cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
+  if (prec == Prec::kBF16P || cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   return gemm_unit_density(cfg, &g, prec, s);
 }
 
 hipError_t launch_gemm_typed(GemmKind kind, Prec prec, int cfg, const GemmArgs& g, int w_is_f32,
                              int out_is_f32, hipStream_t s) {
   if (prec == Prec::kBF16P) return launch_gemm_bf16p(kind, cfg, g, out_is_f32, 0, s);
-  if (prec == Prec::kBF16x3) return launch_gemm_bf16x3(kind, cfg, g, w_is_f32, out_is_f32, s);
   if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   return unit_dispatch(kind, prec, cfg, &g, nullptr, w_is_f32, out_is_f32, s);
 }
@@ -212,9 +208,6 @@ hipError_t launch_gemm_persist(GemmKind kind, Prec prec, int cfg, const GemmArgs
                                int out_is_f32, hipStream_t s) {
   if (prec == Prec::kBF16P)
     return launch_gemm_bf16p_persist(kind, cfg, jobs, items, n_items, grid, out_is_f32, nullptr, s);
-  if (prec == Prec::kBF16x3)
-    return launch_gemm_bf16x3_persist(kind, cfg, jobs, items, n_items, grid, w_is_f32, out_is_f32,
-                                      nullptr, s);
   if (cfg < 0 || cfg >= kNumTiles) return hipErrorInvalidValue;
   PersistLaunch pl{jobs, items, n_items, grid, nullptr};
   return unit_dispatch(kind, prec, cfg, nullptr, &pl, w_is_f32, out_is_f32, s);
@@ -223,11 +216,6 @@ hipError_t launch_gemm_persist(GemmKind kind, Prec prec, int cfg, const GemmArgs
 int gemm_persist_blocks_per_cu(GemmKind kind, Prec prec, int cfg, int w_is_f32, int out_is_f32) {
   int n = 1;
   if (prec == Prec::kBF16P) return gemm_bf16p_blocks_per_cu(kind, cfg, out_is_f32);
-  if (prec == Prec::kBF16x3) {
-    (void)launch_gemm_bf16x3_persist(kind, cfg, nullptr, nullptr, 0, 0, w_is_f32, out_is_f32, &n,
-                                     nullptr);
-    return n;
-  }
   if (cfg < 0 || cfg >= kNumTiles) return 1;
   PersistLaunch pl{nullptr, nullptr, 0, 0, &n};
   (void)unit_dispatch(kind, prec, cfg, nullptr, &pl, w_is_f32, out_is_f32, nullptr);

@@ -125,11 +125,9 @@ struct GemmArgs {
   int64_t sDi, sDj, oDz;
   int64_t M, N, L, Lchunk;
   int32_t nsplit, nbatch;   // gridDim.y = nbatch * nsplit
-  // BF16x3 kernel only: second (lo) plane of a pre-split operand, and bit 0 /
-  // bit 1 set when A / B rows allow 16-byte vector loads.
+  // BF16x3 kernel only: second (lo) plane of a pre-split operand.
   const void* A2;
   const void* B2;
-  int32_t vec_ok;
   // Workgroup -> tile order of the grid launch.  0: the N tiles of one M tile
   // run back to back on one XCD (A tile reused from that XCD's L2).  1: all
   // tiles of one batch index z run together on one XCD (split products,
@@ -212,10 +210,9 @@ __device__ __forceinline__ AxisD axis_derivs(int e, double t, double t2, double 
 }
 
 enum class GemmKind { kForward, kGbar, kDcoef, kDensity, kJastrow };
-// kBF16x3: BF16x3 products that split FP32/FP64 operands as they load them
-// (batch executor); kBF16P: BF16x3 products on operands pre-split into bf16
-// planes (a context's own products in the BF16x3 mode).
-enum class Prec { kF64, kF32, kBF16x3, kBF16P };
+// kBF16P: BF16x3 products on operands pre-split into bf16 hi / lo planes.
+// The values are part of the persisted tile-table keys.
+enum class Prec { kF64 = 0, kF32 = 1, kBF16P = 3 };
 
 // Launchers (return hipError_t of the launch).
 // out_is_f32: 0 FP64, 1 FP32, 2 split bf16 planes (hi, lo; see AoOut::plane).
@@ -296,12 +293,6 @@ int gemm_bf16p_blocks_per_cu(GemmKind kind, int cfg, int out_is_f32);
 // plane row p holds W row perm[p] (the screened products' point order).
 hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int64_t Pp, int64_t Nw,
                           const int32_t* perm, void* hi, void* lo, hipStream_t s);
-// BF16x3 kernel (gemm_bf16.hip); reached through launch_gemm_typed.
-int gemm_bf16_num_tiles();
-TileCfg gemm_bf16_tile(int cfg);
-size_t gemm_bf16_tile_lds_bytes(int cfg);
-hipError_t launch_gemm_bf16x3(GemmKind kind, int cfg, const GemmArgs& g, int w_is_f32,
-                              int out_is_f32, hipStream_t s);
 
 // Autotuner (tuner.cpp).
 struct GemmProblem {
@@ -380,9 +371,6 @@ hipError_t launch_reduce_batch(const RedJob* jobs, const int64_t* prefix, int n_
                                hipStream_t s);
 hipError_t launch_reduce_nuc_batch(const NucRedJob* jobs, const int64_t* prefix, int n_jobs,
                                    int64_t total, hipStream_t s);
-hipError_t launch_gemm_bf16x3_persist(GemmKind kind, int cfg, const GemmArgs* jobs,
-                                      const WorkItem* items, int n_items, int grid, int w_is_f32,
-                                      int out_is_f32, int* occupancy, hipStream_t s);
 // Persistent form of the pre-split BF16x3 kernel (no screening).
 // occupancy != NULL: stores the resident workgroups per compute unit and
 // launches nothing.
