@@ -33,25 +33,27 @@ __device__ __forceinline__ void st(T* p, double v, int64_t) { *p = static_cast<T
 // half, so that every lane writes one 32-bit word: the even lane the hi
 // values of its point and the next, the odd lane the lo values of the
 // previous point and its own.  A wave's store therefore covers 128 bytes of
-// each plane, and both lanes of every pair must take part.
+// each plane, and both lanes of every pair must take part.  The odd lane's
+// output pointer already points at its word of the lo plane (the kernel
+// moves it by plane - 1 elements once), so `plane` is not used here.
 struct Bf16Pair {
   uint16_t bits;
 };
-__device__ __forceinline__ void st(Bf16Pair* p, double v, int64_t plane) {
-  const float f = static_cast<float>(v);
+__device__ __forceinline__ void st(Bf16Pair* p, double v, int64_t) {
+  float f = static_cast<float>(v);
+  // hi is the bf16 rounding of the FP32 value: without this barrier the two
+  // conversions would be merged into one FP64 -> bf16 rounding
+  asm volatile("" : "+v"(f));
   const __bf16 h = static_cast<__bf16>(f);
   const __bf16 l = static_cast<__bf16>(f - static_cast<float>(h));
-  const uint32_t hb = __builtin_bit_cast(uint16_t, h), lb = __builtin_bit_cast(uint16_t, l);
-  const bool odd = (threadIdx.x & 1) != 0;
-  // quad_perm [1, 0, 3, 2]: exchange with the neighbouring lane
-  const uint32_t recv = static_cast<uint32_t>(
-      __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? hb : lb), 0xB1, 0xF, 0xF, true));
-  // one store instruction for the whole wave: the address and the word are
-  // selected per lane
-  uint16_t* q = reinterpret_cast<uint16_t*>(p);
-  uint32_t* dst = reinterpret_cast<uint32_t*>(odd ? q - 1 + plane : q);
-  const uint32_t word = odd ? ((recv & 0xffffu) | (lb << 16)) : (hb | (recv << 16));
-  *dst = word;
+  const uint32_t pk = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h)) |
+                      (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l)) << 16);
+  // quad_perm [1, 0, 3, 2]: the neighbouring lane's (hi, lo) pair
+  const uint32_t rp = static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(pk), 0xB1, 0xF, 0xF, true));
+  // bytes 0-3 of the selection are pk, 4-7 rp: the even lane takes (pk.hi,
+  // rp.hi), the odd lane (rp.lo, pk.lo)
+  const uint32_t sel = (threadIdx.x & 1) ? 0x03020706u : 0x05040100u;
+  *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(rp, pk, sel);
 }
 
 // Stores value, gradient and Laplacian of the (l+1)(l+2)/2 Cartesian AOs of
@@ -156,9 +158,11 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
     ry = pts.coord[src * pts.s_pt + pts.s_ax];
     rz = pts.coord[src * pts.s_pt + 2 * pts.s_ax];
   }
-  OutT* const obase = static_cast<OutT*>(out.out) + p * out.sP;
-  const double T = t.T;
   constexpr bool kPairs = std::is_same<OutT, Bf16Pair>::value;
+  // split planes: the odd lane of each pair writes the lo plane, one point back
+  OutT* const obase = static_cast<OutT*>(out.out) + p * out.sP +
+                      ((kPairs && (threadIdx.x & 1)) ? out.plane - 1 : 0);
+  const double T = t.T;
 
   for (int a = 0; a < nn; ++a) {
     const NucDev nu = s_nuc[a];

@@ -558,7 +558,9 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
         // vector loads need every group of eight weights to start 16-byte aligned
         const int vec = reinterpret_cast<uintptr_t>(ws[i]) % 16 == 0 && (mp.N * esz_w) % 16 == 0;
         split.push_back(SplitJob{ws[i], mp.P, mp.N, mp.Pp, mp.Nw, vec, hi, hi + mp.Pp * 5 * mp.Nw});
-        split_prefix.push_back(split_prefix.back() + mp.Pp * 5 * (mp.Nw / 8));
+        const int64_t nj = mp.Pp * 5 * (mp.Nw / 8);
+        if (nj > 0xffffffffLL) return bfail(b, QMK_SIZE, "context " + std::to_string(i) + ": W too large to split");
+        split_prefix.push_back(split_prefix.back() + nj);
       }
       gj[1].push_back(gemm_job(b, i, GemmKind::kGbar, nullptr, ws[i]));
       gj[2].push_back(gemm_job(b, i, GemmKind::kDcoef, nullptr, ws[i]));

@@ -24,16 +24,18 @@ __global__ __launch_bounds__(256) void f64_to_f32_kernel(const double* __restric
 
 // W[p][c][n] -> hi, lo planes [Pp][5][Nw]: hi = bf16(x), lo = bf16(x - hi) of
 // the FP32-rounded weight x (round to nearest even); zeros beyond P and N.
-// One thread per eight consecutive n of one (p, c) row: idx < Pp * 5 * Nw / 8.
+// One thread per eight consecutive n of one (p, c) row: idx < Pp * 5 * Nw / 8,
+// which the launchers keep below 2^32 (32-bit index arithmetic).
 template <typename T>
 __device__ __forceinline__ void split_w8(const T* __restrict__ w, int64_t P, int64_t N, int64_t Nw, int vec,
                                          const int32_t* __restrict__ perm, __bf16* __restrict__ hi,
-                                         __bf16* __restrict__ lo, int64_t idx) {
+                                         __bf16* __restrict__ lo, uint32_t idx) {
   typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-  const int64_t cpr = Nw / 8;
-  const int64_t row = idx / cpr, n0 = (idx - row * cpr) * 8;
+  const uint32_t cpr = static_cast<uint32_t>(Nw / 8);
+  const uint32_t row32 = idx / cpr;
+  const int64_t row = row32, n0 = static_cast<int64_t>(idx - row32 * cpr) * 8;
   // source row: point perm[p] (or p), same component
-  const int64_t p = row / 5;
+  const int64_t p = row32 / 5u;
   const int64_t srow = (perm && p < P) ? static_cast<int64_t>(perm[p]) * 5 + (row - p * 5) : row;
   float x[8];
   if (row < P * 5 && vec && n0 + 8 <= N) {
@@ -59,6 +61,9 @@ __device__ __forceinline__ void split_w8(const T* __restrict__ w, int64_t P, int
   bf16x8 h, l;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
+    // hi is the bf16 rounding of the FP32 value: without this barrier the
+    // two conversions of an FP64 weight would be merged into one rounding
+    asm volatile("" : "+v"(x[e]));
     const __bf16 hh = static_cast<__bf16>(x[e]);
     h[e] = hh;
     l[e] = static_cast<__bf16>(x[e] - static_cast<float>(hh));
@@ -71,8 +76,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void split_w_kernel(const T* __restrict__ w, int64_t P, int64_t N, int64_t Pp,
                                                       int64_t Nw, int vec, const int32_t* __restrict__ perm,
                                                       __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= Pp * 5 * (Nw / 8)) return;
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<uint64_t>(Pp * 5 * (Nw / 8))) return;
   split_w8(w, P, N, Nw, vec, perm, hi, lo, idx);
 }
 
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(256) void split_w_batch_kernel(const SplitJob* __re
   const int jb = find_job(prefix, n_jobs, e);
   const SplitJob& j = jobs[jb];
   split_w8(static_cast<const T*>(j.w), j.P, j.N, j.Nw, j.vec, static_cast<const int32_t*>(nullptr),
-           static_cast<__bf16*>(j.hi), static_cast<__bf16*>(j.lo), e - prefix[jb]);
+           static_cast<__bf16*>(j.hi), static_cast<__bf16*>(j.lo), static_cast<uint32_t>(e - prefix[jb]));
 }
 
 }  // namespace
@@ -95,8 +100,8 @@ hipError_t launch_split_w(const void* w, int w_is_f32, int64_t P, int64_t N, int
   if (Pp <= 0 || Nw <= 0) return hipSuccess;
   if (Nw % 8 != 0 || Pp < P || Nw < N) return hipErrorInvalidValue;
   const int64_t n = Pp * 5 * (Nw / 8);
+  if (n > 0xffffffffLL - 255) return hipErrorInvalidValue;
   const int64_t blocks = (n + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const size_t esz = w_is_f32 ? 4 : 8;
   // vector loads need every group of eight weights to start 16-byte aligned
   const int vec = reinterpret_cast<uintptr_t>(w) % 16 == 0 && (N * esz) % 16 == 0;

@@ -390,7 +390,8 @@ __device__ __forceinline__ int find_job(const int64_t* prefix, int n_jobs, int64
   return lo;
 }
 // Batched W split (batch executor): job j covers elements prefix[j] ..
-// prefix[j+1]-1 of a flat range, one per eight weights of its planes.
+// prefix[j+1]-1 of a flat range, one per eight weights of its planes (fewer
+// than 2^32 per job).
 struct SplitJob {
   const void* w;
   int64_t P, N, Pp, Nw;
