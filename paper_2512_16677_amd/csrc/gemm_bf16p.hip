@@ -26,7 +26,20 @@
 // zero-padded to a multiple of 32 there.  Rows past the operand's row count
 // are staged as zeros (their chunks are loaded from the last row in range, so
 // every load stays in bounds).  Stores are guarded on both indices.
+//
+// Two staging schemes (the tile's DEPTH):
+//   DEPTH 1, 2: each thread loads its chunks into registers DEPTH K steps
+//     ahead and stores them to one of two LDS buffers;
+//   DEPTH >= 3: an LDS ring of DEPTH stages filled by global_load_lds_dwordx4
+//     (each lane's 16 bytes go from global memory straight to LDS), so the
+//     loads of step kt + DEPTH - 1 are in flight while step kt computes and
+//     no registers hold operand data.  The ring lays a tile out without
+//     padding (a load instruction fills 1 KB of consecutive LDS); an
+//     MN-major tile permutes the 16-byte chunks of each k-row instead (see
+//     mn_xor), and rows past the operand's row count hold copies of the last
+//     row's chunks: they only reach outputs that are not stored.
 #include <algorithm>
+#include <type_traits>
 
 #include "qmk_internal.h"
 
@@ -154,6 +167,178 @@ __device__ __forceinline__ bf16x8 frag_k(const __bf16* t, int r0, int lane) {
   return *reinterpret_cast<const bf16x8*>(t + (r0 + i) * KLD + ((lane >> 4) ^ kswz(i)) * 8);
 }
 
+// ---------------------------------------------------------------------------
+// LDS ring staging (DEPTH >= 3).
+
+// MN-major ring tile of R rows: 16-byte chunk c of k-row l sits at chunk
+// c ^ mn_xor(l).  A 16-lane group of the transposing fragment read touches
+// 32 consecutive bytes of each of four consecutive k-rows; with the k-row
+// pitch R * 2 bytes = 0 (mod 128) the permutation moves them to four
+// different 32-byte bank windows, with pitch = 64 (mod 128) it separates
+// the two pairs of rows that would coincide, and with 32 or 96 the rows
+// already fall apart.  Rows l and l + 4 always share the permutation.
+template <int R>
+__device__ __forceinline__ int mn_xor(int l) {
+  if constexpr ((R * 2) % 128 == 0) return 2 * (l & 3);
+  else if constexpr ((R * 2) % 128 == 64) return 2 * ((l >> 1) & 1);
+  else return 0;
+}
+
+// MFMA fragment of rows r0 .. r0+15 of an MN-major ring tile (as frag_mn).
+template <int R>
+__device__ __forceinline__ bf16x8 frag_mnx(const __bf16* t, int r0, int lane) {
+  const int g = lane >> 4, q = lane & 15;
+  const int l = 8 * g + (q >> 2);
+  const int e = r0 + 4 * (q & 3);
+  const __bf16* p0 = t + l * R + (((e >> 3) ^ mn_xor<R>(l)) << 3) + (e & 7);
+  const __bf16* p1 = p0 + 4 * R;
+  const s16x4 x0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_s16x4*)((__attribute__((address_space(3))) char*)(p0)));
+  const s16x4 x1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (lds_s16x4*)((__attribute__((address_space(3))) char*)(p1)));
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  const s16x8 x = __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, x);
+}
+
+// One stage of the ring: [A hi][A lo][B hi][B lo], BK reduction indices
+// each, 1 KB per load instruction.
+template <int BM, int BN, int S>
+struct RingSmem {
+  static constexpr int STAGE = (BM + BN) * BK * 2;  // elements
+  __bf16 ring[S * STAGE];
+};
+
+__device__ __forceinline__ uint32_t lds_address(const void* p) {
+  return static_cast<uint32_t>(
+      reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char*)(p)));
+}
+
+// One load instruction: lane l's 16 bytes at g land at LDS byte lds + 16 l
+// (the wave-uniform base goes through M0).  The compiler does not see these
+// LDS writes; ring_sync waits for them.
+__device__ __forceinline__ void dma16(const void* g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" : : "s"(lds), "v"(g)
+               : "memory", "m0");
+}
+
+// Waits until at most N of this wave's vector memory instructions are
+// outstanding and its LDS reads have returned, then joins the workgroup
+// barrier.  The memory clobber keeps the next step's LDS reads below it.
+template <int N>
+__device__ __forceinline__ void ring_sync() {
+  static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" : : "n"(N) : "memory");
+}
+
+// K loop of one tile on an S-stage ring.  Every wave issues the same number
+// of load instructions per stage (IPW; a wave short of real ones repeats
+// one, writing the same bytes again), so vmcnt counts stages.
+template <bool A_MN, int WGM, int WGN, int TM, int TN, int S, bool LIST>
+__device__ __forceinline__ void bf16p_ring(__bf16* ring, const __bf16* Ah, const __bf16* Al, const __bf16* Bh,
+                                           const __bf16* Bl, int64_t sAi, int64_t sAl, int64_t sBj, int64_t sBl,
+                                           int64_t rows_a, int64_t rows_b, int64_t nk, const int16_t* list,
+                                           f32x4 (&acc)[TM][TN]) {
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, NW = WGM * WGN;
+  constexpr int NI = (BM + BN) / 8;  // load instructions per stage: 1 KB each
+  constexpr int IPW = (NI + NW - 1) / NW;
+  constexpr int STAGE = RingSmem<BM, BN, S>::STAGE;
+  static_assert((S - 2) * IPW < 64, "outstanding loads exceed vmcnt");
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w / WGN, wn = w % WGN;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const uint32_t ring_lds = __builtin_amdgcn_readfirstlane(lds_address(ring));
+
+  // per instruction: this lane's source (tile base + chunk offset), the
+  // bytes one K step moves it, and the LDS offset of its 1 KB in a stage
+  const char* gp[IPW];
+  int64_t step[IPW];
+  uint32_t ldso[IPW];
+#pragma unroll
+  for (int i = 0; i < IPW; ++i) {
+    int ig = wu + NW * i;
+    if (NI % NW != 0 && ig >= NI) ig -= NI;
+    ldso[i] = static_cast<uint32_t>(ig) * 1024u;
+    const bool is_a = ig < BM / 8;
+    const bool lo = is_a ? ig >= BM / 16 : ig >= BM / 8 + BN / 16;
+    const int j = is_a ? (lo ? ig - BM / 16 : ig) : (lo ? ig - BM / 8 - BN / 16 : ig - BM / 8);
+    const int sl = 64 * j + lane;  // 16-byte slot within the plane's tile
+    int64_t off;
+    if (is_a && A_MN) {
+      const int l = sl / (BM / 8), c = sl % (BM / 8);
+      const int64_t row = static_cast<int64_t>((c ^ mn_xor<BM>(l)) * 8);
+      const int64_t rr = row < rows_a ? row : ((rows_a - 1) & ~int64_t(7));
+      off = rr * sAi + l * sAl;
+    } else {
+      const int r = sl >> 2, kq = (sl & 3) ^ kswz(sl >> 2);
+      const int64_t rows = is_a ? rows_a : rows_b;
+      const int64_t rr = r < rows ? r : rows - 1;
+      off = rr * (is_a ? sAi : sBj) + kq * 8;
+    }
+    const __bf16* base = is_a ? (lo ? Al : Ah) : (lo ? Bl : Bh);
+    gp[i] = reinterpret_cast<const char*>(base + off);
+    step[i] = static_cast<int64_t>(BK) * (is_a ? sAl : sBl) * 2;
+  }
+  auto issue = [&](int slot, int64_t kt) {
+    const int64_t t = LIST ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[kt])) : kt;
+    const uint32_t sb = ring_lds + static_cast<uint32_t>(slot * STAGE * 2);
+#pragma unroll
+    for (int i = 0; i < IPW; ++i) dma16(gp[i] + t * step[i], sb + ldso[i]);
+  };
+  auto compute = [&](const __bf16* st) {
+    const __bf16* A0 = st;
+    const __bf16* A1 = st + BM * BK;
+    const __bf16* B0 = st + 2 * BM * BK;
+    const __bf16* B1 = B0 + BN * BK;
+    bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int r0 = (wm * TM + a) * 16;
+      if constexpr (A_MN) {
+        ah[a] = frag_mnx<BM>(A0, r0, lane);
+        al[a] = frag_mnx<BM>(A1, r0, lane);
+      } else {
+        ah[a] = frag_k(A0, r0, lane);
+        al[a] = frag_k(A1, r0, lane);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int r0 = (wn * TN + b) * 16;
+      bh[b] = frag_k(B0, r0, lane);
+      bl[b] = frag_k(B1, r0, lane);
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+      }
+  };
+  auto sync = [&](int64_t later) {  // stages issued after the one to read
+    static_assert(S <= 5, "ring_sync cases");
+    if (later >= 3) ring_sync<(S > 4 ? 3 : 0) * IPW>();
+    else if (later == 2) ring_sync<(S > 3 ? 2 : 0) * IPW>();
+    else if (later == 1) ring_sync<IPW>();
+    else ring_sync<0>();
+  };
+
+  if (nk <= 0) return;
+#pragma unroll
+  for (int st = 0; st < S - 1; ++st)
+    if (st < nk) issue(st, st);
+  int slot = 0;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    sync(min(nk - 1 - kt, static_cast<int64_t>(S - 2)));
+    // the slot read in step kt - 1 is free once every wave has passed the barrier
+    if (kt + S - 1 < nk) issue(slot == 0 ? S - 1 : slot - 1, kt + S - 1);
+    compute(ring + slot * STAGE);
+    slot = slot + 1 == S ? 0 : slot + 1;
+  }
+}
+
 // The K loop of one tile.  FULL: every row of both operand tiles is in
 // range (no zero fill).  The loop is unrolled by two so that both staging
 // buffers are compile-time constants.
@@ -257,9 +442,13 @@ __device__ __forceinline__ void bf16p_loop(PSmem<16 * WGM * TM, 16 * WGN * TN, A
 //     64-point block has an active chunk among the tile's AO columns.
 // Skipped steps and tiles hold exact zeros of the AO operand, so every
 // output is a sum of the same non-zero terms as in the dense product.
+template <bool A_MN, int WGM, int WGN, int TM, int TN, int DEPTH>
+using SmemOf = std::conditional_t<(DEPTH >= 3), RingSmem<16 * WGM * TM, 16 * WGN * TN, DEPTH>,
+                                  PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>>;
+
 template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR>
 __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, int z,
-                                           PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>& sm,
+                                           SmemOf<A_MN, WGM, WGN, TM, TN, DEPTH>& sm,
                                            int16_t* s_list, int* s_n) {
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
@@ -275,16 +464,6 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
   const int tid = threadIdx.x;
   const int64_t rows_a = g.M - i0, rows_b = g.N - j0;
 
-  // DEPTH register stages: the global loads of K step k + DEPTH are issued
-  // before the MFMAs of step k, so each load has DEPTH steps of MFMA work to
-  // arrive (DEPTH 2 costs one more operand tile of registers per thread).
-  PTile<BM, NT, A_MN> la[DEPTH];
-  PTile<BN, NT, false> lb[DEPTH];
-#pragma unroll
-  for (int r = 0; r < DEPTH; ++r) {
-    la[r].init(g.sAi, g.sAl, rows_a, tid);
-    lb[r].init(g.sBj, g.sBl, rows_b, tid);
-  }
   f32x4 acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -344,13 +523,28 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
     if (!on) nk = 0;
   }
   constexpr bool LIST = SCR == 2 || SCR == 4;
-  const int64_t stepA = BK * g.sAl, stepB = BK * g.sBl;
-  if (rows_a >= BM && rows_b >= BN)
-    bf16p_loop<A_MN, true, WGM, WGN, TM, TN, DEPTH, LIST>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, s_list,
-                                                          acc);
-  else
-    bf16p_loop<A_MN, false, WGM, WGN, TM, TN, DEPTH, LIST>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, s_list,
-                                                           acc);
+  if constexpr (DEPTH >= 3) {
+    bf16p_ring<A_MN, WGM, WGN, TM, TN, DEPTH, LIST>(sm.ring, Ah, Al, Bh, Bl, g.sAi, g.sAl, g.sBj, g.sBl, rows_a,
+                                                    rows_b, nk, s_list, acc);
+  } else {
+    // DEPTH register stages: the global loads of K step k + DEPTH are issued
+    // before the MFMAs of step k, so each load has DEPTH steps of MFMA work
+    // to arrive (DEPTH 2 costs one more operand tile of registers per thread).
+    PTile<BM, NT, A_MN> la[DEPTH];
+    PTile<BN, NT, false> lb[DEPTH];
+#pragma unroll
+    for (int r = 0; r < DEPTH; ++r) {
+      la[r].init(g.sAi, g.sAl, rows_a, tid);
+      lb[r].init(g.sBj, g.sBl, rows_b, tid);
+    }
+    const int64_t stepA = BK * g.sAl, stepB = BK * g.sBl;
+    if (rows_a >= BM && rows_b >= BN)
+      bf16p_loop<A_MN, true, WGM, WGN, TM, TN, DEPTH, LIST>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk, s_list,
+                                                            acc);
+    else
+      bf16p_loop<A_MN, false, WGM, WGN, TM, TN, DEPTH, LIST>(sm, la, lb, Ah, Al, Bh, Bl, stepA, stepB, nk,
+                                                             s_list, acc);
+  }
 
   // accumulator element r of lane l: row 4 (l / 16) + r, column l % 16
   const int lane = tid & 63, w = tid >> 6;
@@ -372,7 +566,7 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
 
 template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(GemmArgs g, int nM, int nN) {
-  __shared__ __align__(16) PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN> sm;
+  __shared__ __align__(16) SmemOf<A_MN, WGM, WGN, TM, TN, DEPTH> sm;
   __shared__ int16_t s_list[(SCR == 2 || SCR == 4) ? kSparseMaxStages : 1];
   __shared__ int s_n;
   int mt, nt, z;
@@ -386,7 +580,7 @@ template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
 __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmArgs* __restrict__ jobs,
                                                                     const WorkItem* __restrict__ items,
                                                                     int n_items) {
-  __shared__ __align__(16) PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN> sm;
+  __shared__ __align__(16) SmemOf<A_MN, WGM, WGN, TM, TN, DEPTH> sm;
   __shared__ int16_t s_list[1];
   __shared__ int s_n;
   for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
@@ -396,7 +590,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmA
   }
 }
 
-// {WGM, WGN, TM, TN, DEPTH}; the reduction step is always 32.
+// {WGM, WGN, TM, TN, DEPTH}; the reduction step is always 32.  DEPTH 1, 2:
+// register staging; DEPTH >= 3: LDS ring of DEPTH stages.
 #define QMK_BF16P_TILE_LIST(X) \
   X(0, 2, 2, 4, 4, 1)          \
   X(1, 2, 2, 4, 4, 2)          \
@@ -413,12 +608,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmA
   X(12, 1, 2, 5, 5, 1)         \
   X(13, 4, 1, 4, 5, 1)         \
   X(14, 2, 4, 4, 2, 2)         \
-  X(15, 2, 2, 4, 5, 1)
+  X(15, 2, 2, 4, 5, 1)         \
+  X(16, 4, 2, 4, 4, 3)         \
+  X(17, 2, 2, 4, 4, 3)         \
+  X(18, 2, 2, 4, 4, 4)         \
+  X(19, 4, 1, 4, 5, 3)         \
+  X(20, 4, 2, 4, 5, 3)         \
+  X(21, 2, 2, 5, 5, 3)         \
+  X(22, 1, 2, 5, 5, 4)         \
+  X(23, 2, 4, 5, 4, 3)         \
+  X(24, 8, 1, 2, 5, 3)
 
 [[maybe_unused]] constexpr TileCfg kBfpTiles[] = {
 #define QMK_BFP_ENTRY(id, wgm, wgn, tm, tn, depth) {wgm, wgn, tm, tn, BK},
     QMK_BF16P_TILE_LIST(QMK_BFP_ENTRY)
 #undef QMK_BFP_ENTRY
+};
+[[maybe_unused]] constexpr int kBfpDepth[] = {
+#define QMK_BFP_DEPTH(id, wgm, wgn, tm, tn, depth) depth,
+    QMK_BF16P_TILE_LIST(QMK_BFP_DEPTH)
+#undef QMK_BFP_DEPTH
 };
 
 template <bool A_MN, typename TD, int SCR, int WGM, int WGN, int TM, int TN, int DEPTH>
@@ -522,6 +731,7 @@ TileCfg gemm_bf16p_tile(int cfg) { return kBfpTiles[cfg]; }
 size_t gemm_bf16p_tile_lds_bytes(int cfg) {
   const TileCfg& t = kBfpTiles[cfg];
   const int bm = 16 * t.wgm * t.tm, bn = 16 * t.wgn * t.tn;
+  if (kBfpDepth[cfg] >= 3) return static_cast<size_t>(kBfpDepth[cfg]) * (bm + bn) * BK * 4;  // ring
   // the larger of the two staging layouts of A (MN-major for the forward and
   // W^T ao products, K-major for the W C product)
   const size_t a = std::max<size_t>(static_cast<size_t>(BK) * mn_pitch(bm), static_cast<size_t>(bm) * KLD);
