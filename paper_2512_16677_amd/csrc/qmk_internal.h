@@ -129,9 +129,10 @@ struct GemmArgs {
   const void* A2;
   const void* B2;
   // Workgroup -> tile order of the grid launch.  0: the N tiles of one M tile
-  // run back to back on one XCD (A tile reused from that XCD's L2).  1: all
-  // tiles of one batch index z run together on one XCD (split products,
-  // whose z slab of both operands is shared by every tile of that z).
+  // run back to back on one XCD (A tile reused from that XCD's L2).  1: the
+  // tiles of all z in contiguous ranges per XCD, blocked so that the tiles
+  // resident together share both operands (split products, whose z slab of
+  // both operands is shared by every tile of that z; see grid_tile).
   // 2: the M tiles of one N tile run back to back on one XCD (B tile reused;
   // for products with few M tiles and a long N axis).
   int32_t map_slab;
@@ -163,12 +164,25 @@ __device__ __forceinline__ bool grid_tile(const GemmArgs& g, int nM, int nN, int
                                           int& nt, int& z) {
   const int x = bid & 7, j = bid >> 3;
   if (g.map_slab == 1) {
-    const int tiles = nM * nN, nz = g.nbatch * g.nsplit;
-    z = (j / tiles) * 8 + x;
-    const int t = j % tiles;
-    mt = t / nN;
-    nt = t % nN;
-    return z < nz;
+    // The tiles of every z in one list cut into eight contiguous ranges,
+    // one per XCD, so that no XCD idles when there are fewer than eight z.
+    // Within a z the N tiles go in groups of gn and each group visits every
+    // M tile: the ~32 workgroups one XCD holds at a time share both operand
+    // tiles through its L2.
+    const int tiles = nM * nN;
+    const int64_t total = static_cast<int64_t>(tiles) * g.nbatch * g.nsplit;
+    const int64_t per = (total + 7) / 8;
+    const int64_t item = static_cast<int64_t>(x) * per + j;
+    if (j >= per || item >= total) return false;
+    z = static_cast<int>(item / tiles);
+    const int r = static_cast<int>(item - static_cast<int64_t>(z) * tiles);
+    const int gn = min(nN, max(1, (32 + nM - 1) / nM));
+    const int grp = r / (nM * gn), n0 = grp * gn;
+    const int width = min(gn, nN - n0);
+    const int rem = r - grp * nM * gn;
+    mt = rem / width;
+    nt = n0 + rem % width;
+    return true;
   }
   z = blockIdx.y;
   if (g.map_slab == 2) {
@@ -189,7 +203,10 @@ __device__ __forceinline__ bool grid_tile(const GemmArgs& g, int nM, int nN, int
 // Grid of a launch for GemmArgs g and tile counts nM x nN.
 inline dim3 grid_of(const GemmArgs& g, int nM, int nN) {
   const int nz = g.nbatch * g.nsplit;
-  if (g.map_slab == 1) return dim3(8 * nM * nN * ((nz + 7) / 8), 1);
+  if (g.map_slab == 1) {
+    const int64_t total = static_cast<int64_t>(nM) * nN * nz;
+    return dim3(static_cast<unsigned>(8 * ((total + 7) / 8)), 1);
+  }
   if (g.map_slab == 2) return dim3(8 * nM * ((nN + 7) / 8), nz);
   const int gx = nM >= 8 ? 8 * nN * ((nM + 7) / 8) : nM * nN;
   return dim3(gx, nz);
