@@ -70,6 +70,10 @@ def parse():
                     help="walkers in the oracle's one-thread timed sample")
     ap.add_argument("--quick", action="store_true",
                     help="default workload only: skip the batch and 7500-AO workloads of the default line")
+    ap.add_argument("--traffic-summary", nargs=5, metavar=("MODE", "FETCH_DB", "WRITE_DB", "COPY_FETCH_DB",
+                                                            "COPY_WRITE_DB"),
+                    help="no GPU work: summarise rocprofv3 FETCH_SIZE / WRITE_SIZE databases of a medium-workload "
+                         "run in MODE and of a --copy-calibration run into per-class HBM bytes")
     return ap.parse_args()
 
 
@@ -121,6 +125,18 @@ def run_gpu(s, mode: str, steps: int, warmup: int, bits: int, keep_outputs: bool
     ms = (t1 - t0) * 1e3 / steps
     per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
     timing["_step_ms"] = {"min": per[0], "median": per[len(per) // 2], "max": per[-1]}
+    # the same step with AO retention off: the adjoint evaluates the AO
+    # array again instead of reading the forward pass's (not the timed value)
+    ctx.set_ao_retention(False)
+    n_re = max(3, steps // 2)
+    step(0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(n_re):
+        step(i)
+    torch.cuda.synchronize()
+    timing["_recompute_ms"] = (time.perf_counter() - t2) * 1e3 / n_re
+    ctx.set_ao_retention(True)
     outs = None
     if keep_outputs:  # one more (untimed) step on the first coordinate set
         ctx.set_point(r0)
@@ -276,13 +292,23 @@ def cpu_baseline(walkers: int, threads: int = 0):
 
 
 def cpu_model() -> str:
-    """Model name of the host CPU (lscpu, else /proc/cpuinfo), or an empty string."""
+    """Model of the host CPU as lscpu reports it: the model name plus the
+    BIOS model name, family, model and stepping when present (some virtual
+    machines report only a short model name); else /proc/cpuinfo's model
+    name, or an empty string."""
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        f = {}
         for ln in out.splitlines():
-            if ln.strip().startswith("Model name:"):
-                return ln.split(":", 1)[1].strip()
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                f.setdefault(k.strip(), v.strip())
+        if f.get("Model name"):
+            extra = [f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping") if f.get(k)]
+            bios = f.get("BIOS Model name", "")
+            name = f["Model name"] + (f" / BIOS: {bios}" if bios and bios != f["Model name"] else "")
+            return name + (f" ({', '.join(extra)})" if extra else "")
     except (OSError, subprocess.SubprocessError):
         pass
     try:
@@ -806,8 +832,98 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
 
 
+def _counter_rows(db: str, counter: str):
+    """(dispatch id, kernel name, summed counter value) of every dispatch in a
+    rocprofv3 database, in launch order."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select dispatch_id, kernel_name, sum(value) from counters_collection "
+                     "where counter_name = ? group by dispatch_id order by dispatch_id", (counter,)).fetchall()
+    c.close()
+    return rows
+
+
+def _classify(name: str):
+    """Kernel class of a dispatch of the medium step (None: not counted).
+    Products are told apart by their order within a step (forward, G-bar,
+    dC), since G-bar and dC may run the same kernel."""
+    if "ao_vgl" in name:
+        return "ao"
+    if "ao_adjoint" in name:
+        return "ao_adjoint"
+    if "split_w" in name or "f64_to_f32" in name:
+        return "convert"
+    if "gemm" in name:
+        return "product"
+    return None
+
+
+def traffic_summary(mode, fetch_db, write_db, cfetch_db, cwrite_db):
+    """Per-class HBM bytes per launch from counter databases (KiB per dispatch),
+    each counter scaled by what it reads for the 1 GiB copy."""
+    def copy_kib(db, counter):
+        v = [x for _, n, x in _counter_rows(db, counter) if "copyBuffer" in n or "copy" in n.lower()]
+        return sum(v) / len(v)
+    f_scale = (1 << 30) / (copy_kib(cfetch_db, "FETCH_SIZE") * 1024.0)
+    w_scale = (1 << 30) / (copy_kib(cwrite_db, "WRITE_SIZE") * 1024.0)
+    per = {}
+    for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        k = 0
+        for _, name, v in _counter_rows(db, counter):
+            cls = _classify(name)
+            if cls is None:
+                continue
+            if cls == "product":
+                cls = ("mo", "gbar", "dcoef")[k % 3]
+                k += 1
+            per.setdefault(cls, {}).setdefault(counter, []).append((v, name))
+    import synth
+    s = make_workload(512)
+    P, K, N = s.point_num, s.ao_num, s.mo_num
+    # element bytes of the AO array / G-bar / C (bf16 planes: hi + lo), and of W
+    # as the products read it (the medium step passes FP64 W and writes FP64
+    # mo_vgl in every mode; the mixed modes convert W once per call)
+    esz = 8 if mode == "fp64" else 4
+    wsz = 8 if mode == "fp64" else 4
+    ao = 5.0 * K * P * esz
+    algo = {  # operands read once + results written once
+        "ao": ao + 24.0 * P,
+        "mo": ao + K * N * esz + 5.0 * P * N * 8,
+        "gbar": 5.0 * P * N * wsz + K * N * esz + ao,
+        "dcoef": 5.0 * P * N * wsz + ao + N * K * 8.0,
+        "ao_adjoint": ao + 48.0 * P,
+        "convert": 5.0 * P * N * (8 + 4),
+    }
+    lines = []
+    for cls in ("ao", "mo", "gbar", "dcoef", "ao_adjoint", "convert"):
+        if cls not in per or "FETCH_SIZE" not in per[cls] or "WRITE_SIZE" not in per[cls]:
+            continue
+        fk = sum(v for v, _ in per[cls]["FETCH_SIZE"]) / len(per[cls]["FETCH_SIZE"])
+        wk = sum(v for v, _ in per[cls]["WRITE_SIZE"]) / len(per[cls]["WRITE_SIZE"])
+        b = fk * 1024.0 * f_scale + wk * 1024.0 * w_scale
+        kname = per[cls]["FETCH_SIZE"][0][1].split("(")[0][:60]
+        src = sources_digest(cls) if cls in KERNEL_SOURCES else "-"
+        lines.append({"class": cls, "fetch_kib": fk, "write_kib": wk, "bytes": b, "algorithmic": algo[cls],
+                      "ratio": b / algo[cls], "launches": len(per[cls]["FETCH_SIZE"]), "kernel": kname,
+                      "sources": src})
+    print(f"# copy calibration: bytes = FETCH_SIZE x 1024 x {f_scale:.4f}, WRITE_SIZE x 1024 x {w_scale:.4f}")
+    print(f"{'class':12s} {'FETCH KiB':>12s} {'WRITE KiB':>12s} {'HBM bytes':>11s} {'algorithmic':>11s} "
+          f"{'ratio':>6s}  kernel")
+    for d in lines:
+        print(f"{d['class']:12s} {d['fetch_kib']:12.1f} {d['write_kib']:12.1f} {d['bytes']:11.4g} "
+              f"{d['algorithmic']:11.4g} {d['ratio']:6.2f}  {d['kernel']}")
+    print()
+    for d in lines:
+        if d["sources"] != "-":
+            print(f"traffic: mode={mode} class={d['class']} bytes={d['bytes']:.6g} fetch_kib={d['fetch_kib']:.1f} "
+                  f"write_kib={d['write_kib']:.1f} sources={d['sources']}")
+
+
 def main():
     a = parse()
+    if a.traffic_summary:
+        traffic_summary(*a.traffic_summary)
+        return
     if a.copy_calibration:
         copy_calibration()
         return
@@ -877,6 +993,7 @@ def main():
                                 "dL/dR_elec and dL/dR_nucl"},
         "roofline": roof,
         "step_ms_spread": timing.get("_step_ms"),
+        "ao_recompute_ms_per_step": timing.get("_recompute_ms"),
     }
     variants = {}
     for m in variants_list:
@@ -885,6 +1002,7 @@ def main():
         kv = kernel_roofline(s, m, vt)
         variants[m] = {"value": s.point_num / (vms * 1e-3), "unit": "e-evals/s", "ms_per_step": vms,
                        "step_ms_spread": vt.get("_step_ms"),
+                       "ao_recompute_ms_per_step": vt.get("_recompute_ms"),
                        "speedup_vs_primary": ms / vms, "bits": a.mixed_bits,
                        "mo_gemm_frac_of_peak": (kv["mo"]["TFLOPs"] * (3 if m == "mixed_bf16x3" else 1) / peak_v)
                        if "mo" in kv else None,

@@ -271,8 +271,10 @@ qmk_status qmk_get_screening_density(qmk_ctx ctx, double* active_fraction);
  *   det  device FP64 [batch]
  *   adj  device FP64 [batch][n][n], adj(A) = transpose of the cofactor matrix
  * 1 <= n <= 4: explicit cofactors (exact also for singular matrices).
- * 5 <= n <= 32: LU with partial pivoting, adj = det * A^{-1}; a singular
- * matrix gives det = 0 and a non-finite adjugate.  batch = 0 does nothing
+ * 5 <= n <= 32: LU with partial pivoting, adj = det * A^{-1}; when the
+ * factorisation meets an exactly zero pivot, det = 0 and the adjugate is
+ * the rank-one cofactor matrix built from the null vectors of the
+ * triangular factor (one zero pivot) or zero (two or more).  batch = 0 does nothing
  * (the pointers may then be NULL).  Runs on the context's device and the
  * given stream; uses no other context state. */
 qmk_status qmk_det_adj(qmk_ctx ctx, int64_t n, int64_t batch, const double* a, double* det, double* adj,
@@ -307,10 +309,26 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
  *   d_elec  [walk][elec][3] device FP64, dL/dr      (or NULL)
  *   d_nucl  [nucl][3]   device FP64, dL/dR_nucleus  (or NULL)
  * Outputs are overwritten (not accumulated).  AO derivatives up to third
- * order are recomputed from the coordinates, never stored.  Deterministic:
- * the same inputs give bitwise the same outputs. */
+ * order (for d_elec and d_nucl) are recomputed from the coordinates, never
+ * stored.  d_coef needs the AO values themselves: by default the product
+ * reads the AO array that the forward pass left for the same points
+ * (Section 2.2: a value is kept until one of its inputs changes); see
+ * qmk_set_ao_retention.  Deterministic: the same inputs give bitwise the
+ * same outputs. */
 qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, double* d_coef,
                               double* d_elec, double* d_nucl, void* hip_stream);
+
+/* AO values in the adjoint (Section 2.2 keeps a computed value until its
+ * inputs change; the differentiation pattern may instead evaluate the AO
+ * values again in the backward pass):
+ *   retain = 1 (default): the dC product of qmk_mo_vgl_adjoint reads the AO
+ *            array of the last forward pass when the points are unchanged;
+ *   retain = 0: qmk_mo_vgl_adjoint evaluates the AO array again (one more AO
+ *            kernel launch; with screening on, the point sort and activity
+ *            bitmap too).
+ * The outputs are bitwise the same either way.  QMK_INVALID_ARG_BASE + 2 for
+ * any other value. */
+qmk_status qmk_set_ao_retention(qmk_ctx ctx, int32_t retain);
 
 /* Number of kernel launches issued by the context so far (for tests of the
  * time-stamp logic). */

@@ -49,7 +49,7 @@ EXPORTED = [
     "qmk_get_mo_value", "qmk_get_density", "qmk_set_mo_cusp", "qmk_set_screening",
     "qmk_get_screening_density", "qmk_det_adj", "qmk_jastrow_een_terms", "qmk_jastrow_een",
     "qmk_mo_vgl_adjoint", "qmk_get_launch_count", "qmk_set_timing", "qmk_get_timing",
-    "qmk_get_tile_count", "qmk_set_tile",
+    "qmk_get_tile_count", "qmk_set_tile", "qmk_set_ao_retention",
     "qmk_batch_create", "qmk_batch_destroy", "qmk_batch_last_error", "qmk_batch_run",
 ]
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "qmk_get_density": ([P, P, I64, P, I64, P], I32),
         "qmk_set_mo_cusp": ([P, I64, P, P], I32),
         "qmk_set_screening": ([P, I32], I32),
+        "qmk_set_ao_retention": ([P, I32], I32),
         "qmk_get_screening_density": ([P, P], I32),
         "qmk_det_adj": ([P, I64, I64, P, P, P, P], I32),
         "qmk_jastrow_een_terms": ([I64, P], I32),
@@ -347,6 +348,12 @@ class Context:
         """Screened (block-sparse) forward contraction on or off."""
         self._cfg_version += 1
         self._check(self._lib.qmk_set_screening(self._h, 1 if enable else 0))
+
+    def set_ao_retention(self, retain: bool = True):
+        """Whether the adjoint's dC product reads the forward pass's AO array of
+        the same points (True, the default) or evaluates the AO values again
+        (False); the outputs are the same either way."""
+        self._check(self._lib.qmk_set_ao_retention(self._h, 1 if retain else 0))
 
     def screening_density(self) -> float:
         """Fraction of (64-point block, 16-AO chunk) pairs with a non-zero AO

@@ -350,14 +350,15 @@ qmk_status check_ready(qmk_ctx ctx, bool need_coef) {
   return QMK_OK;
 }
 
-// provide(ao_vgl): recompute the AO array iff its time stamp is stale.
-qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
+// provide(ao_vgl): recompute the AO array iff its time stamp is stale (or
+// `force`: the adjoint with AO retention off).
+qmk_status provide_ao(qmk_ctx ctx, hipStream_t s, bool force = false) {
   qmk_status st = ensure_tables(ctx);
   if (st != QMK_OK) return st;
   // 0: FP64; 1: FP32; 2: bf16 hi and lo planes (BF16x3 mode), same bytes as FP32
   const int f32 = ctx->ao_format();
   const int64_t Pp = round_up(ctx->P(), kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
-  if (ctx->ao_date == ctx->date && ctx->ao_f32 == f32 && ctx->ao_Pp == Pp && ctx->ao_Kp == Kp)
+  if (!force && ctx->ao_date == ctx->date && ctx->ao_f32 == f32 && ctx->ao_Pp == Pp && ctx->ao_Kp == Kp)
     return QMK_OK;
   if (ctx->ao_Pp != Pp || ctx->ao_Kp != Kp || ctx->ao_f32 != f32 || !ctx->ao.p) {
     const size_t bytes = static_cast<size_t>(Kp * 5 * Pp) * (f32 ? 4 : 8);
@@ -382,12 +383,12 @@ qmk_status provide_ao(qmk_ctx ctx, hipStream_t s) {
 // Tile for one product: forced by qmk_set_tile, else the autotuner's choice.
 // Screened contraction input: the points sorted by nearest nucleus, the AO
 // array in that order and the (64-point block, 16-AO chunk) activity bitmap.
-qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s) {
+qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
   qmk_status st = ensure_tables(ctx);
   if (st != QMK_OK) return st;
   const int f32 = ctx->ao_format();  // 0 FP64, 1 FP32, 2 bf16 hi and lo planes
   const int64_t P = ctx->P(), Pp = round_up(P, kPointPad), Kp = round_up(ctx->ao_num, kAoPad);
-  if (ctx->aos_date == ctx->date && ctx->aos_f32 == f32 && ctx->aos_Pp == Pp && ctx->aos_Kp == Kp)
+  if (!force && ctx->aos_date == ctx->date && ctx->aos_f32 == f32 && ctx->aos_Pp == Pp && ctx->aos_Kp == Kp)
     return QMK_OK;
   const int64_t nn = ctx->nucl_num;
   if (ctx->nuc_xyz_version != ctx->geom_version) {
@@ -1163,6 +1164,13 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
   return QMK_OK;
 }
 
+qmk_status qmk_set_ao_retention(qmk_ctx ctx, int32_t retain) {
+  QMK_CHECK_CTX(ctx);
+  if (retain != 0 && retain != 1) return bad_arg(ctx, 2, "retain must be 0 or 1");
+  ctx->ao_retain = retain == 1;
+  return QMK_OK;
+}
+
 qmk_status qmk_set_screening(qmk_ctx ctx, int32_t enable) {
   QMK_CHECK_CTX(ctx);
   if (enable != 0 && enable != 1) return bad_arg(ctx, 2, "enable must be 0 or 1");
@@ -1554,7 +1562,11 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   if ((st = ensure_coef(ctx)) != QMK_OK) return st;
   // screened adjoint: every product in sorted point order (Section 3.2)
   const bool scr = ctx->sparse;
-  if ((st = scr ? provide_ao_sorted(ctx, s) : provide_ao(ctx, s)) != QMK_OK) return st;
+  // dC reads the AO values: by default the forward pass's array of the same
+  // points (memoised, as the provide scheme keeps any value whose inputs are
+  // unchanged); with retention off they are evaluated again here
+  const bool again = !ctx->ao_retain;
+  if ((st = scr ? provide_ao_sorted(ctx, s, again) : provide_ao(ctx, s, again)) != QMK_OK) return st;
   const int64_t P = ctx->P(), N = ctx->mo_num, K = ctx->ao_num;
   const int64_t Pp = scr ? ctx->aos_Pp : ctx->ao_Pp, Kp = ctx->Kp, Np = ctx->Np;
   const void* ao_arr = scr ? ctx->aos.p : ctx->ao.p;

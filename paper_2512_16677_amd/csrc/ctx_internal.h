@@ -106,6 +106,9 @@ struct qmk_ctx_s {
   DevBuf ao;
   int64_t ao_Pp = 0, ao_Kp = 0, ao_date = -1;
   int ao_f32 = -1;
+  // the adjoint's dC product reads the forward's AO array of the same points
+  // (true) or evaluates the AO values again (false; qmk_set_ao_retention)
+  bool ao_retain = true;
 
   // AO values only [Kp][Pp], valid at aov_date (used when the full AO array
   // is stale for the current points)

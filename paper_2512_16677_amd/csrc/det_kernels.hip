@@ -101,6 +101,7 @@ __global__ __launch_bounds__(256) void det_adj_lu_kernel(const double* __restric
                                                          double* __restrict__ adj) {
   __shared__ double s_lu[4][32][33];
   __shared__ int s_piv[4][32];
+  __shared__ double s_a[4][32], s_r[4][32];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t b = static_cast<int64_t>(blockIdx.x) * 4 + w;
   if (b >= batch) return;  // whole waves leave together; no workgroup barrier below
@@ -139,7 +140,8 @@ __global__ __launch_bounds__(256) void det_adj_lu_kernel(const double* __restric
     const double piv = lu[k][k];
     d *= piv;
     if (lane > k && lane < n) {
-      const double l = lu[lane][k] / piv;
+      // a zero pivot leaves only zeros below it: nothing to eliminate
+      const double l = piv != 0.0 ? lu[lane][k] / piv : 0.0;
       lu[lane][k] = l;
       for (int j = k + 1; j < n; ++j) lu[lane][j] -= l * lu[k][j];
     }
@@ -149,6 +151,67 @@ __global__ __launch_bounds__(256) void det_adj_lu_kernel(const double* __restric
   }
   d *= sign;
   if (lane == 0) det[b] = d;
+  // Exactly zero pivots make d A^{-1} undefined; the adjugate is still the
+  // transposed cofactor matrix.  With PA = LU, adj(A) = adj(U) L^{-1} sign P.
+  // Two or more zero pivots (rank <= n - 2): adj(A) = 0.  One, at k0 (rank
+  // n - 1): adj(U) = c a b^T with c = prod_{m != k0} u_mm (the (k0, k0)
+  // cofactor), U a = 0, a_k0 = 1, a_m = 0 past k0, and b^T U = 0, b_k0 = 1,
+  // b_m = 0 before k0; so adj(A) = sign c a r^T with r = P^T L^{-T} b.
+  int nzero = 0, k0 = -1;
+  for (int m = 0; m < n; ++m)
+    if (lu[m][m] == 0.0) {
+      ++nzero;
+      k0 = m;
+    }
+  if (nzero > 0) {
+    double* dst = adj + b * n * n;
+    if (nzero >= 2) {
+      for (int e = lane; e < n * n; e += 64) dst[e] = 0.0;
+      return;
+    }
+    if (lane == 0) {
+      double c = sign;
+      for (int m = 0; m < n; ++m)
+        if (m != k0) c *= lu[m][m];
+      double* a = s_a[w];
+      double* r = s_r[w];
+      for (int m = n - 1; m >= 0; --m) {
+        if (m >= k0) {
+          a[m] = m == k0 ? 1.0 : 0.0;
+        } else {
+          double t = 0.0;
+          for (int q = m + 1; q <= k0; ++q) t += lu[m][q] * a[q];
+          a[m] = -t / lu[m][m];
+        }
+      }
+      // b into r, then z = L^{-T} b in place (L unit lower, below the diagonal of lu)
+      for (int j = 0; j < n; ++j) {
+        if (j <= k0) {
+          r[j] = j == k0 ? 1.0 : 0.0;
+        } else {
+          double t = 0.0;
+          for (int q = k0; q < j; ++q) t += r[q] * lu[q][j];
+          r[j] = -t / lu[j][j];
+        }
+      }
+      for (int i = n - 1; i >= 0; --i)
+        for (int j = i + 1; j < n; ++j) r[i] -= lu[j][i] * r[j];
+      // r = P^T z: the row swaps undone in reverse order
+      for (int k = n - 1; k >= 0; --k) {
+        const int p = s_piv[w][k];
+        const double t = r[k];
+        r[k] = r[p];
+        r[p] = t;
+      }
+      for (int m = 0; m < n; ++m) a[m] *= c;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < n)
+      for (int i = 0; i < n; ++i) dst[i * n + lane] = s_a[w][i] * s_r[w][lane];
+    return;
+  }
   // column `lane` of A^{-1}: solve L U x = P e_lane
   if (lane < n) {
     double x[32];

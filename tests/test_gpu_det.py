@@ -50,6 +50,32 @@ def test_lu_path_matches_oracle(n):
     assert np.abs(g - radj).max() <= 1e-11 * np.abs(radj).max()
 
 
+@pytest.mark.parametrize("n", [5, 8, 16, 32])
+def test_lu_path_singular_matrices_match_cofactors(n):
+    """Exactly singular matrices on the LU path (a repeated row, a zero
+    column: rank n - 1; two zero rows: rank n - 2): det is 0 and the adjugate
+    is the oracle's transposed cofactor matrix, finite, within 1e-10 of its
+    largest entry (zero for rank n - 2)."""
+    rng = np.random.default_rng(300 + n)
+    a = rng.normal(size=(12, n, n))
+    a[0:4, 3] = a[0:4, 1]          # repeated row
+    a[4:8, :, 2] = 0.0             # zero column
+    a[8:12, 0] = 0.0               # two zero rows
+    a[8:12, n - 1] = 0.0
+    c = ctx()
+    det, adj = c.det_adj(torch.from_numpy(a).cuda())
+    c.close()
+    det = det.cpu().numpy()
+    g = adj.cpu().numpy()
+    rdet, radj = oracle.det_adj(a)
+    assert np.all(det == 0.0), det
+    assert np.all(np.isfinite(g))
+    for b in range(8):
+        assert np.abs(g[b] - radj[b]).max() <= 1e-10 * np.abs(radj[b]).max(), b
+    assert np.all(g[8:] == 0.0)
+    assert np.abs(radj[8:]).max() <= 1e-12 * np.abs(radj[:8]).max()
+
+
 def test_det_errors_and_empty_batch():
     import paper_2512_16677_amd as q
     c = ctx()

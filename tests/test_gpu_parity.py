@@ -137,6 +137,37 @@ def test_time_stamps_recompute_only_when_points_change():
     assert rownorm_err(mo.reshape(-1, 5, s.mo_num), ref).max() <= TOL
 
 
+@pytest.mark.parametrize("mode,screened", [("fp64", False), ("fp64", True), ("mixed_bf16x3", False),
+                                           ("mixed_bf16x3", True)])
+def test_ao_retention_off_recomputes_and_matches(mode, screened):
+    """With AO retention off the adjoint evaluates the AO array again (one
+    more AO launch, or sort + bitmap + AO launches when screened) and its
+    outputs are bitwise those of the default (retained) adjoint."""
+    q = qmk()
+    s = synth.medium(walkers=2)
+    ctx = q.Context.from_system(s, bits=53 if mode == "fp64" else 24, mode=mode)
+    ctx.set_screening(screened)
+    w = torch.from_numpy(synth.adjoint_weights(s, seed=8)).cuda()
+    if mode != "fp64":
+        w = w.float()
+    ctx.get_mo_vgl()
+    g_keep = {k: v.clone() for k, v in ctx.adjoint(w).items()}
+    n_keep = ctx.launch_count()
+    ctx.adjoint(w)
+    per_keep = ctx.launch_count() - n_keep
+    ctx.set_ao_retention(False)
+    n0 = ctx.launch_count()
+    g_again = ctx.adjoint(w)
+    per_again = ctx.launch_count() - n0
+    assert per_again > per_keep, (per_again, per_keep)
+    for k in ("d_coef", "d_elec", "d_nucl"):
+        assert bool((g_again[k] == g_keep[k]).all()), k
+    with pytest.raises(q.QmkError) as e:
+        ctx._check(ctx._lib.qmk_set_ao_retention(ctx._h, 2))
+    assert e.value.status == q.QMK_INVALID_ARG_BASE + 2
+    ctx.close()
+
+
 def test_error_codes():
     q = qmk()
     ctx = q.Context()
