@@ -70,6 +70,9 @@ def parse():
                     help="walkers in the oracle's one-thread timed sample")
     ap.add_argument("--quick", action="store_true",
                     help="default workload only: skip the batch and 7500-AO workloads of the default line")
+    ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
+                    help="no GPU work: MODE DB [DB ...]: sums of every counter of rocprofv3 databases of a "
+                         "medium-workload run per product class (forward, G-bar, dL/dC), with derived ratios")
     ap.add_argument("--traffic-summary", nargs=5, metavar=("MODE", "FETCH_DB", "WRITE_DB", "COPY_FETCH_DB",
                                                             "COPY_WRITE_DB"),
                     help="no GPU work: summarise rocprofv3 FETCH_SIZE / WRITE_SIZE databases of a medium-workload "
@@ -858,6 +861,44 @@ def _classify(name: str):
     return None
 
 
+def counter_summary(mode, *dbs):
+    """Per product class (forward, G-bar, dL/dC, in launch order within a
+    step), the sum over its dispatches of every counter in the databases."""
+    import sqlite3
+    tot = {}
+    for db in dbs:
+        c = sqlite3.connect(db)
+        names = [r[0] for r in c.execute("select distinct counter_name from counters_collection")]
+        c.close()
+        for counter in names:
+            k = 0
+            for _, name, v in _counter_rows(db, counter):
+                if _classify(name) != "product":
+                    continue
+                cls = ("mo", "gbar", "dcoef")[k % 3]
+                k += 1
+                tot.setdefault(cls, {}).setdefault(counter, 0.0)
+                tot[cls][counter] += v
+    print(f"mode {mode}: counter sums over the dispatches of each product class")
+    for cls in ("mo", "gbar", "dcoef"):
+        if cls not in tot:
+            continue
+        t = tot[cls]
+        print(f"\n{cls}:")
+        for k in sorted(t):
+            print(f"    {k:28s} {t[k]:.4g}")
+        if t.get("SQ_INSTS_MFMA"):
+            if "SQ_INSTS_VALU" in t:
+                print(f"    {'VALU instructions per MFMA':28s} {t['SQ_INSTS_VALU'] / t['SQ_INSTS_MFMA']:.2f}")
+            if "SQ_INSTS_LDS" in t:
+                print(f"    {'LDS instructions per MFMA':28s} {t['SQ_INSTS_LDS'] / t['SQ_INSTS_MFMA']:.2f}")
+        if t.get("SQ_WAVE_CYCLES") and "SQ_WAIT_ANY" in t:
+            print(f"    {'SQ_WAIT_ANY / SQ_WAVE_CYCLES':28s} {t['SQ_WAIT_ANY'] / t['SQ_WAVE_CYCLES']:.2f}")
+        if t.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in t:
+            print(f"    {'LDS conflict cycles per LDS instruction':28s} "
+                  f"{t['SQ_LDS_BANK_CONFLICT'] / t['SQ_INSTS_LDS']:.2f}")
+
+
 def traffic_summary(mode, fetch_db, write_db, cfetch_db, cwrite_db):
     """Per-class HBM bytes per launch from counter databases (KiB per dispatch),
     each counter scaled by what it reads for the 1 GiB copy."""
@@ -923,6 +964,9 @@ def main():
     a = parse()
     if a.traffic_summary:
         traffic_summary(*a.traffic_summary)
+        return
+    if a.counter_summary:
+        counter_summary(*a.counter_summary)
         return
     if a.copy_calibration:
         copy_calibration()
