@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
                     help="no GPU work: MODE DB [DB ...]: sums of every counter of rocprofv3 databases of a "
                          "medium-workload run per product class (forward, G-bar, dL/dC), with derived ratios")
+    ap.add_argument("--kernel-counter-summary", nargs="+", metavar="DB",
+                    help="no GPU work: per kernel name, dispatch count and mean per dispatch of every counter "
+                         "of rocprofv3 databases")
     ap.add_argument("--traffic-summary", nargs=5, metavar=("MODE", "FETCH_DB", "WRITE_DB", "COPY_FETCH_DB",
                                                             "COPY_WRITE_DB"),
                     help="no GPU work: summarise rocprofv3 FETCH_SIZE / WRITE_SIZE databases of a medium-workload "
@@ -861,6 +864,20 @@ def _classify(name: str):
     return None
 
 
+def kernel_counter_summary(*dbs):
+    """Per kernel name: dispatches and the mean per dispatch of each counter."""
+    import sqlite3
+    for db in dbs:
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, counter_name, count(distinct dispatch_id), sum(value) "
+                         "from counters_collection group by kernel_name, counter_name").fetchall()
+        c.close()
+        print(f"# {db}")
+        print(f"{'dispatches':>10s} {'counter':14s} {'mean per dispatch':>18s}  kernel")
+        for name, counter, n, tot in sorted(rows, key=lambda r: -r[3]):
+            print(f"{n:10d} {counter:14s} {tot / n:18.1f}  {name[:150]}")
+
+
 def counter_summary(mode, *dbs):
     """Per product class (forward, G-bar, dL/dC, in launch order within a
     step), the sum over its dispatches of every counter in the databases."""
@@ -967,6 +984,9 @@ def main():
         return
     if a.counter_summary:
         counter_summary(*a.counter_summary)
+        return
+    if a.kernel_counter_summary:
+        kernel_counter_summary(*a.kernel_counter_summary)
         return
     if a.copy_calibration:
         copy_calibration()

@@ -151,7 +151,7 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
   for (int a = 0; a < nn; ++a) {
     const NucDev nu = s_nuc[a];
     const double dx = rx - nu.x, dy = ry - nu.y, dz = rz - nu.z;
-    const double u = dx * dx + dy * dy + dz * dz;
+    const double u = dist2(dx, dy, dz);
     const bool near = valid && (nu.gmin * u < T);
     double tx = 0.0, ty = 0.0, tz = 0.0;
     if (__any(near)) {

@@ -135,7 +135,16 @@ __device__ __forceinline__ void shell_zero(int l, OutT* __restrict__ o, int64_t 
   }
 }
 
-template <typename OutT, bool VAL>
+// SCR = 0: dense.  SCR = 1: activity pass of the screened evaluation: marks
+// in out.act the 16-AO chunks in which some point of the wave's 64-point
+// block has a primitive inside the cutoff (the first, smallest exponent
+// decides, as in the radial sums) and stores nothing.  SCR = 2: screened
+// store: a shell whose chunks are all inactive is neither evaluated nor
+// stored, unless one of them was active in the previous evaluation into the
+// same array (out.act_prev), in which case it is stored as zeros.  So every
+// inactive chunk of the array holds zeros without being written again, and
+// an active chunk holds all of its values.
+template <typename OutT, bool VAL, int SCR = 0>
 __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& pts,
                                             const AoOut& out, int bx, int gy,
                                             unsigned char* smem) {
@@ -167,9 +176,24 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
   for (int a = 0; a < nn; ++a) {
     const NucDev nu = s_nuc[a];
     const double dx = rx - nu.x, dy = ry - nu.y, dz = rz - nu.z;
-    const double u = dx * dx + dy * dy + dz * dz;
+    const double u = dist2(dx, dy, dz);
     const bool near = valid && (nu.gmin * u < T);
-    if (!__any(near)) {
+    if constexpr (SCR == 1) {
+      if (!__any(near)) continue;
+      for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
+        const ShellDev sh = s_shell[s];
+        const bool on0 = near && sh.p_begin < sh.p_end && (s_prim[sh.p_begin].gamma * u < T);
+        if (__any(on0) && (threadIdx.x & 63) == 0) {
+          uint32_t* const w = out.act + (p >> 6) * out.act_words;
+          const int c0 = sh.ao_off / kSparseChunk;
+          const int c1 = (sh.ao_off + (sh.l + 1) * (sh.l + 2) / 2 - 1) / kSparseChunk;
+          for (int c = c0; c <= c1; ++c) atomicOr(w + (c >> 5), 1u << (c & 31));
+        }
+      }
+      continue;
+    }
+    const bool any_near = __any(near);
+    if (SCR == 0 && !any_near) {
       for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
         const ShellDev sh = s_shell[s];
         shell_zero<OutT, VAL>(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, out.plane, valid || kPairs);
@@ -178,27 +202,34 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
     }
     for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
       const ShellDev sh = s_shell[s];
+      if constexpr (SCR == 2) {
+        // the wave's block: chunks of this shell active now, or before
+        const int64_t blk = (static_cast<int64_t>(bx) * blockDim.x + (threadIdx.x & ~63)) >> 6;
+        const int c0 = sh.ao_off / kSparseChunk;
+        const int c1 = (sh.ao_off + (sh.l + 1) * (sh.l + 2) / 2 - 1) / kSparseChunk;
+        bool now = false, was = false;
+        for (int c = c0; c <= c1; ++c) {
+          now = now || ((out.act[blk * out.act_words + (c >> 5)] >> (c & 31)) & 1u);
+          was = was || ((out.act_prev[blk * out.act_words + (c >> 5)] >> (c & 31)) & 1u);
+        }
+        if (!now || !any_near) {
+          if (now || was)
+            shell_zero<OutT, VAL>(sh.l, obase + sh.ao_off * out.sK, out.sK, out.sC, out.plane, valid || kPairs);
+          continue;
+        }
+      }
       double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-      bool any_on = false;
       for (int k = sh.p_begin; k < sh.p_end; ++k) {
         const PrimDev pr = s_prim[k];
         const double x = pr.gamma * u;
         const bool on = near && (x < T);
         if (!__any(on)) break;  // ascending exponents: every later one is cut too
-        any_on = true;
         if (on) {
           const double e = pr.coef * exp(-x);
           g0 += e;
           g1 -= pr.gamma * e;
           g2 += pr.gamma * pr.gamma * e;
         }
-      }
-      if (out.act && any_on && (threadIdx.x & 63) == 0) {
-        // this wave's block has non-zero AOs in the shell's chunks
-        uint32_t* const w = out.act + (p >> 6) * out.act_words;
-        const int c0 = sh.ao_off / kSparseChunk;
-        const int c1 = (sh.ao_off + (sh.l + 1) * (sh.l + 2) / 2 - 1) / kSparseChunk;
-        for (int c = c0; c <= c1; ++c) atomicOr(w + (c >> 5), 1u << (c & 31));
       }
       // (the split-plane store needs both lanes of every pair: lanes past the
       // last point store the zeros their empty sums give)
@@ -214,10 +245,10 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
   }
 }
 
-template <typename OutT, bool VAL>
+template <typename OutT, bool VAL, int SCR = 0>
 __global__ __launch_bounds__(256, 4) void ao_vgl_kernel(AoTables t, PointArgs pts, AoOut out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  ao_vgl_body<OutT, VAL>(t, pts, out, blockIdx.x, blockIdx.y, smem);
+  ao_vgl_body<OutT, VAL, SCR>(t, pts, out, blockIdx.x, blockIdx.y, smem);
 }
 
 // Persistent form: the grid walks a list of (molecule, point block, group).
@@ -268,6 +299,24 @@ hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& o
     hipLaunchKernelGGL((ao_vgl_kernel<float, false>), grid, dim3(256), smem, s, t, pts, out);
   else
     hipLaunchKernelGGL((ao_vgl_kernel<double, false>), grid, dim3(256), smem, s, t, pts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ao_vgl_screened(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
+                                  hipStream_t s) {
+  if (pts.P <= 0 || t.n_groups <= 0) return hipSuccess;
+  if (!out.act || !out.act_prev) return hipErrorInvalidValue;
+  const size_t smem = static_cast<size_t>(t.smem_bytes);
+  dim3 grid(static_cast<unsigned>((pts.P + 255) / 256), static_cast<unsigned>(t.n_groups));
+  // activity first: a chunk's bit may come from a shell of another nucleus
+  // group, so the stores of the second pass need the whole bitmap
+  hipLaunchKernelGGL((ao_vgl_kernel<double, false, 1>), grid, dim3(256), smem, s, t, pts, out);
+  if (out_is_f32 == 2)
+    hipLaunchKernelGGL((ao_vgl_kernel<Bf16Pair, false, 2>), grid, dim3(256), smem, s, t, pts, out);
+  else if (out_is_f32)
+    hipLaunchKernelGGL((ao_vgl_kernel<float, false, 2>), grid, dim3(256), smem, s, t, pts, out);
+  else
+    hipLaunchKernelGGL((ao_vgl_kernel<double, false, 2>), grid, dim3(256), smem, s, t, pts, out);
   return hipGetLastError();
 }
 

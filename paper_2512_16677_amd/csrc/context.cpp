@@ -405,8 +405,14 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
   QMK_HIP(ctx, ctx->d_sort_scratch.ensure(scratch), "alloc sort scratch");
   ctx->act_words = (Kp / kSparseChunk + 31) / 32;
   const int64_t act_n = (Pp / 64) * ctx->act_words;
+  // the previous evaluation's bitmap tells which chunks of the array still
+  // hold non-zeros (the store pass writes no inactive chunk otherwise)
+  std::swap(ctx->d_act.p, ctx->d_act_prev.p);
+  std::swap(ctx->d_act.bytes, ctx->d_act_prev.bytes);
   QMK_HIP(ctx, ctx->d_act.ensure(static_cast<size_t>(act_n) * 4), "alloc activity bitmap");
-  if (ctx->aos_Pp != Pp || ctx->aos_Kp != Kp || ctx->aos_f32 != f32 || !ctx->aos.p) {
+  const bool fresh = ctx->aos_Pp != Pp || ctx->aos_Kp != Kp || ctx->aos_f32 != f32 || !ctx->aos.p ||
+                     ctx->d_act_prev.bytes < static_cast<size_t>(act_n) * 4;
+  if (fresh) {
     const size_t bytes = static_cast<size_t>(Kp * 5 * Pp) * (f32 ? 4 : 8);
     ctx->aos.release();
     QMK_HIP(ctx, ctx->aos.ensure(bytes), "alloc sorted AO array");
@@ -414,6 +420,9 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
     ctx->aos_Pp = Pp;
     ctx->aos_Kp = Kp;
     ctx->aos_f32 = f32;
+    // an all-zero array: no chunk was active before
+    QMK_HIP(ctx, ctx->d_act_prev.ensure(static_cast<size_t>(act_n) * 4), "alloc activity bitmap");
+    QMK_HIP(ctx, launch_fill_u32(ctx->d_act_prev.as<uint32_t>(), act_n, 0u, s), "clear activity bitmap");
   }
   PointArgs pa = point_args(ctx);
   {
@@ -425,11 +434,11 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
     QMK_HIP(ctx, launch_fill_u32(ctx->d_act.as<uint32_t>(), act_n, 0u, s), "clear activity bitmap");
   }
   pa.perm = ctx->d_perm.as<int32_t>();
-  AoOut o{ctx->aos.p, 5 * Pp, Pp, 1, ctx->d_act.as<uint32_t>(), ctx->act_words};
+  AoOut o{ctx->aos.p, 5 * Pp, Pp, 1, ctx->d_act.as<uint32_t>(), ctx->act_words, ctx->d_act_prev.as<uint32_t>()};
   o.plane = Kp * 5 * Pp;
   {
     LaunchTimer lt(ctx, QMK_KERNEL_AO, s);
-    QMK_HIP(ctx, launch_ao_vgl(ctx->tab, pa, o, f32, f32, s), "AO kernel (sorted points)");
+    QMK_HIP(ctx, launch_ao_vgl_screened(ctx->tab, pa, o, f32, s), "AO kernel (sorted points)");
   }
   ctx->aos_date = ctx->date;
   return QMK_OK;

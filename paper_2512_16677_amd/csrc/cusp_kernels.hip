@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void cusp_apply_kernel(CuspArgs c, PointArgs p
     const double dx = pts.coord[q * pts.s_pt] - nu.x;
     const double dy = pts.coord[q * pts.s_pt + pts.s_ax] - nu.y;
     const double dz = pts.coord[q * pts.s_pt + 2 * pts.s_ax] - nu.z;
-    const double u = dx * dx + dy * dy + dz * dz;
+    const double u = dist2(dx, dy, dz);
     const double r = sqrt(u);
     const double ir = 1.0 / r;  // a point exactly on the nucleus: the cusp diverges
     const int ns = nu.s_end - nu.s_begin;

@@ -73,14 +73,24 @@ struct PointArgs {
   const int32_t* perm;      // AO kernel only: point p reads coordinates perm[p] (NULL: p)
 };
 
+// Squared point-nucleus distance with one fixed rounding sequence, so that
+// every kernel that screens on it (AO values, their activity bitmap, the
+// adjoint, the cusp correction's s part) takes the same decisions.
+__device__ __forceinline__ double dist2(double dx, double dy, double dz) {
+  return __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+}
+
 // Strided AO output: element (k, c, p) at out[k*sK + c*sC + p*sP].
 struct AoOut {
   void* out;
   int64_t sK, sC, sP;
-  // when non-NULL: bit c of act[(p/64)*act_words + c/32] is set if any point
-  // of the 64-point block of p has a non-zero AO in chunk c (16 AOs)
+  // screened (sorted-point) evaluation: bit c of act[(p/64)*act_words + c/32]
+  // is set if any point of the 64-point block of p has a non-zero AO in chunk
+  // c (16 AOs); act_prev is the bitmap of the previous evaluation into the
+  // same array (see launch_ao_vgl_screened)
   uint32_t* act;
   int64_t act_words;
+  const uint32_t* act_prev;
   // split bf16 output (launch_ao_vgl with out_is_f32 = 2): elements from the
   // hi plane at `out` to the lo plane; P must be padded to a multiple of 256
   // and every point offset even
@@ -235,6 +245,14 @@ enum class Prec { kF64 = 0, kF32 = 1, kBF16P = 3 };
 // out_is_f32: 0 FP64, 1 FP32, 2 split bf16 planes (hi, lo; see AoOut::plane).
 hipError_t launch_ao_vgl(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                          int fp32_compute, hipStream_t s);
+// Screened evaluation of sorted points into an array that the previous
+// screened evaluation (bitmap out.act_prev) left with zeros in all of its
+// inactive chunks: an activity pass fills out.act (cleared by the caller),
+// then the store pass writes only the shells of chunks active now, and zeros
+// for the shells of chunks active before but not now.  Afterwards every
+// inactive chunk holds zeros again.
+hipError_t launch_ao_vgl_screened(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
+                                  hipStream_t s);
 // Values only, one plane: element (k, p) at out.out[k*out.sK + p*out.sP].
 hipError_t launch_ao_value(const AoTables& t, const PointArgs& pts, const AoOut& out, int out_is_f32,
                            hipStream_t s);
