@@ -42,69 +42,149 @@ __device__ __forceinline__ void load_gbar(const GT* __restrict__ q, int64_t sC, 
   for (int c = 0; c < 5; ++c) G[c] = static_cast<double>(q[c * sC]);
 }
 
+// Cartesian component `idx` of a shell of angular momentum l: (a, b, l-a-b)
+// with a descending, then b descending.
+constexpr int cart_a(int l, int idx) {
+  int a = l;
+  while (idx > l - a) {
+    idx -= l - a + 1;
+    --a;
+  }
+  return a;
+}
+constexpr int cart_b(int l, int idx) {
+  int a = l;
+  while (idx > l - a) {
+    idx -= l - a + 1;
+    --a;
+  }
+  return l - a - idx;
+}
+
+// Derivatives of t^E (E known at compile time) of order 0..3.
+template <int E>
+__device__ __forceinline__ AxisD axis_c(double t, double t2, double t3) {
+  AxisD r;
+  if constexpr (E == 0) {
+    r = AxisD{1.0, 0.0, 0.0, 0.0};
+  } else if constexpr (E == 1) {
+    r = AxisD{t, 1.0, 0.0, 0.0};
+  } else if constexpr (E == 2) {
+    r = AxisD{t2, 2.0 * t, 2.0, 0.0};
+  } else {
+    r = AxisD{t3, 3.0 * t2, 6.0 * t, 6.0};
+  }
+  return r;
+}
+
+// Shell quantities shared by its components.
+struct ShellRadial {
+  double dx, dy, dz, dx2, dy2, dz2, dx3, dy3, dz3;
+  double g0, g1, g2, tg1, fg2, fug2, eug3, c1, c2;
+};
+
+// Component I of a shell of angular momentum L, then the rest: the powers of
+// the displacement are compile-time choices (no selects), and the component
+// loop is unrolled per L.
+// Gc holds the component's five Gbar values.  FP64 Gbar is loaded one
+// component ahead (the first component's by the caller, before the radial
+// sums), so that the loads overlap the arithmetic; FP32 Gbar is loaded where
+// it is used.  A compiler barrier closes each component, so that the
+// unrolled components do not pile their loads and temporaries up at once.
+template <typename GT, int L, int I>
+__device__ __forceinline__ void adj_components(const ShellRadial& r, const double* __restrict__ M,
+                                               const GT* __restrict__ gb, int64_t sK, int64_t sC,
+                                               const double* Gc, double& tx, double& ty, double& tz) {
+  if constexpr (I < (L + 1) * (L + 2) / 2) {
+    constexpr int a = cart_a(L, I), b = cart_b(L, I), c = L - a - b;
+    constexpr bool kAhead = std::is_same<GT, double>::value;
+    double G[5], Gn[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) G[q] = Gc[q];
+      if constexpr (I + 1 < (L + 1) * (L + 2) / 2) load_gbar(gb + (I + 1) * sK, sC, Gn);
+    } else {
+      load_gbar(gb + I * sK, sC, G);
+    }
+    // fresh copies of the powers: without them common products of different
+    // components would be kept alive across the whole shell
+    double px = r.dx, px2 = r.dx2, px3 = r.dx3, py = r.dy, py2 = r.dy2, py3 = r.dy3, pz = r.dz, pz2 = r.dz2,
+           pz3 = r.dz3;
+    asm volatile("" : "+v"(px), "+v"(px2), "+v"(px3), "+v"(py), "+v"(py2), "+v"(py3), "+v"(pz), "+v"(pz2),
+                 "+v"(pz3));
+    const AxisD X = axis_c<a>(px, px2, px3);
+    const AxisD Y = axis_c<b>(py, py2, py3);
+    const AxisD Z = axis_c<c>(pz, pz2, pz3);
+    const double G0 = G[0], G1 = G[1], G2 = G[2], G3 = G[3], G4 = G[4];
+    const double P = X.v0 * Y.v0 * Z.v0;
+    const double Px = X.v1 * Y.v0 * Z.v0, Py = X.v0 * Y.v1 * Z.v0, Pz = X.v0 * Y.v0 * Z.v1;
+    const double Pxx = X.v2 * Y.v0 * Z.v0, Pyy = X.v0 * Y.v2 * Z.v0, Pzz = X.v0 * Y.v0 * Z.v2;
+    const double Pxy = X.v1 * Y.v1 * Z.v0, Pxz = X.v1 * Y.v0 * Z.v1, Pyz = X.v0 * Y.v1 * Z.v1;
+    const double lapP = Pxx + Pyy + Pzz;
+    const double lPx = X.v3 * Y.v0 * Z.v0 + X.v1 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
+    const double lPy = Y.v3 * X.v0 * Z.v0 + Y.v1 * (X.v2 * Z.v0 + X.v0 * Z.v2);
+    const double lPz = Z.v3 * X.v0 * Y.v0 + Z.v1 * (X.v2 * Y.v0 + X.v0 * Y.v2);
+    const double Gd = G1 * r.dx + G2 * r.dy + G3 * r.dz;
+    const double GdP = G1 * Px + G2 * Py + G3 * Pz;
+    const double HGx = Pxx * G1 + Pxy * G2 + Pxz * G3;
+    const double HGy = Pxy * G1 + Pyy * G2 + Pyz * G3;
+    const double HGz = Pxz * G1 + Pyz * G2 + Pzz * G3;
+    const double m = M[I];
+    // per direction i: G0 d_i chi + sum_j Gj d_i d_j chi + G4 d_i lap chi (over M)
+    const double Pg = P * Gd * r.fg2, Pe = P * r.eug3, Pl = P * r.c2 * r.g2;
+    tx += m * (G0 * (Px * r.g0 + r.dx * P * r.tg1) + r.g0 * HGx + r.tg1 * (Px * Gd + r.dx * GdP + G1 * P) +
+               r.dx * Pg + G4 * (lPx * r.g0 + (2.0 * r.dx * lapP + r.c1 * Px) * r.g1 + r.dx * Pl + r.fug2 * Px +
+                                 r.dx * Pe));
+    ty += m * (G0 * (Py * r.g0 + r.dy * P * r.tg1) + r.g0 * HGy + r.tg1 * (Py * Gd + r.dy * GdP + G2 * P) +
+               r.dy * Pg + G4 * (lPy * r.g0 + (2.0 * r.dy * lapP + r.c1 * Py) * r.g1 + r.dy * Pl + r.fug2 * Py +
+                                 r.dy * Pe));
+    tz += m * (G0 * (Pz * r.g0 + r.dz * P * r.tg1) + r.g0 * HGz + r.tg1 * (Pz * Gd + r.dz * GdP + G3 * P) +
+               r.dz * Pg + G4 * (lPz * r.g0 + (2.0 * r.dz * lapP + r.c1 * Pz) * r.g1 + r.dz * Pl + r.fug2 * Pz +
+                                 r.dz * Pe));
+    asm volatile("" ::: "memory");  // keeps the next component's loads below this one
+    adj_components<GT, L, I + 1>(r, M, gb, sK, sC, Gn, tx, ty, tz);
+  }
+}
+
+template <typename GT, int L>
+__device__ __forceinline__ void shell_adjoint_l(double dx, double dy, double dz, double u, double g0,
+                                                double g1, double g2, double g3, const double* __restrict__ M,
+                                                const GT* __restrict__ gb, int64_t sK, int64_t sC,
+                                                const double* G_first, double& tx, double& ty, double& tz) {
+  ShellRadial r;
+  r.dx = dx;
+  r.dy = dy;
+  r.dz = dz;
+  r.dx2 = dx * dx;
+  r.dy2 = dy * dy;
+  r.dz2 = dz * dz;
+  r.dx3 = r.dx2 * dx;
+  r.dy3 = r.dy2 * dy;
+  r.dz3 = r.dz2 * dz;
+  r.g0 = g0;
+  r.g1 = g1;
+  r.g2 = g2;
+  r.tg1 = 2.0 * g1;
+  r.fg2 = 4.0 * g2;
+  r.fug2 = 4.0 * u * g2;
+  r.eug3 = 8.0 * u * g3;
+  r.c1 = 4.0 * L + 6.0;
+  r.c2 = 8.0 * L + 20.0;
+  adj_components<GT, L, 0>(r, M, gb, sK, sC, G_first, tx, ty, tz);
+}
+
+// Contracts the shell's third-order AO derivatives with Gbar (l <= 3,
+// wave-uniform).
 template <typename GT>
-__device__ __forceinline__ void shell_adjoint(int l, double dx, double dy, double dz, double u,
-                                              double g0, double g1, double g2, double g3,
-                                              const double* __restrict__ M,
+__device__ __forceinline__ void shell_adjoint(int l, double dx, double dy, double dz, double u, double g0,
+                                              double g1, double g2, double g3, const double* __restrict__ M,
                                               const GT* __restrict__ gb, int64_t sK, int64_t sC,
                                               const double* G_first, double& tx, double& ty, double& tz) {
-  const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
-  const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
-  const double c1 = 4.0 * l + 6.0, c2 = 8.0 * l + 20.0;
-  const double tg1 = 2.0 * g1, fg2 = 4.0 * g2, eug3 = 8.0 * u * g3, fug2 = 4.0 * u * g2;
-  // components (a, b, c) with a descending, then b descending
-  const int ncart = (l + 1) * (l + 2) / 2;
-  constexpr bool kAhead = std::is_same<GT, double>::value;
-  double Gc[5] = {G_first[0], G_first[1], G_first[2], G_first[3], G_first[4]};
-  int a = l, b = 0;
-#pragma unroll 1
-  for (int idx = 0; idx < ncart; ++idx) {
-    {
-      double Gn[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      if constexpr (kAhead) {
-        if (idx + 1 < ncart) load_gbar(gb + (idx + 1) * sK, sC, Gn);
-      } else {
-        load_gbar(gb + idx * sK, sC, Gc);
-      }
-      const int c = l - a - b;
-      const AxisD X = axis_derivs(a, dx, dx2, dx3);
-      const AxisD Y = axis_derivs(b, dy, dy2, dy3);
-      const AxisD Z = axis_derivs(c, dz, dz2, dz3);
-      const double G0 = Gc[0], G1 = Gc[1], G2 = Gc[2], G3 = Gc[3], G4 = Gc[4];
-      const double P = X.v0 * Y.v0 * Z.v0;
-      const double Px = X.v1 * Y.v0 * Z.v0, Py = X.v0 * Y.v1 * Z.v0, Pz = X.v0 * Y.v0 * Z.v1;
-      const double Pxx = X.v2 * Y.v0 * Z.v0, Pyy = X.v0 * Y.v2 * Z.v0, Pzz = X.v0 * Y.v0 * Z.v2;
-      const double Pxy = X.v1 * Y.v1 * Z.v0, Pxz = X.v1 * Y.v0 * Z.v1, Pyz = X.v0 * Y.v1 * Z.v1;
-      const double lapP = Pxx + Pyy + Pzz;
-      const double lPx = X.v3 * Y.v0 * Z.v0 + X.v1 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
-      const double lPy = Y.v3 * X.v0 * Z.v0 + Y.v1 * (X.v2 * Z.v0 + X.v0 * Z.v2);
-      const double lPz = Z.v3 * X.v0 * Y.v0 + Z.v1 * (X.v2 * Y.v0 + X.v0 * Y.v2);
-      const double Gd = G1 * dx + G2 * dy + G3 * dz;
-      const double GdP = G1 * Px + G2 * Py + G3 * Pz;
-      const double HGx = Pxx * G1 + Pxy * G2 + Pxz * G3;
-      const double HGy = Pxy * G1 + Pyy * G2 + Pyz * G3;
-      const double HGz = Pxz * G1 + Pyz * G2 + Pzz * G3;
-      const double m = M[idx];
-      // per direction i: G0 d_i chi + sum_j Gj d_i d_j chi + G4 d_i lap chi (over M)
-      const double Pg = P * Gd * fg2, Pe = P * eug3, Pl = P * c2 * g2;
-      tx += m * (G0 * (Px * g0 + dx * P * tg1) + g0 * HGx + tg1 * (Px * Gd + dx * GdP + G1 * P) +
-                 dx * Pg + G4 * (lPx * g0 + (2.0 * dx * lapP + c1 * Px) * g1 + dx * Pl + fug2 * Px +
-                                 dx * Pe));
-      ty += m * (G0 * (Py * g0 + dy * P * tg1) + g0 * HGy + tg1 * (Py * Gd + dy * GdP + G2 * P) +
-                 dy * Pg + G4 * (lPy * g0 + (2.0 * dy * lapP + c1 * Py) * g1 + dy * Pl + fug2 * Py +
-                                 dy * Pe));
-      tz += m * (G0 * (Pz * g0 + dz * P * tg1) + g0 * HGz + tg1 * (Pz * Gd + dz * GdP + G3 * P) +
-                 dz * Pg + G4 * (lPz * g0 + (2.0 * dz * lapP + c1 * Pz) * g1 + dz * Pl + fug2 * Pz +
-                                 dz * Pe));
-#pragma unroll
-      for (int q = 0; q < 5; ++q) Gc[q] = Gn[q];
-    }
-    if (b > 0) {
-      --b;
-    } else {
-      --a;
-      b = l - a;
-    }
+  switch (l) {
+    case 0: shell_adjoint_l<GT, 0>(dx, dy, dz, u, g0, g1, g2, g3, M, gb, sK, sC, G_first, tx, ty, tz); break;
+    case 1: shell_adjoint_l<GT, 1>(dx, dy, dz, u, g0, g1, g2, g3, M, gb, sK, sC, G_first, tx, ty, tz); break;
+    case 2: shell_adjoint_l<GT, 2>(dx, dy, dz, u, g0, g1, g2, g3, M, gb, sK, sC, G_first, tx, ty, tz); break;
+    default: shell_adjoint_l<GT, 3>(dx, dy, dz, u, g0, g1, g2, g3, M, gb, sK, sC, G_first, tx, ty, tz); break;
   }
 }
 
