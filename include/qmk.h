@@ -248,7 +248,7 @@ qmk_status qmk_set_mo_cusp(qmk_ctx ctx, int64_t nucl_num, const double* charge,
  * Only exact zeros (AOs beyond the exponent cutoff) are skipped, so the
  * result equals the dense product's bit for bit (up to the sign of a zero).
  * Every precision mode (FP64, FP32 and BF16x3 products).  At most 16384 AOs
- * (QMK_UNSUPPORTED above).  qmk_mo_vgl_adjoint screens too: W is
+ * and 16384 nuclei (QMK_UNSUPPORTED above).  qmk_mo_vgl_adjoint screens too: W is
  * reordered once into the sorted point order, G-bar tiles whose AOs are zero
  * at all of their points are stored as zeros, and dC skips point stages with
  * no non-zero AO in its columns; electron gradients equal the dense path bit

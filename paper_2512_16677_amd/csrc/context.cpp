@@ -391,6 +391,10 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
   if (!force && ctx->aos_date == ctx->date && ctx->aos_f32 == f32 && ctx->aos_Pp == Pp && ctx->aos_Kp == Kp)
     return QMK_OK;
   const int64_t nn = ctx->nucl_num;
+  if (nn > kSortMaxNuclei)
+    return fail(ctx, QMK_UNSUPPORTED,
+                "the screened evaluation sorts points by nearest nucleus for at most " +
+                    std::to_string(kSortMaxNuclei) + " nuclei");
   if (ctx->nuc_xyz_version != ctx->geom_version) {
     QMK_HIP(ctx, ctx->d_nuc_xyz.ensure(static_cast<size_t>(3 * nn) * 8), "alloc nuclei");
     QMK_HIP(ctx, hipMemcpy(ctx->d_nuc_xyz.p, ctx->nucl.data(), static_cast<size_t>(3 * nn) * 8,
@@ -398,8 +402,6 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
     ctx->nuc_xyz_version = ctx->geom_version;
   }
   QMK_HIP(ctx, ctx->d_sort_key.ensure(static_cast<size_t>(P) * 4), "alloc sort keys");
-  QMK_HIP(ctx, ctx->d_sort_key2.ensure(static_cast<size_t>(P) * 4), "alloc sorted keys");
-  QMK_HIP(ctx, ctx->d_sort_idx.ensure(static_cast<size_t>(P) * 4), "alloc sort indices");
   QMK_HIP(ctx, ctx->d_perm.ensure(static_cast<size_t>(P) * 4), "alloc permutation");
   const size_t scratch = std::max<size_t>(sort_scratch_bytes(P, nn), 16);
   QMK_HIP(ctx, ctx->d_sort_scratch.ensure(scratch), "alloc sort scratch");
@@ -428,7 +430,6 @@ qmk_status provide_ao_sorted(qmk_ctx ctx, hipStream_t s, bool force = false) {
   {
     LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
     QMK_HIP(ctx, launch_sort_points(pa, ctx->d_nuc_xyz.as<double>(), nn, ctx->d_sort_key.as<int32_t>(),
-                                    ctx->d_sort_key2.as<int32_t>(), ctx->d_sort_idx.as<int32_t>(),
                                     ctx->d_perm.as<int32_t>(), ctx->d_sort_scratch.p, scratch, s),
             "sort points");
     QMK_HIP(ctx, launch_fill_u32(ctx->d_act.as<uint32_t>(), act_n, 0u, s), "clear activity bitmap");

@@ -126,7 +126,7 @@ struct qmk_ctx_s {
   // screened contraction: points sorted by nearest nucleus, the AO array in
   // that order [Kp][5][Pp] and its activity bitmap, valid at aos_date
   bool sparse = false;
-  DevBuf d_sort_key, d_sort_key2, d_sort_idx, d_sort_scratch, d_perm, d_act, aos, d_nuc_xyz, w_sorted;
+  DevBuf d_sort_key, d_sort_scratch, d_perm, d_act, aos, d_nuc_xyz, w_sorted;
   // bitmap of the previous screened evaluation into aos (swapped with d_act)
   DevBuf d_act_prev;
   int64_t aos_Pp = 0, aos_Kp = 0, aos_date = -1, act_words = 0, nuc_xyz_version = -1;

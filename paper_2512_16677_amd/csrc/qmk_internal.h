@@ -276,13 +276,13 @@ hipError_t launch_gemm_screened_adj(GemmKind kind, Prec prec, int cfg, const Gem
                                     hipStream_t s);
 // Screened forward product (FP64 or FP32 tile cfg; D in FP64 or FP32).
 hipError_t launch_gemm_sparse(Prec prec, int cfg, const GemmArgs& g, int out_is_f32, hipStream_t s);
-// Point sort by nearest nucleus (stable radix sort): perm[i] = original
-// index of sorted point i.  key, key_sorted, index: P entries each; scratch
-// of sort_scratch_bytes(P, n_nuc) bytes.
+// Point sort by nearest nucleus (stable counting sort): perm[i] = original
+// index of sorted point i.  key: P entries; scratch of
+// sort_scratch_bytes(P, n_nuc) bytes; 1 <= n_nuc <= kSortMaxNuclei.
+constexpr int kSortMaxNuclei = 16384;
 size_t sort_scratch_bytes(int64_t P, int64_t n_nuc);
 hipError_t launch_sort_points(const PointArgs& pts, const double* nuc_xyz, int64_t n_nuc, int32_t* key,
-                              int32_t* key_sorted, int32_t* index, int32_t* perm, void* scratch,
-                              size_t scratch_bytes, hipStream_t s);
+                              int32_t* perm, void* scratch, size_t scratch_bytes, hipStream_t s);
 // Determinants det[b] and adjugates adj[b] (row-major n x n) of a batch of
 // row-major n x n FP64 matrices, 1 <= n <= 32.
 hipError_t launch_det_adj(int n, int64_t batch, const double* A, double* det, double* adj, hipStream_t s);
