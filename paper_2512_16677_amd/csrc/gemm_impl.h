@@ -2,6 +2,8 @@
 // that instantiate them; see gemm_kernels.hip).
 #pragma once
 
+#include <type_traits>
+
 #include "qmk_internal.h"
 
 namespace qmk {
@@ -45,11 +47,157 @@ struct Mfma<float> {
 // so the workgroup tile is BM = 16 WGM TM rows by BN = 16 WGN TN columns,
 // with a reduction step of BK.
 template <typename T, int BM, int BN, int BK>
-struct GemmSmem {
+struct alignas(16) GemmSmem {
   static constexpr int PAD = 16 / sizeof(T);
   T A[2][BK][BM + PAD];
   T B[2][BK][BN + PAD];
 };
+
+// ---------------------------------------------------------------------------
+// FP64 K loop with direct global -> LDS loads (global_load_lds_dwordx4: 16
+// bytes per lane, one 1 KB block per wave and instruction, written at the
+// wave-uniform LDS address in M0 plus 16 lane).  The operand tiles never pass
+// through registers, so the register staging of the generic loop, its LDS
+// stores and their address arithmetic go away.  Two stages: the loads of K
+// step k + 1 run under the products of step k.
+//
+// Stage layout in LDS (no padding: the loads fill whole 1 KB blocks):
+//   A, i contiguous:  [BK][BM]  element (l, i) at l BM + (i ^ dma_xr<BM>(l))
+//   B, j contiguous:  [BK][BN]  element (l, j) at l BN + (j ^ dma_xr<BN>(l))
+//   B, l contiguous:  [BN][BK]  element (l, j) at j BK + 2 ((l/2) ^ (j/2 % 8)) + l % 2
+// A half-wave's fragment read touches two consecutive rows of an i- or
+// j-contiguous tile; when a row is a multiple of 256 bytes, dma_xr swaps the
+// 128-byte halves of odd rows so that the two rows use different banks.  The
+// pair swizzle of the l-contiguous layout spreads the 16 rows that one
+// fragment read touches over all banks.
+//
+// Rows past the end of the matrix read a copy of the last in-range pair (or
+// row); their products land in outputs that are never stored.  The K extent
+// must be a whole number of steps (no zero fill).
+template <int R>
+__device__ __forceinline__ int dma_xr(int l) {
+  return R % 32 == 0 ? (l & 1) << 4 : 0;
+}
+
+__device__ __forceinline__ uint32_t dma_lds_address(const void* p) {
+  return static_cast<uint32_t>(
+      reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char*)(p)));
+}
+
+// Lane l's 16 bytes at g land at LDS byte lds + 16 l.  The compiler does not
+// see these LDS writes: dma_sync waits for them.
+__device__ __forceinline__ void dma_b128(const void* g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" : : "s"(lds), "v"(g)
+               : "memory", "m0");
+}
+
+// Waits for this wave's loads and LDS reads, then joins the workgroup
+// barrier; the memory clobber keeps LDS reads from moving across it.
+__device__ __forceinline__ void dma_sync() {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" : : : "memory");
+}
+
+// Whether this tile may take the direct-load loop: unit stride along i (A)
+// and along j or l (B), 16-byte aligned operands and even strides (every
+// 16-byte pair starts aligned), an even row (and, for j-contiguous B, column)
+// count so that the clamped last pair is in range, and whole K steps.
+template <int BK, bool B_J>
+__device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, const void* Bp, int64_t Ls) {
+  if (BK != 16 || g.sAi != 1 || (g.sAl & 1) || (g.M & 1) || Ls % BK != 0) return false;
+  if (B_J ? (g.sBj != 1 || (g.sBl & 1) || (g.N & 1)) : (g.sBl != 1 || (g.sBj & 1))) return false;
+  return ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) == 0;
+}
+
+// K loop of one tile: At / Bt point at the tile's first row / column,
+// rows_a = M - i0 and rows_b = N - j0 (both even where pairs are clamped),
+// nk K steps (LIST: the steps list[0 .. nk)).  The caller synchronises the
+// workgroup before the LDS is written again after the loop.
+template <bool B_J, int WGM, int WGN, int TM, int TN, bool LIST>
+__device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, const double* Bt, int64_t sAl,
+                                             int64_t sBl, int64_t sBj, int64_t rows_a, int64_t rows_b,
+                                             int64_t nk, const int16_t* list,
+                                             typename Mfma<double>::v4 (&acc)[TM][TN]) {
+  constexpr int BK = 16, BM = 16 * WGM * TM, BN = 16 * WGN * TN, NW = WGM * WGN;
+  constexpr int NIA = BM / 8, NI = (BM + BN) / 8;  // 1 KB blocks per stage (A first)
+  constexpr int IPW = (NI + NW - 1) / NW;
+  constexpr int STAGE = (BM + BN) * BK;  // doubles
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w / WGN, wn = w % WGN;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(dma_lds_address(stages));
+
+  // per instruction: this lane's source in step 0, the bytes a K step moves
+  // it, and the LDS offset of its block within a stage.  A wave short of
+  // blocks repeats one (the same bytes written twice).
+  const char* gp[IPW];
+  int64_t step[IPW];
+  uint32_t ldso[IPW];
+#pragma unroll
+  for (int q = 0; q < IPW; ++q) {
+    int ig = wu + NW * q;
+    if (NI % NW != 0 && ig >= NI) ig -= NI;
+    ldso[q] = static_cast<uint32_t>(ig) * 1024u;
+    const double* src;
+    if (ig < NIA) {
+      const int sl = 64 * ig + lane, l = sl / (BM / 2);
+      const int i = (2 * (sl % (BM / 2))) ^ dma_xr<BM>(l);
+      src = At + (i < rows_a ? i : rows_a - 2) + l * sAl;
+      step[q] = static_cast<int64_t>(BK) * sAl * 8;
+    } else if constexpr (B_J) {
+      const int sl = 64 * (ig - NIA) + lane, l = sl / (BN / 2);
+      const int j = (2 * (sl % (BN / 2))) ^ dma_xr<BN>(l);
+      src = Bt + (j < rows_b ? j : rows_b - 2) + l * sBl;
+      step[q] = static_cast<int64_t>(BK) * sBl * 8;
+    } else {
+      const int sl = 64 * (ig - NIA) + lane, j = sl / (BK / 2);
+      const int l = 2 * ((sl % (BK / 2)) ^ ((j >> 1) & 7));
+      src = Bt + (j < rows_b ? j : rows_b - 1) * sBj + l;
+      step[q] = static_cast<int64_t>(BK) * 8;
+    }
+    gp[q] = reinterpret_cast<const char*>(src);
+  }
+  auto issue = [&](int slot, int64_t kt) {
+    const int64_t t = LIST ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[kt])) : kt;
+    const uint32_t sb = lds0 + static_cast<uint32_t>(slot * STAGE * 8);
+#pragma unroll
+    for (int q = 0; q < IPW; ++q) dma_b128(gp[q] + t * step[q], sb + ldso[q]);
+  };
+  // fragments of sub-step kk + 1 are read before the products of kk
+  auto compute = [&](const double* sa) {
+    const double* sb = sa + BM * BK;
+    const int ci = lane & 15, kq = lane >> 4;
+    double fa[2][TM], fb[2][TN];
+    auto rd = [&](int kk, int u) {
+      const int k = kk * 4 + kq;
+#pragma unroll
+      for (int a = 0; a < TM; ++a) fa[u][a] = sa[k * BM + (((wm * TM + a) * 16 + ci) ^ dma_xr<BM>(k))];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int j = (wn * TN + b) * 16 + ci;
+        fb[u][b] = B_J ? sb[k * BN + (j ^ dma_xr<BN>(k))]
+                       : sb[j * BK + ((((k >> 1) ^ ((ci >> 1) & 7)) << 1) | (k & 1))];
+      }
+    };
+    rd(0, 0);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      if (kk + 1 < BK / 4) rd(kk + 1, (kk + 1) & 1);
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<double>::op(fa[kk & 1][a], fb[kk & 1][b], acc[a][b]);
+    }
+  };
+
+  if (nk <= 0) return;
+  issue(0, 0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    // step kt has landed; the stage read in step kt - 1 is free
+    dma_sync();
+    if (kt + 1 < nk) issue(static_cast<int>((kt + 1) & 1), kt + 1);
+    compute(stages + (kt & 1) * STAGE);
+  }
+}
 
 // One output tile (mt, nt) of batch index z.  EPI = 0 stores D; EPI = 1 is
 // the density epilogue: each wave reduces occ[j] * D(i, j)^2 over its own
@@ -77,6 +225,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
+  // FP64 products with i-contiguous A may take the direct-load K loop
+  constexpr bool kDirect = std::is_same<T, double>::value && std::is_same<TA, double>::value &&
+                           std::is_same<TB, double>::value && BK == 16 && A_I && EPI != 4 && EPI != 5;
   typedef typename Mfma<T>::v4 v4;
   auto& As = sm.A;
   auto& Bs = sm.B;
@@ -232,17 +383,28 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     auto l0_of = [&](int64_t t) -> int64_t {
       return (EPI == 2 ? static_cast<int64_t>(stage_list[t]) : t) * BK;
     };
-    if (nk > 0) {
-      load(l0_of(0));
-      stash(0);
+    bool direct = false;
+    if constexpr (kDirect) {
+      if (dma_tile_ok<BK, B_J>(g, Ap, Bp, Ls)) {
+        direct = true;
+        f64_dma_loop<B_J, WGM, WGN, TM, TN, EPI == 2>(reinterpret_cast<double*>(&sm), Ap + i0,
+                                                      Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
+                                                      g.M - i0, g.N - j0, nk, stage_list, acc);
+      }
     }
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-      const int buf = static_cast<int>(kt & 1);
-      if (kt + 1 < nk) load(l0_of(kt + 1));
-      mma(buf);
-      if (kt + 1 < nk) stash(buf ^ 1);
+    if (!direct) {
+      if (nk > 0) {
+        load(l0_of(0));
+        stash(0);
+      }
       __syncthreads();
+      for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = static_cast<int>(kt & 1);
+        if (kt + 1 < nk) load(l0_of(kt + 1));
+        mma(buf);
+        if (kt + 1 < nk) stash(buf ^ 1);
+        __syncthreads();
+      }
     }
   }
 
