@@ -64,19 +64,27 @@ struct alignas(16) GemmSmem {
 // Stage layout in LDS (no padding: the loads fill whole 1 KB blocks):
 //   A, i contiguous:  [BK][BM]  element (l, i) at l BM + (i ^ dma_xr<BM>(l))
 //   B, j contiguous:  [BK][BN]  element (l, j) at l BN + (j ^ dma_xr<BN>(l))
-//   B, l contiguous:  [BN][BK]  element (l, j) at j BK + 2 ((l/2) ^ (j/2 % 8)) + l % 2
-// A half-wave's fragment read touches two consecutive rows of an i- or
-// j-contiguous tile; when a row is a multiple of 256 bytes, dma_xr swaps the
-// 128-byte halves of odd rows so that the two rows use different banks.  The
-// pair swizzle of the l-contiguous layout spreads the 16 rows that one
-// fragment read touches over all banks.
+//   B, l contiguous:  [BN][BK]  element (l, j) at j BK + 2 ((l/2) ^ dma_kx<BK>(j)) + l % 2
+// (BK = 16 or 32).  A half-wave's fragment read touches two consecutive rows
+// of an i- or j-contiguous tile; when a row is a multiple of 256 bytes,
+// dma_xr swaps the 128-byte halves of odd rows so that the two rows use
+// different banks.  The pair swizzle of the l-contiguous layout spreads the
+// 16 rows that one fragment read touches over all banks.
 //
 // Rows past the end of the matrix read a copy of the last in-range pair (or
-// row); their products land in outputs that are never stored.  The K extent
-// must be a whole number of steps (no zero fill).
+// row); their products land in outputs that are never stored.  A partial
+// last K step (the K extent not a multiple of 16) is staged through
+// registers instead, with zeros beyond the extent.
 template <int R>
 __device__ __forceinline__ int dma_xr(int l) {
   return R % 32 == 0 ? (l & 1) << 4 : 0;
+}
+
+// rows of 128 bytes (BK = 16): consecutive rows already alternate bank
+// halves, so pairs of rows share a swizzle; rows of 256 bytes: one per row
+template <int BK>
+__device__ __forceinline__ int dma_kx(int j) {
+  return BK == 16 ? (j >> 1) & 7 : j & 15;
 }
 
 __device__ __forceinline__ uint32_t dma_lds_address(const void* p) {
@@ -99,26 +107,28 @@ __device__ __forceinline__ void dma_sync() {
 
 // Whether this tile may take the direct-load loop: unit stride along i (A)
 // and along j or l (B), 16-byte aligned operands and even strides (every
-// 16-byte pair starts aligned), an even row (and, for j-contiguous B, column)
-// count so that the clamped last pair is in range, and whole K steps.
+// 16-byte pair starts aligned), and an even row (and, for j-contiguous B,
+// column) count so that the clamped last pair is in range.
 template <int BK, bool B_J>
-__device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, const void* Bp, int64_t Ls) {
-  if (BK != 16 || g.sAi != 1 || (g.sAl & 1) || (g.M & 1) || Ls % BK != 0) return false;
+__device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, const void* Bp) {
+  if ((BK != 16 && BK != 32) || g.sAi != 1 || (g.sAl & 1) || (g.M & 1)) return false;
   if (B_J ? (g.sBj != 1 || (g.sBl & 1) || (g.N & 1)) : (g.sBl != 1 || (g.sBj & 1))) return false;
   return ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) == 0;
 }
 
 // K loop of one tile: At / Bt point at the tile's first row / column,
 // rows_a = M - i0 and rows_b = N - j0 (both even where pairs are clamped),
-// nk K steps (LIST: the steps list[0 .. nk)).  The caller synchronises the
+// nk K steps (LIST: the steps list[0 .. nk)), of which the last holds only
+// tail < 16 values of l when tail > 0.  The caller synchronises the
 // workgroup before the LDS is written again after the loop.
-template <bool B_J, int WGM, int WGN, int TM, int TN, bool LIST>
+template <int BK, bool B_J, int WGM, int WGN, int TM, int TN, bool LIST>
 __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, const double* Bt, int64_t sAl,
                                              int64_t sBl, int64_t sBj, int64_t rows_a, int64_t rows_b,
-                                             int64_t nk, const int16_t* list,
+                                             int64_t nk, int tail, const int16_t* list,
                                              typename Mfma<double>::v4 (&acc)[TM][TN]) {
-  constexpr int BK = 16, BM = 16 * WGM * TM, BN = 16 * WGN * TN, NW = WGM * WGN;
-  constexpr int NIA = BM / 8, NI = (BM + BN) / 8;  // 1 KB blocks per stage (A first)
+  constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, NW = WGM * WGN;
+  static_assert(BK == 16 || BK == 32, "K step");
+  constexpr int NIA = BM * BK / 128, NI = (BM + BN) * BK / 128;  // 1 KB blocks per stage (A first)
   constexpr int IPW = (NI + NW - 1) / NW;
   constexpr int STAGE = (BM + BN) * BK;  // doubles
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -150,7 +160,7 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
       step[q] = static_cast<int64_t>(BK) * sBl * 8;
     } else {
       const int sl = 64 * (ig - NIA) + lane, j = sl / (BK / 2);
-      const int l = 2 * ((sl % (BK / 2)) ^ ((j >> 1) & 7));
+      const int l = 2 * ((sl % (BK / 2)) ^ dma_kx<BK>(j));
       src = Bt + (j < rows_b ? j : rows_b - 1) * sBj + l;
       step[q] = static_cast<int64_t>(BK) * 8;
     }
@@ -175,7 +185,7 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
       for (int b = 0; b < TN; ++b) {
         const int j = (wn * TN + b) * 16 + ci;
         fb[u][b] = B_J ? sb[k * BN + (j ^ dma_xr<BN>(k))]
-                       : sb[j * BK + ((((k >> 1) ^ ((ci >> 1) & 7)) << 1) | (k & 1))];
+                       : sb[j * BK + ((((k >> 1) ^ dma_kx<BK>(ci)) << 1) | (k & 1))];
       }
     };
     rd(0, 0);
@@ -189,13 +199,44 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
     }
   };
 
+  // the partial last step, through registers with zeros beyond l < tail and
+  // beyond the last row / column
+  auto stage_tail = [&](double* st, int64_t t) {
+    constexpr int NT = 64 * NW;
+    const int64_t l0 = t * BK;
+    for (int e = tid; e < BM * BK; e += NT) {
+      const int l = e / BM, i = e % BM;
+      st[l * BM + (i ^ dma_xr<BM>(l))] = l < tail && i < rows_a ? At[i + (l0 + l) * sAl] : 0.0;
+    }
+    double* sb = st + BM * BK;
+    for (int e = tid; e < BN * BK; e += NT) {
+      if constexpr (B_J) {
+        const int l = e / BN, j = e % BN;
+        sb[l * BN + (j ^ dma_xr<BN>(l))] = l < tail && j < rows_b ? Bt[j + (l0 + l) * sBl] : 0.0;
+      } else {
+        const int j = e / BK, l = e % BK;
+        sb[j * BK + ((((l >> 1) ^ dma_kx<BK>(j)) << 1) | (l & 1))] =
+            l < tail && j < rows_b ? Bt[j * sBj + l0 + l] : 0.0;
+      }
+    }
+  };
+
   if (nk <= 0) return;
-  issue(0, 0);
-  for (int64_t kt = 0; kt < nk; ++kt) {
+  const int64_t nd = tail > 0 ? nk - 1 : nk;  // steps by direct loads
+  if (nd > 0) issue(0, 0);
+  for (int64_t kt = 0; kt < nd; ++kt) {
     // step kt has landed; the stage read in step kt - 1 is free
     dma_sync();
-    if (kt + 1 < nk) issue(static_cast<int>((kt + 1) & 1), kt + 1);
+    if (kt + 1 < nd) issue(static_cast<int>((kt + 1) & 1), kt + 1);
     compute(stages + (kt & 1) * STAGE);
+  }
+  if (tail > 0) {
+    // stage nd & 1 was last read in step nd - 2, before every wave passed the
+    // barrier of step nd - 1
+    double* st = stages + (nd & 1) * STAGE;
+    stage_tail(st, LIST ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[nk - 1])) : nd);
+    __syncthreads();
+    compute(st);
   }
 }
 
@@ -227,7 +268,8 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
   constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
   // FP64 products with i-contiguous A may take the direct-load K loop
   constexpr bool kDirect = std::is_same<T, double>::value && std::is_same<TA, double>::value &&
-                           std::is_same<TB, double>::value && BK == 16 && A_I && EPI != 4 && EPI != 5;
+                           std::is_same<TB, double>::value && (BK == 16 || BK == 32) && A_I && EPI != 4 &&
+                           EPI != 5;
   typedef typename Mfma<T>::v4 v4;
   auto& As = sm.A;
   auto& Bs = sm.B;
@@ -243,7 +285,13 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
   // Operand tiles fully inside the matrices take an unguarded path (uniform
   // branch per K step); only edge tiles test every element.
   const bool a_rows_in = i0 + BM <= g.M, b_cols_in = j0 + BN <= g.N;
+  // In the instantiations that also hold the direct-load loop, this loop
+  // recomputes its per-thread element indices at every K step (the thread
+  // index is opaque to the compiler here), so that they are not kept in
+  // registers across the whole kernel.
   auto load = [&](int64_t l0) {
+    int tid = threadIdx.x;
+    if constexpr (kDirect) asm volatile("" : "+v"(tid));
     const bool l_in = l0 + BK <= Ls;
     if (a_rows_in && l_in && BM * BK % NT == 0) {
       const TA* base = Ap + i0 * g.sAi + l0 * g.sAl;
@@ -287,6 +335,8 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     }
   };
   auto stash = [&](int buf) {
+    int tid = threadIdx.x;
+    if constexpr (kDirect) asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int r = 0; r < EA; ++r) {
       const int e = tid + NT * r;
@@ -385,11 +435,15 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     };
     bool direct = false;
     if constexpr (kDirect) {
-      if (dma_tile_ok<BK, B_J>(g, Ap, Bp, Ls)) {
+      if (dma_tile_ok<BK, B_J>(g, Ap, Bp)) {
         direct = true;
-        f64_dma_loop<B_J, WGM, WGN, TM, TN, EPI == 2>(reinterpret_cast<double*>(&sm), Ap + i0,
-                                                      Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
-                                                      g.M - i0, g.N - j0, nk, stage_list, acc);
+        // the last K step is partial when Ls is not a multiple of BK and the
+        // step list reaches it
+        const int64_t last = (Ls - 1) / BK;
+        const bool part = Ls % BK != 0 && nk > 0 && (EPI == 2 ? stage_list[nk - 1] == last : true);
+        f64_dma_loop<BK, B_J, WGM, WGN, TM, TN, EPI == 2>(
+            reinterpret_cast<double*>(&sm), Ap + i0, Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
+            g.M - i0, g.N - j0, nk, part ? static_cast<int>(Ls % BK) : 0, stage_list, acc);
       }
     }
     if (!direct) {
