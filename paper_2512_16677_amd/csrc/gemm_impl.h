@@ -117,14 +117,16 @@ __device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, c
 }
 
 // K loop of one tile: At / Bt point at the tile's first row / column,
-// rows_a = M - i0 and rows_b = N - j0 (both even where pairs are clamped),
-// nk K steps (LIST: the steps list[0 .. nk)), of which the last holds only
-// tail < 16 values of l when tail > 0.  The caller synchronises the
-// workgroup before the LDS is written again after the loop.
-template <int BK, bool B_J, int WGM, int WGN, int TM, int TN, bool LIST>
+// rows_a = M - i0 and rows_b = N - j0 (both even where pairs are clamped).
+// The K steps visited are first, next(first), next(next(first)), ... up to
+// the first one >= end, in increasing order (the caller's next() returns the
+// following step to visit, wave-uniform).  Step `part`, when visited, is the
+// last one and holds only tail < BK values of l.  The caller synchronises
+// the workgroup before the LDS is written again after the loop.
+template <int BK, bool B_J, int WGM, int WGN, int TM, int TN, class Next>
 __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, const double* Bt, int64_t sAl,
                                              int64_t sBl, int64_t sBj, int64_t rows_a, int64_t rows_b,
-                                             int64_t nk, int tail, const int16_t* list,
+                                             int64_t first, int64_t end, int64_t part, int tail, Next next,
                                              typename Mfma<double>::v4 (&acc)[TM][TN]) {
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, NW = WGM * WGN;
   static_assert(BK == 16 || BK == 32, "K step");
@@ -167,7 +169,7 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
     gp[q] = reinterpret_cast<const char*>(src);
   }
   auto issue = [&](int slot, int64_t kt) {
-    const int64_t t = LIST ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[kt])) : kt;
+    const int64_t t = __builtin_amdgcn_readfirstlane(static_cast<int>(kt));
     const uint32_t sb = lds0 + static_cast<uint32_t>(slot * STAGE * 8);
 #pragma unroll
     for (int q = 0; q < IPW; ++q) dma_b128(gp[q] + t * step[q], sb + ldso[q]);
@@ -221,20 +223,30 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
     }
   };
 
-  if (nk <= 0) return;
-  const int64_t nd = tail > 0 ? nk - 1 : nk;  // steps by direct loads
-  if (nd > 0) issue(0, 0);
-  for (int64_t kt = 0; kt < nd; ++kt) {
-    // step kt has landed; the stage read in step kt - 1 is free
+  int64_t cur = first;
+  if (cur >= end) return;
+  // nxt: the step after cur, found one step ahead of its use
+  int64_t nxt = cur == part ? end : next(cur);
+  int slot = 0;
+  if (cur != part) issue(0, cur);
+  while (cur < end && cur != part) {
+    // step cur has landed; the stage read in the step before it is free
     dma_sync();
-    if (kt + 1 < nd) issue(static_cast<int>((kt + 1) & 1), kt + 1);
-    compute(stages + (kt & 1) * STAGE);
+    int64_t after = end;
+    if (nxt < end && nxt != part) {
+      issue(slot ^ 1, nxt);
+      after = next(nxt);
+    }
+    compute(stages + slot * STAGE);
+    cur = nxt;
+    nxt = after;
+    slot ^= 1;
   }
-  if (tail > 0) {
-    // stage nd & 1 was last read in step nd - 2, before every wave passed the
-    // barrier of step nd - 1
-    double* st = stages + (nd & 1) * STAGE;
-    stage_tail(st, LIST ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(list[nk - 1])) : nd);
+  if (cur < end) {
+    // the partial step, into the stage last read two steps earlier (before
+    // every wave passed the barrier of the step in between)
+    double* st = stages + slot * STAGE;
+    stage_tail(st, cur);
     __syncthreads();
     compute(st);
   }
@@ -268,8 +280,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
   constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
   // FP64 products with i-contiguous A may take the direct-load K loop
   constexpr bool kDirect = std::is_same<T, double>::value && std::is_same<TA, double>::value &&
-                           std::is_same<TB, double>::value && (BK == 16 || BK == 32) && A_I && EPI != 4 &&
-                           EPI != 5;
+                           std::is_same<TB, double>::value && (BK == 16 || BK == 32) && A_I && EPI != 5;
   typedef typename Mfma<T>::v4 v4;
   auto& As = sm.A;
   auto& Bs = sm.B;
@@ -402,21 +413,33 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
       }
       return t;
     };
-    int64_t cur = next(0);
-    int buf = 0;
-    if (cur < nk) {
-      load(cur * BK);
-      stash(0);
+    bool direct = false;
+    if constexpr (kDirect) {
+      if (dma_tile_ok<BK, B_J>(g, Ap, Bp)) {
+        direct = true;
+        f64_dma_loop<BK, B_J, WGM, WGN, TM, TN>(
+            reinterpret_cast<double*>(&sm), Ap + i0, Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
+            g.M - i0, g.N - j0, next(0), nk, Ls % BK != 0 ? nk - 1 : -1, static_cast<int>(Ls % BK),
+            [&](int64_t t) { return next(t + 1); }, acc);
+      }
     }
-    __syncthreads();
-    while (cur < nk) {
-      const int64_t nxt = next(cur + 1);
-      if (nxt < nk) load(nxt * BK);
-      mma(buf);
-      if (nxt < nk) stash(buf ^ 1);
+    if (!direct) {
+      int64_t cur = next(0);
+      int buf = 0;
+      if (cur < nk) {
+        load(cur * BK);
+        stash(0);
+      }
       __syncthreads();
-      cur = nxt;
-      buf ^= 1;
+      while (cur < nk) {
+        const int64_t nxt = next(cur + 1);
+        if (nxt < nk) load(nxt * BK);
+        mma(buf);
+        if (nxt < nk) stash(buf ^ 1);
+        __syncthreads();
+        cur = nxt;
+        buf ^= 1;
+      }
     }
   } else {
     int64_t nk = EPI == 2 ? n_stages : (Ls + BK - 1) / BK;
@@ -437,13 +460,23 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     if constexpr (kDirect) {
       if (dma_tile_ok<BK, B_J>(g, Ap, Bp)) {
         direct = true;
-        // the last K step is partial when Ls is not a multiple of BK and the
-        // step list reaches it
-        const int64_t last = (Ls - 1) / BK;
-        const bool part = Ls % BK != 0 && nk > 0 && (EPI == 2 ? stage_list[nk - 1] == last : true);
-        f64_dma_loop<BK, B_J, WGM, WGN, TM, TN, EPI == 2>(
-            reinterpret_cast<double*>(&sm), Ap + i0, Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
-            g.M - i0, g.N - j0, nk, part ? static_cast<int>(Ls % BK) : 0, stage_list, acc);
+        // steps 0 .. nk-1, or the listed ones; the last step of the extent is
+        // partial when Ls is not a multiple of BK
+        const int64_t end = (Ls + BK - 1) / BK, part = Ls % BK != 0 ? end - 1 : -1;
+        double* const stages = reinterpret_cast<double*>(&sm);
+        const double* const At = Ap + i0;
+        const double* const Bt = Bp + (B_J ? j0 : j0 * g.sBj);
+        if constexpr (EPI == 2) {
+          int pos = 0;
+          f64_dma_loop<BK, B_J, WGM, WGN, TM, TN>(
+              stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, nk > 0 ? stage_list[0] : end, end, part,
+              static_cast<int>(Ls % BK), [&](int64_t) -> int64_t { return ++pos < nk ? stage_list[pos] : end; },
+              acc);
+        } else {
+          f64_dma_loop<BK, B_J, WGM, WGN, TM, TN>(stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, 0,
+                                                  nk, part, static_cast<int>(Ls % BK),
+                                                  [](int64_t t) { return t + 1; }, acc);
+        }
       }
     }
     if (!direct) {
