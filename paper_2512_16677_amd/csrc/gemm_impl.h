@@ -54,37 +54,39 @@ struct alignas(16) GemmSmem {
 };
 
 // ---------------------------------------------------------------------------
-// FP64 K loop with direct global -> LDS loads (global_load_lds_dwordx4: 16
-// bytes per lane, one 1 KB block per wave and instruction, written at the
-// wave-uniform LDS address in M0 plus 16 lane).  The operand tiles never pass
-// through registers, so the register staging of the generic loop, its LDS
-// stores and their address arithmetic go away.  Two stages: the loads of K
-// step k + 1 run under the products of step k.
+// K loop with direct global -> LDS loads (FP64 and FP32 operands;
+// global_load_lds_dwordx4: 16 bytes per lane, one 1 KB block per wave and
+// instruction, written at the wave-uniform LDS address in M0 plus 16 lane).
+// The operand tiles never pass through registers, so the register staging of
+// the generic loop, its LDS stores and their address arithmetic go away.  Two
+// stages: the loads of K step k + 1 run under the products of step k.
 //
-// Stage layout in LDS (no padding: the loads fill whole 1 KB blocks):
-//   A, i contiguous:  [BK][BM]  element (l, i) at l BM + (i ^ dma_xr<BM>(l))
-//   B, j contiguous:  [BK][BN]  element (l, j) at l BN + (j ^ dma_xr<BN>(l))
-//   B, l contiguous:  [BN][BK]  element (l, j) at j BK + 2 ((l/2) ^ dma_kx<BK>(j)) + l % 2
-// (BK = 16 or 32).  A half-wave's fragment read touches two consecutive rows
-// of an i- or j-contiguous tile; when a row is a multiple of 256 bytes,
-// dma_xr swaps the 128-byte halves of odd rows so that the two rows use
-// different banks.  The pair swizzle of the l-contiguous layout spreads the
-// 16 rows that one fragment read touches over all banks.
+// Stage layout in LDS (no padding: the loads fill whole 1 KB blocks; E = 2
+// doubles or 4 floats per 16 bytes):
+//   A, i contiguous:  [BK][BM]  element (l, i) at l BM + (i ^ dma_xr<T, BM>(l))
+//   B, j contiguous:  [BK][BN]  element (l, j) at l BN + (j ^ dma_xr<T, BN>(l))
+//   B, l contiguous:  [BN][BK]  element (l, j) at j BK + E ((l/E) ^ dma_kx<T, BK>(j)) + l % E
+// (BK = 16 or 32).  One fragment read (64 lanes; lane l reads column l % 16
+// of row l / 16 of a 16-wide block) is served in two halves of 256 bytes for
+// FP64 and in one for FP32.  dma_xr permutes the 16-element blocks of a row
+// (by XOR) so that the rows one such half touches fall on different banks;
+// dma_kx permutes the 16-byte slots of an l-contiguous row so that the 16 rows
+// a fragment read touches spread over all banks.
 //
-// Rows past the end of the matrix read a copy of the last in-range pair (or
-// row); their products land in outputs that are never stored.  A partial
-// last K step (the K extent not a multiple of 16) is staged through
+// Rows past the end of the matrix read a copy of the last in-range 16 bytes
+// (or row); their products land in outputs that are never stored.  A partial
+// last K step (the K extent not a multiple of BK) is staged through
 // registers instead, with zeros beyond the extent.
-template <int R>
+template <typename T, int R>
 __device__ __forceinline__ int dma_xr(int l) {
-  return R % 32 == 0 ? (l & 1) << 4 : 0;
+  if constexpr (sizeof(T) == 8) return R % 32 == 0 ? (l & 1) << 4 : 0;
+  return R % 64 == 0 ? (l & 3) << 4 : (R % 64 == 32 ? ((l >> 1) & 1) << 4 : 0);
 }
 
-// rows of 128 bytes (BK = 16): consecutive rows already alternate bank
-// halves, so pairs of rows share a swizzle; rows of 256 bytes: one per row
-template <int BK>
+template <typename T, int BK>
 __device__ __forceinline__ int dma_kx(int j) {
-  return BK == 16 ? (j >> 1) & 7 : j & 15;
+  if constexpr (sizeof(T) == 8) return BK == 16 ? (j >> 1) & 7 : j & 15;
+  return BK == 16 ? (j >> 2) & 3 : (j >> 1) & 7;
 }
 
 __device__ __forceinline__ uint32_t dma_lds_address(const void* p) {
@@ -106,33 +108,37 @@ __device__ __forceinline__ void dma_sync() {
 }
 
 // Whether this tile may take the direct-load loop: unit stride along i (A)
-// and along j or l (B), 16-byte aligned operands and even strides (every
-// 16-byte pair starts aligned), and an even row (and, for j-contiguous B,
-// column) count so that the clamped last pair is in range.
-template <int BK, bool B_J>
+// and along j or l (B), 16-byte aligned operands, strides that are multiples
+// of E = 16 / sizeof(T) (every 16-byte slot starts aligned), and a row (and,
+// for j-contiguous B, column) count that is a multiple of E, so that the
+// clamped last slot is in range.
+template <typename T, int BK, bool B_J>
 __device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, const void* Bp) {
-  if ((BK != 16 && BK != 32) || g.sAi != 1 || (g.sAl & 1) || (g.M & 1)) return false;
-  if (B_J ? (g.sBj != 1 || (g.sBl & 1) || (g.N & 1)) : (g.sBl != 1 || (g.sBj & 1))) return false;
+  constexpr int64_t E = 16 / sizeof(T);
+  if ((BK != 16 && BK != 32) || g.sAi != 1 || g.sAl % E != 0 || g.M % E != 0) return false;
+  if (B_J ? (g.sBj != 1 || g.sBl % E != 0 || g.N % E != 0) : (g.sBl != 1 || g.sBj % E != 0)) return false;
   return ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) == 0;
 }
 
 // K loop of one tile: At / Bt point at the tile's first row / column,
-// rows_a = M - i0 and rows_b = N - j0 (both even where pairs are clamped).
-// The K steps visited are first, next(first), next(next(first)), ... up to
-// the first one >= end, in increasing order (the caller's next() returns the
-// following step to visit, wave-uniform).  Step `part`, when visited, is the
-// last one and holds only tail < BK values of l.  The caller synchronises
-// the workgroup before the LDS is written again after the loop.
-template <int BK, bool B_J, int WGM, int WGN, int TM, int TN, class Next>
-__device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, const double* Bt, int64_t sAl,
-                                             int64_t sBl, int64_t sBj, int64_t rows_a, int64_t rows_b,
-                                             int64_t first, int64_t end, int64_t part, int tail, Next next,
-                                             typename Mfma<double>::v4 (&acc)[TM][TN]) {
+// rows_a = M - i0 and rows_b = N - j0 (multiples of E where slots are
+// clamped).  The K steps visited are first, next(first), next(next(first)),
+// ... up to the first one >= end, in increasing order (the caller's next()
+// returns the following step to visit, wave-uniform).  Step `part`, when
+// visited, is the last one and holds only tail < BK values of l.  The caller
+// synchronises the workgroup before the LDS is written again after the loop.
+template <typename T, int BK, bool B_J, int WGM, int WGN, int TM, int TN, class Next>
+__device__ __forceinline__ void dma_loop(T* stages, const T* At, const T* Bt, int64_t sAl, int64_t sBl,
+                                         int64_t sBj, int64_t rows_a, int64_t rows_b, int64_t first,
+                                         int64_t end, int64_t part, int tail, Next next,
+                                         typename Mfma<T>::v4 (&acc)[TM][TN]) {
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN, NW = WGM * WGN;
+  constexpr int E = 16 / sizeof(T), SZ = sizeof(T);
   static_assert(BK == 16 || BK == 32, "K step");
-  constexpr int NIA = BM * BK / 128, NI = (BM + BN) * BK / 128;  // 1 KB blocks per stage (A first)
+  constexpr int NIA = BM * BK * SZ / 1024, NI = (BM + BN) * BK * SZ / 1024;  // 1 KB blocks per stage (A first)
+  static_assert(NIA * 1024 == BM * BK * SZ && NI * 1024 == (BM + BN) * BK * SZ, "whole 1 KB blocks");
   constexpr int IPW = (NI + NW - 1) / NW;
-  constexpr int STAGE = (BM + BN) * BK;  // doubles
+  constexpr int STAGE = (BM + BN) * BK;  // elements
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WGN, wn = w % WGN;
   const int wu = __builtin_amdgcn_readfirstlane(w);
@@ -149,45 +155,45 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
     int ig = wu + NW * q;
     if (NI % NW != 0 && ig >= NI) ig -= NI;
     ldso[q] = static_cast<uint32_t>(ig) * 1024u;
-    const double* src;
+    const T* src;
     if (ig < NIA) {
-      const int sl = 64 * ig + lane, l = sl / (BM / 2);
-      const int i = (2 * (sl % (BM / 2))) ^ dma_xr<BM>(l);
-      src = At + (i < rows_a ? i : rows_a - 2) + l * sAl;
-      step[q] = static_cast<int64_t>(BK) * sAl * 8;
+      const int sl = 64 * ig + lane, l = sl / (BM / E);
+      const int i = (E * (sl % (BM / E))) ^ dma_xr<T, BM>(l);
+      src = At + (i < rows_a ? i : rows_a - E) + l * sAl;
+      step[q] = static_cast<int64_t>(BK) * sAl * SZ;
     } else if constexpr (B_J) {
-      const int sl = 64 * (ig - NIA) + lane, l = sl / (BN / 2);
-      const int j = (2 * (sl % (BN / 2))) ^ dma_xr<BN>(l);
-      src = Bt + (j < rows_b ? j : rows_b - 2) + l * sBl;
-      step[q] = static_cast<int64_t>(BK) * sBl * 8;
+      const int sl = 64 * (ig - NIA) + lane, l = sl / (BN / E);
+      const int j = (E * (sl % (BN / E))) ^ dma_xr<T, BN>(l);
+      src = Bt + (j < rows_b ? j : rows_b - E) + l * sBl;
+      step[q] = static_cast<int64_t>(BK) * sBl * SZ;
     } else {
-      const int sl = 64 * (ig - NIA) + lane, j = sl / (BK / 2);
-      const int l = 2 * ((sl % (BK / 2)) ^ dma_kx<BK>(j));
+      const int sl = 64 * (ig - NIA) + lane, j = sl / (BK / E);
+      const int l = E * ((sl % (BK / E)) ^ dma_kx<T, BK>(j));
       src = Bt + (j < rows_b ? j : rows_b - 1) * sBj + l;
-      step[q] = static_cast<int64_t>(BK) * 8;
+      step[q] = static_cast<int64_t>(BK) * SZ;
     }
     gp[q] = reinterpret_cast<const char*>(src);
   }
   auto issue = [&](int slot, int64_t kt) {
     const int64_t t = __builtin_amdgcn_readfirstlane(static_cast<int>(kt));
-    const uint32_t sb = lds0 + static_cast<uint32_t>(slot * STAGE * 8);
+    const uint32_t sb = lds0 + static_cast<uint32_t>(slot * STAGE * SZ);
 #pragma unroll
     for (int q = 0; q < IPW; ++q) dma_b128(gp[q] + t * step[q], sb + ldso[q]);
   };
   // fragments of sub-step kk + 1 are read before the products of kk
-  auto compute = [&](const double* sa) {
-    const double* sb = sa + BM * BK;
+  auto compute = [&](const T* sa) {
+    const T* sb = sa + BM * BK;
     const int ci = lane & 15, kq = lane >> 4;
-    double fa[2][TM], fb[2][TN];
+    T fa[2][TM], fb[2][TN];
     auto rd = [&](int kk, int u) {
       const int k = kk * 4 + kq;
 #pragma unroll
-      for (int a = 0; a < TM; ++a) fa[u][a] = sa[k * BM + (((wm * TM + a) * 16 + ci) ^ dma_xr<BM>(k))];
+      for (int a = 0; a < TM; ++a) fa[u][a] = sa[k * BM + (((wm * TM + a) * 16 + ci) ^ dma_xr<T, BM>(k))];
 #pragma unroll
       for (int b = 0; b < TN; ++b) {
         const int j = (wn * TN + b) * 16 + ci;
-        fb[u][b] = B_J ? sb[k * BN + (j ^ dma_xr<BN>(k))]
-                       : sb[j * BK + ((((k >> 1) ^ dma_kx<BK>(ci)) << 1) | (k & 1))];
+        fb[u][b] = B_J ? sb[k * BN + (j ^ dma_xr<T, BN>(k))]
+                       : sb[j * BK + (((k / E) ^ dma_kx<T, BK>(ci)) * E + k % E)];
       }
     };
     rd(0, 0);
@@ -197,28 +203,27 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<double>::op(fa[kk & 1][a], fb[kk & 1][b], acc[a][b]);
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::op(fa[kk & 1][a], fb[kk & 1][b], acc[a][b]);
     }
   };
 
   // the partial last step, through registers with zeros beyond l < tail and
   // beyond the last row / column
-  auto stage_tail = [&](double* st, int64_t t) {
+  auto stage_tail = [&](T* st, int64_t t) {
     constexpr int NT = 64 * NW;
     const int64_t l0 = t * BK;
     for (int e = tid; e < BM * BK; e += NT) {
       const int l = e / BM, i = e % BM;
-      st[l * BM + (i ^ dma_xr<BM>(l))] = l < tail && i < rows_a ? At[i + (l0 + l) * sAl] : 0.0;
+      st[l * BM + (i ^ dma_xr<T, BM>(l))] = l < tail && i < rows_a ? At[i + (l0 + l) * sAl] : T(0);
     }
-    double* sb = st + BM * BK;
+    T* sb = st + BM * BK;
     for (int e = tid; e < BN * BK; e += NT) {
       if constexpr (B_J) {
         const int l = e / BN, j = e % BN;
-        sb[l * BN + (j ^ dma_xr<BN>(l))] = l < tail && j < rows_b ? Bt[j + (l0 + l) * sBl] : 0.0;
+        sb[l * BN + (j ^ dma_xr<T, BN>(l))] = l < tail && j < rows_b ? Bt[j + (l0 + l) * sBl] : T(0);
       } else {
         const int j = e / BK, l = e % BK;
-        sb[j * BK + ((((l >> 1) ^ dma_kx<BK>(j)) << 1) | (l & 1))] =
-            l < tail && j < rows_b ? Bt[j * sBj + l0 + l] : 0.0;
+        sb[j * BK + (((l / E) ^ dma_kx<T, BK>(j)) * E + l % E)] = l < tail && j < rows_b ? Bt[j * sBj + l0 + l] : T(0);
       }
     }
   };
@@ -245,7 +250,7 @@ __device__ __forceinline__ void f64_dma_loop(double* stages, const double* At, c
   if (cur < end) {
     // the partial step, into the stage last read two steps earlier (before
     // every wave passed the barrier of the step in between)
-    double* st = stages + slot * STAGE;
+    T* st = stages + slot * STAGE;
     stage_tail(st, cur);
     __syncthreads();
     compute(st);
@@ -278,9 +283,11 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
   constexpr int NT = 64 * WGM * WGN;
   constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
   constexpr int EA = (BM * BK + NT - 1) / NT, EB = (BK * BN + NT - 1) / NT;
-  // FP64 products with i-contiguous A may take the direct-load K loop
-  constexpr bool kDirect = std::is_same<T, double>::value && std::is_same<TA, double>::value &&
-                           std::is_same<TB, double>::value && (BK == 16 || BK == 32) && A_I && EPI != 5;
+  // FP64 / FP32 products with i-contiguous A and unconverted operands may
+  // take the direct-load K loop
+  constexpr bool kDirect = (std::is_same<T, double>::value || std::is_same<T, float>::value) &&
+                           std::is_same<TA, T>::value && std::is_same<TB, T>::value && (BK == 16 || BK == 32) &&
+                           A_I && EPI != 5;
   typedef typename Mfma<T>::v4 v4;
   auto& As = sm.A;
   auto& Bs = sm.B;
@@ -415,10 +422,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     };
     bool direct = false;
     if constexpr (kDirect) {
-      if (dma_tile_ok<BK, B_J>(g, Ap, Bp)) {
+      if (dma_tile_ok<T, BK, B_J>(g, Ap, Bp)) {
         direct = true;
-        f64_dma_loop<BK, B_J, WGM, WGN, TM, TN>(
-            reinterpret_cast<double*>(&sm), Ap + i0, Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
+        dma_loop<T, BK, B_J, WGM, WGN, TM, TN>(
+            reinterpret_cast<T*>(&sm), Ap + i0, Bp + (B_J ? j0 : j0 * g.sBj), g.sAl, g.sBl, g.sBj,
             g.M - i0, g.N - j0, next(0), nk, Ls % BK != 0 ? nk - 1 : -1, static_cast<int>(Ls % BK),
             [&](int64_t t) { return next(t + 1); }, acc);
       }
@@ -458,24 +465,24 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
     };
     bool direct = false;
     if constexpr (kDirect) {
-      if (dma_tile_ok<BK, B_J>(g, Ap, Bp)) {
+      if (dma_tile_ok<T, BK, B_J>(g, Ap, Bp)) {
         direct = true;
         // steps 0 .. nk-1, or the listed ones; the last step of the extent is
         // partial when Ls is not a multiple of BK
         const int64_t end = (Ls + BK - 1) / BK, part = Ls % BK != 0 ? end - 1 : -1;
-        double* const stages = reinterpret_cast<double*>(&sm);
-        const double* const At = Ap + i0;
-        const double* const Bt = Bp + (B_J ? j0 : j0 * g.sBj);
+        T* const stages = reinterpret_cast<T*>(&sm);
+        const T* const At = Ap + i0;
+        const T* const Bt = Bp + (B_J ? j0 : j0 * g.sBj);
         if constexpr (EPI == 2) {
           int pos = 0;
-          f64_dma_loop<BK, B_J, WGM, WGN, TM, TN>(
+          dma_loop<T, BK, B_J, WGM, WGN, TM, TN>(
               stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, nk > 0 ? stage_list[0] : end, end, part,
               static_cast<int>(Ls % BK), [&](int64_t) -> int64_t { return ++pos < nk ? stage_list[pos] : end; },
               acc);
         } else {
-          f64_dma_loop<BK, B_J, WGM, WGN, TM, TN>(stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, 0,
-                                                  nk, part, static_cast<int>(Ls % BK),
-                                                  [](int64_t t) { return t + 1; }, acc);
+          dma_loop<T, BK, B_J, WGM, WGN, TM, TN>(stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, 0, nk,
+                                                 part, static_cast<int>(Ls % BK), [](int64_t t) { return t + 1; },
+                                                 acc);
         }
       }
     }
