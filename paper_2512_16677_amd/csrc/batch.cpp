@@ -245,6 +245,7 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.sAi = 1;
     g.sAl = 5 * mp.Pp;
     g.oAc = mp.Pp;
+    g.pad_ok = 3;  // AO rows padded to Pp points, C^T rows to Np MOs
     if (planes) {
       g.A2 = ao_lo;
       g.B = c->d_Cb_hi.p;

@@ -706,6 +706,7 @@ GemmArgs gbar_args(Prec prec, const void* w, const void* w_lo, int64_t Nw, const
   g.A = C;  // C [n][k]
   g.sAi = 1;
   g.sAl = Kp;
+  g.pad_ok = 1;  // rows padded to Kp AOs
   g.B = w;  // W [p][c][n]
   g.sBl = 1;
   g.sBj = 5 * N;
@@ -753,6 +754,7 @@ qmk_status get_mo_vgl_screened(qmk_ctx ctx, void* out, int32_t dtype, hipStream_
   ga.sAi = 1;
   ga.sAl = 5 * Pp;
   ga.oAc = Pp;
+  ga.pad_ok = 3;  // AO rows padded to Pp points, C^T rows to Np MOs
   const bool planes = ctx->mode == QMK_MIXED_BF16X3;
   if (planes) {  // sorted AO array as bf16 hi / lo planes, C [n][k] split
     ga.A2 = static_cast<const uint16_t*>(ctx->aos.p) + ctx->aos_Kp * 5 * Pp;
@@ -1355,6 +1357,7 @@ qmk_status qmk_get_mo_vgl(qmk_ctx ctx, void* out, int64_t size_max, int32_t dtyp
   ga.sAi = 1;
   ga.sAl = 5 * Pp;
   ga.oAc = Pp;
+  ga.pad_ok = 3;  // AO rows padded to Pp points, C^T rows to Np MOs
   if (ctx->mode == QMK_MIXED_BF16X3) {
     // AO array as bf16 hi / lo planes, C [n][k] split (reduction index contiguous)
     ga.A2 = static_cast<const uint16_t*>(ctx->ao.p) + ctx->ao_Kp * 5 * Pp;
@@ -1418,6 +1421,7 @@ qmk_status qmk_get_mo_value(qmk_ctx ctx, void* out, int64_t size_max, int32_t dt
   ga.A = plane;
   ga.sAi = 1;
   ga.sAl = row;
+  ga.pad_ok = 3;  // value rows padded to whole point blocks, C^T rows to Np MOs
   ga.B = ctx->d_Ct.p;
   ga.sBl = ctx->Np;
   ga.sBj = 1;
@@ -1520,6 +1524,7 @@ qmk_status qmk_get_density(qmk_ctx ctx, const double* occ, int64_t occ_num, doub
   ga.A = plane;
   ga.sAi = 1;
   ga.sAl = row;
+  ga.pad_ok = 3;  // value rows padded to whole point blocks, occupied C^T rows to Nop MOs
   ga.B = ctx->d_Cocc_t.p;
   ga.sBl = ctx->Nop;
   ga.sBj = 1;

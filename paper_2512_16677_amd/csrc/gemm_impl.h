@@ -73,8 +73,9 @@ struct alignas(16) GemmSmem {
 // dma_kx permutes the 16-byte slots of an l-contiguous row so that the 16 rows
 // a fragment read touches spread over all banks.
 //
-// Rows past the end of the matrix read a copy of the last in-range 16 bytes
-// (or row); their products land in outputs that are never stored.  A partial
+// Rows past the end of the matrix read a copy of the last 16 bytes that hold
+// an in-range element (or of the last row); their products land in outputs
+// that are never stored.  A partial
 // last K step (the K extent not a multiple of BK) is staged through
 // registers instead, with zeros beyond the extent.
 template <typename T, int R>
@@ -110,19 +111,21 @@ __device__ __forceinline__ void dma_sync() {
 // Whether this tile may take the direct-load loop: unit stride along i (A)
 // and along j or l (B), 16-byte aligned operands, strides that are multiples
 // of E = 16 / sizeof(T) (every 16-byte slot starts aligned), and a row (and,
-// for j-contiguous B, column) count that is a multiple of E, so that the
-// clamped last slot is in range.
+// for j-contiguous B, column) count that is a multiple of E or padded
+// (GemmArgs::pad_ok), so that the last slot is in range.
 template <typename T, int BK, bool B_J>
 __device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, const void* Bp) {
   constexpr int64_t E = 16 / sizeof(T);
-  if ((BK != 16 && BK != 32) || g.sAi != 1 || g.sAl % E != 0 || g.M % E != 0) return false;
-  if (B_J ? (g.sBj != 1 || g.sBl % E != 0 || g.N % E != 0) : (g.sBl != 1 || g.sBj % E != 0)) return false;
+  if ((BK != 16 && BK != 32) || g.sAi != 1 || g.sAl % E != 0 || (g.M % E != 0 && !(g.pad_ok & 1))) return false;
+  if (B_J ? (g.sBj != 1 || g.sBl % E != 0 || (g.N % E != 0 && !(g.pad_ok & 2)))
+          : (g.sBl != 1 || g.sBj % E != 0))
+    return false;
   return ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) == 0;
 }
 
 // K loop of one tile: At / Bt point at the tile's first row / column,
-// rows_a = M - i0 and rows_b = N - j0 (multiples of E where slots are
-// clamped).  The K steps visited are first, next(first), next(next(first)),
+// rows_a = M - i0 and rows_b = N - j0 (slots past them are clamped to the
+// last slot that holds an in-range element).  The K steps visited are first, next(first), next(next(first)),
 // ... up to the first one >= end, in increasing order (the caller's next()
 // returns the following step to visit, wave-uniform).  Step `part`, when
 // visited, is the last one and holds only tail < BK values of l.  The caller
@@ -159,12 +162,12 @@ __device__ __forceinline__ void dma_loop(T* stages, const T* At, const T* Bt, in
     if (ig < NIA) {
       const int sl = 64 * ig + lane, l = sl / (BM / E);
       const int i = (E * (sl % (BM / E))) ^ dma_xr<T, BM>(l);
-      src = At + (i < rows_a ? i : rows_a - E) + l * sAl;
+      src = At + (i < rows_a ? i : (rows_a - 1) & ~int64_t(E - 1)) + l * sAl;
       step[q] = static_cast<int64_t>(BK) * sAl * SZ;
     } else if constexpr (B_J) {
       const int sl = 64 * (ig - NIA) + lane, l = sl / (BN / E);
       const int j = (E * (sl % (BN / E))) ^ dma_xr<T, BN>(l);
-      src = Bt + (j < rows_b ? j : rows_b - E) + l * sBl;
+      src = Bt + (j < rows_b ? j : (rows_b - 1) & ~int64_t(E - 1)) + l * sBl;
       step[q] = static_cast<int64_t>(BK) * sBl * SZ;
     } else {
       const int sl = 64 * (ig - NIA) + lane, j = sl / (BK / E);

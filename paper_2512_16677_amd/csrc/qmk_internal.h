@@ -146,6 +146,11 @@ struct GemmArgs {
   // 2: the M tiles of one N tile run back to back on one XCD (B tile reused;
   // for products with few M tiles and a long N axis).
   int32_t map_slab;
+  // Direct-load products only.  Bit 0: every row l of A is readable along i
+  // up to M rounded up to 16 bytes (a padded, allocated stride); bit 1: the
+  // same for the rows of an l-major B along j up to N.  The values read
+  // there only reach outputs that are not stored.
+  int32_t pad_ok;
   // Density epilogue only: occupation of column j (device, N entries).
   const double* occ;
   // Screened forward product only: activity bitmap of (64-point block,
