@@ -1,8 +1,9 @@
 """Every tile shape of the FP64 and FP32 products on shapes that take each
 branch of their K loop: the direct global-to-LDS loop with whole K steps,
-the same loop with a partial last K step staged through registers, and the
-register-staged loop (odd or non-multiple-of-four row counts, which the
-direct loop does not take).  Forward and adjoint against the oracle: FP64 at
+the same loop with a partial last K step staged through registers, the
+same loop reading the padded rows of internal operands (odd point and MO
+counts), and the register-staged loop (the dC product on an odd MO count,
+whose caller-owned W has no padding).  Forward and adjoint against the oracle: FP64 at
 1e-12 (rows) / 1e-11 (gradients), FP32 at its stated tolerances with the
 oracle at the same B.
 
