@@ -265,7 +265,8 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.N = mp.N;
     g.L = g.Lchunk = mp.K;
   } else if (kind == GemmKind::kGbar) {
-    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, mp.Nw, c->d_C.p, c->d_Ctb_hi.p,
+    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, planes ? mp.Nw : mp.N, c->d_C.p,
+                  c->d_Ctb_hi.p,
                   c->d_Ctb_lo.p, gbp, mp.P, mp.Pp, mp.K, mp.Kp, mp.N, mp.Np);
   } else {
     g.A = w;

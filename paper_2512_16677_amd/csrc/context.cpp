@@ -707,10 +707,10 @@ GemmArgs gbar_args(Prec prec, const void* w, const void* w_lo, int64_t Nw, const
   g.sAi = 1;
   g.sAl = Kp;
   g.pad_ok = 1;  // rows padded to Kp AOs
-  g.B = w;  // W [p][c][n]
+  g.B = w;  // W [p][c][n], rows of Nw
   g.sBl = 1;
-  g.sBj = 5 * N;
-  g.oBc = N;
+  g.sBj = 5 * Nw;
+  g.oBc = Nw;
   g.D = gbar;
   g.sDi = 5 * Pp;
   g.sDj = 1;
@@ -1592,15 +1592,32 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   int w32 = w_dtype == QMK_F32;
   const int f32 = ctx->f32_storage() ? 1 : 0;
   const Prec prec = gemm_prec(ctx);
+  // row length of W as the products read it ([p][c][ldw]); the copies below
+  // pad their rows with zeros
+  int64_t ldw = N;
+  int w_pad = 0;
   if (!w32 && ctx->mode == QMK_MIXED_F32) {
     // the FP32 products round W to FP32 as they load it; one streaming pass
     // does the same rounding and halves the bytes both products read
-    const int64_t n = P * 5 * N;
-    QMK_HIP(ctx, ctx->w_f32.ensure(static_cast<size_t>(n) * 4), "alloc FP32 W");
+    ldw = round_up(N, 4);
+    w_pad = 1;
+    QMK_HIP(ctx, ctx->w_f32.ensure(static_cast<size_t>(P * 5 * ldw) * 4), "alloc FP32 W");
     LaunchTimer lt(ctx, QMK_KERNEL_CONVERT, s);
-    QMK_HIP(ctx, launch_f64_to_f32(static_cast<const double*>(w), ctx->w_f32.as<float>(), n, s), "convert W");
+    QMK_HIP(ctx, launch_pad_rows(w, 0, ctx->w_f32.p, 1, P * 5, N, ldw, s), "convert W");
     w = ctx->w_f32.p;
     w32 = 1;
+  } else if ((ctx->mode == QMK_FP64 && !w32) || (ctx->mode == QMK_MIXED_F32 && w32)) {
+    // the products load W in 16-byte pieces when its rows start 16-byte
+    // aligned; other row lengths (or a misaligned W) get a padded copy
+    const int64_t e = w32 ? 4 : 2;
+    if ((5 * N) % e != 0 || reinterpret_cast<uintptr_t>(w) % 16 != 0) {
+      ldw = round_up(N, 4);
+      w_pad = 1;
+      QMK_HIP(ctx, ctx->w_f32.ensure(static_cast<size_t>(P * 5 * ldw) * (w32 ? 4 : 8)), "alloc padded W");
+      LaunchTimer lt(ctx, QMK_KERNEL_CONVERT, s);
+      QMK_HIP(ctx, launch_pad_rows(w, w32, ctx->w_f32.p, w32, P * 5, N, ldw, s), "pad W");
+      w = ctx->w_f32.p;
+    }
   }
   // BF16x3 mode: W split once into bf16 hi / lo planes [Pp][5][Nw], read by
   // both products (the W C product along n, the W^T ao product along p)
@@ -1621,7 +1638,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
   if (scr && !planes) {
     // W in the sorted point order, once, so that both products read it with
     // their ordinary loaders
-    const int64_t row_bytes = 5 * N * (w32 ? 4 : 8);
+    const int64_t row_bytes = 5 * ldw * (w32 ? 4 : 8);
     QMK_HIP(ctx, ctx->w_sorted.ensure(static_cast<size_t>(P * row_bytes)), "alloc sorted W");
     LaunchTimer lt(ctx, QMK_KERNEL_SORT, s);
     QMK_HIP(ctx, launch_gather_rows(w, ctx->d_perm.as<int32_t>(), P, row_bytes, ctx->w_sorted.p, s),
@@ -1638,7 +1655,7 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       ctx->gbar_Kp = Kp;
       ctx->gbar_f32 = f32;
     }
-    GemmArgs ga = gbar_args(prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, Nw, ctx->d_C.p,
+    GemmArgs ga = gbar_args(prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, planes ? Nw : ldw, ctx->d_C.p,
                             ctx->d_Ctb_hi.p, ctx->d_Ctb_lo.p, ctx->gbar.p, P, Pp, K, Kp, N, Np);
     if (scr) screen(ga);
     GemmProblem pb{GemmKind::kGbar, prec, w32, f32, ga.M, ga.N, N};
@@ -1723,9 +1740,10 @@ qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, doubl
       GemmArgs ga{};
       ga.A = w;
       ga.sAi = 1;
-      ga.sAl = 5 * N;
-      ga.oAc = N;
-      ga.oAs = chunk * 5 * N;
+      ga.sAl = 5 * ldw;
+      ga.oAc = ldw;
+      ga.oAs = chunk * 5 * ldw;
+      ga.pad_ok = w_pad;  // the FP32 copy of W has rows padded to ldw MOs
       ga.B = ao_arr;
       ga.sBl = 1;
       ga.sBj = 5 * Pp;

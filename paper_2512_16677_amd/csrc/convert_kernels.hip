@@ -4,21 +4,34 @@
 // The FP32 products round each FP64 weight to FP32 as they load it; doing
 // that once per call in a streaming pass (round to nearest, as the loaders
 // do) gives the products the same values at half the bytes, and lets them
-// run their FP32-operand instantiations.
+// run their FP32-operand instantiations.  The copy pads its rows to a
+// multiple of four weights, so that both products can load it in 16-byte
+// pieces; the same padded copy (without conversion) serves weights whose row
+// length does not allow that.
 #include "qmk_internal.h"
 
 namespace qmk {
 namespace {
 
-__global__ __launch_bounds__(256) void f64_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
-                                                         int64_t n, int vec) {
-  const int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
-  if (vec && i + 4 <= n) {
-    const double4 v = *reinterpret_cast<const double4*>(src + i);
-    *reinterpret_cast<float4*>(dst + i) =
-        make_float4(static_cast<float>(v.x), static_cast<float>(v.y), static_cast<float>(v.z), static_cast<float>(v.w));
+// rows of n source values -> rows of ldd destination values (ldd a multiple
+// of 4, zeros from n on; FP64 -> FP32 rounds to nearest); one thread per four
+// output values of a row
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void pad_rows_kernel(const TS* __restrict__ src, TD* __restrict__ dst,
+                                                       int64_t rows, int64_t n, int64_t ldd) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x, qpr = ldd / 4;
+  if (q >= rows * qpr) return;
+  const int64_t row = q / qpr, c0 = (q - row * qpr) * 4;
+  const TS* sr = src + row * n;
+  TD v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = c0 + e < n ? static_cast<TD>(sr[c0 + e]) : TD(0);
+  TD* dr = dst + row * ldd + c0;
+  if constexpr (sizeof(TD) == 4) {
+    *reinterpret_cast<float4*>(dr) = make_float4(v[0], v[1], v[2], v[3]);
   } else {
-    for (int64_t k = i; k < min(i + 4, n); ++k) dst[k] = static_cast<float>(src[k]);
+    reinterpret_cast<double2*>(dr)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2*>(dr)[1] = make_double2(v[2], v[3]);
   }
 }
 
@@ -130,13 +143,24 @@ hipError_t launch_split_w_batch(const SplitJob* jobs, const int64_t* prefix, int
   return hipGetLastError();
 }
 
-hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 1023) / 1024;
+hipError_t launch_pad_rows(const void* src, int src_f32, void* dst, int dst_f32, int64_t rows, int64_t n,
+                           int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return hipSuccess;
+  // the vector stores need 16-byte aligned rows; FP32 -> FP64 is not offered
+  if (ldd < n || ldd % 4 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0 || (src_f32 && !dst_f32))
+    return hipErrorInvalidValue;
+  const int64_t blocks = (rows * (ldd / 4) + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  // vector loads and stores need 32-byte / 16-byte aligned pointers
-  const int vec = reinterpret_cast<uintptr_t>(src) % 32 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0;
-  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, src, dst, n, vec);
+  const dim3 grid(static_cast<unsigned>(blocks));
+  if (src_f32)
+    hipLaunchKernelGGL((pad_rows_kernel<float, float>), grid, dim3(256), 0, s, static_cast<const float*>(src),
+                       static_cast<float*>(dst), rows, n, ldd);
+  else if (dst_f32)
+    hipLaunchKernelGGL((pad_rows_kernel<double, float>), grid, dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<float*>(dst), rows, n, ldd);
+  else
+    hipLaunchKernelGGL((pad_rows_kernel<double, double>), grid, dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<double*>(dst), rows, n, ldd);
   return hipGetLastError();
 }
 

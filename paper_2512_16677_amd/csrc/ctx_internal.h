@@ -148,7 +148,8 @@ struct qmk_ctx_s {
   std::vector<double> een_key;  // coefficients and order behind een_q
 
   DevBuf gbar, ws_dc, ws_nuc, ws_elec;
-  DevBuf w_f32;  // FP32 copy of FP64 adjoint weights (FP32 mode)
+  DevBuf w_f32;  // adjoint weights with padded rows: the FP32 copy of FP64 W (FP32 mode), or a copy
+                 // of W whose own rows cannot be loaded in 16-byte pieces
   DevBuf w_split;  // adjoint weights as bf16 hi and lo planes [Pp][5][Nw] (BF16x3 mode)
   int64_t gbar_Pp = 0, gbar_Kp = 0;
   int gbar_f32 = -1;
@@ -209,8 +210,9 @@ Prec product_prec(qmk_ctx ctx, GemmKind kind);
 bool device_accessible(const void* p, int device);
 // Arguments of the product Gbar[k][c][p] = sum_n W[p][c][n] C[n][k].  Both
 // kernels compute Gbar with rows k and columns p; the FP64 / FP32 kernels read
-// C [n][k] and W, the BF16x3 kernel the split C^T planes (Ct_hi / Ct_lo) and
-// the split W planes (w / w_lo, [Pp][5][Nw]).
+// C [n][k] and W ([P][5][Nw]: rows of Nw >= N weights), the BF16x3 kernel the
+// split C^T planes (Ct_hi / Ct_lo) and the split W planes (w / w_lo,
+// [Pp][5][Nw]).
 GemmArgs gbar_args(Prec prec, const void* w, const void* w_lo, int64_t Nw, const void* C, const void* Ct_hi,
                    const void* Ct_lo, void* gbar, int64_t P, int64_t Pp, int64_t K, int64_t Kp,
                    int64_t N, int64_t Np);

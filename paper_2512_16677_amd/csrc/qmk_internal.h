@@ -301,9 +301,11 @@ hipError_t launch_een_finish(const double* part, int64_t slots, const double* j0
                              double* J, hipStream_t s);
 // The Jastrow product with its fused weighted reduction (FP64).
 hipError_t launch_gemm_jastrow(int cfg, const GemmArgs& g, hipStream_t s);
-// dst[i] = (float)src[i], round to nearest (vector accesses when src is
-// 32-byte and dst 16-byte aligned).
-hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+// Rows of n values -> rows of ldd values (ldd >= n, a multiple of 4; zeros
+// from n on; dst 16-byte aligned): FP64 -> FP32 (round to nearest), FP64 ->
+// FP64 or FP32 -> FP32.
+hipError_t launch_pad_rows(const void* src, int src_f32, void* dst, int dst_f32, int64_t rows, int64_t n,
+                           int64_t ldd, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 // dst row q = src row perm[q] for q < rows (rows of row_bytes bytes, a
 // multiple of 4).
