@@ -1,11 +1,14 @@
 """Every tile shape of the FP64 and FP32 products on shapes that take each
-branch of their K loop: the direct global-to-LDS loop with whole K steps,
-the same loop with a partial last K step staged through registers, the
-same loop reading the padded rows of internal operands (odd point and MO
-counts), and the register-staged loop (the dC product on an odd MO count,
-whose caller-owned W has no padding).  Forward and adjoint against the oracle: FP64 at
-1e-12 (rows) / 1e-11 (gradients), FP32 at its stated tolerances with the
-oracle at the same B.
+branch of their direct global-to-LDS K loop: whole K steps, a partial last
+K step staged through registers, reads into the padded rows of internal
+operands (odd point and MO counts), and weights whose rows cannot be loaded
+in 16-byte pieces (odd MO counts in FP64, FP32 weights with an MO count that
+is not a multiple of four), which the adjoint copies into padded rows first.
+Forward and adjoint against the oracle: FP64 at 1e-12 (rows) / 1e-11
+(gradients), FP32 at its stated tolerances with the oracle at the same B.
+(The register-staged loop that operands without unit stride or padding
+take is exercised by the batch tests: a batch reads each molecule's weights
+in place.)
 
 Shapes (P points, K AOs, N MOs; the forward product is P x N over K, G-bar
 K x P over N, dC N x K over P):
@@ -27,7 +30,7 @@ SHAPES = [(3, 5, 3), (5, 9, 4)]
 F32_TOL = {"value": 2e-6, "gradient": 2e-6, "laplacian": 2e-6, "grad": 1e-5}
 
 
-@pytest.mark.parametrize("mode", ["fp64", "mixed_f32"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed_f32", "mixed_f32_wf32"])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_every_tile_on_ragged_shapes(mode, shape):
     import paper_2512_16677_amd as q
@@ -36,8 +39,12 @@ def test_every_tile_on_ragged_shapes(mode, shape):
     assert (s.walk_num * s.elec_num, s.ao_num, s.mo_num) in ((69, 70, 35), (156, 120, 60))
     bits = 53 if mode == "fp64" else 24
     w = synth.adjoint_weights(s, seed=8)
+    if mode == "mixed_f32_wf32":
+        # FP32 weights from the caller; the oracle takes the same rounded values
+        w = w.astype(np.float32)
+        mode = "mixed_f32"
     ref_mo = oracle.mo_vgl(s, B=bits)
-    ref = oracle.adjoint(s, w, B=bits)
+    ref = oracle.adjoint(s, w.astype(np.float64), B=bits)
     wt = torch.from_numpy(w).cuda()
     ctx = q.Context.from_system(s, bits=bits, mode=mode)
     tried = 0
