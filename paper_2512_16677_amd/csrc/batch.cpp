@@ -42,6 +42,12 @@ struct MolPlan {
   size_t ao_off, gbar_off;  // elements of the AO / Gbar arenas
   size_t dc_off;            // doubles of the dC partial arena
   size_t w_off;             // bf16 elements of the split-W arena (hi plane, then lo)
+  // FP64 / FP32 modes: whether the products read a copy of W with rows padded
+  // to ldw weights (the caller's rows of N do not allow 16-byte loads), and
+  // its offset (elements of the padded-W arena)
+  bool pad_w;
+  int64_t ldw;
+  size_t wp_off;
   int64_t nsplit, chunk;
   size_t nuc_off;           // doubles of the nucleus partial arena
   int64_t n_waves;
@@ -71,7 +77,7 @@ struct qmk_batch_s {
   std::vector<int64_t> dims_key;
   std::vector<MolPlan> plan;
   bool planned = false;
-  DevBuf ao, gbar, ws_dc, ws_nuc, ws_elec, discard, wsplit;
+  DevBuf ao, gbar, ws_dc, ws_nuc, ws_elec, discard, wsplit, wpad;
   size_t max_smem = 0;
   int n_cu = 0;
 
@@ -83,9 +89,9 @@ struct qmk_batch_s {
   std::vector<GemmArgs> g_jobs[3];  // host copies of the product job tables
   DevBuf d_ao_items, d_g_items[3];
   DevBuf d_ao_jobs, d_adj_jobs, d_g_jobs[3], d_red_jobs, d_red_prefix, d_nred_jobs,
-      d_nred_prefix, d_split_jobs, d_split_prefix;
-  int n_red = 0, n_nred = 0, n_split = 0;
-  int64_t red_total = 0, nred_total = 0, split_total = 0;
+      d_nred_prefix, d_split_jobs, d_split_prefix, d_pad_jobs, d_pad_prefix;
+  int n_red = 0, n_nred = 0, n_split = 0, n_pad = 0;
+  int64_t red_total = 0, nred_total = 0, split_total = 0, pad_total = 0;
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -161,7 +167,7 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
   drop_graph(b);
   b->plan.clear();
   b->tile[0] = b->tile[1] = b->tile[2] = -1;
-  size_t ao = 0, dc = 0, nuc = 0, elec = 0, dis = 0, wsp = 0;
+  size_t ao = 0, dc = 0, nuc = 0, elec = 0, dis = 0, wsp = 0, wpd = 0;
   const bool planes = b->prec == Prec::kBF16P;
   b->max_smem = 0;
   std::vector<std::pair<int64_t, WorkItem>> ao_items;
@@ -187,6 +193,11 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
     dc += static_cast<size_t>(5 * mp.nsplit * mp.Np * mp.Kp);
     mp.w_off = wsp;
     if (planes) wsp += static_cast<size_t>(2 * mp.Pp * 5 * mp.Nw);
+    // the products load W in 16-byte pieces: 2 FP64 or 4 FP32 weights
+    mp.pad_w = !planes && (5 * mp.N) % (b->prec == Prec::kF64 ? 2 : 4) != 0;
+    mp.ldw = mp.pad_w ? round_up(mp.N, 4) : mp.N;
+    mp.wp_off = wpd;
+    if (mp.pad_w) wpd += static_cast<size_t>(mp.P * 5 * mp.ldw);
     mp.n_waves = (mp.P + 255) / 256 * 4;
     mp.nuc_off = nuc;
     nuc += static_cast<size_t>(mp.n_waves * mp.nucl_dev * 3);
@@ -220,13 +231,16 @@ qmk_status make_plan(qmk_batch b, hipStream_t s) {
   QMK_BHIP(b, b->ws_elec.ensure(std::max<size_t>(elec, 1) * 8), "alloc batch electron partials");
   QMK_BHIP(b, b->discard.ensure(std::max<size_t>(dis, 1) * 8), "alloc batch discard arena");
   if (planes) QMK_BHIP(b, b->wsplit.ensure(std::max<size_t>(wsp, 1) * 2), "alloc batch split W");
+  if (wpd) QMK_BHIP(b, b->wpad.ensure(wpd * 8), "alloc batch padded W");
   QMK_BHIP(b, upload(b->d_ao_items, b->ao_items, s), "upload AO work list");
   b->planned = true;
   return QMK_OK;
 }
 
 // Per-molecule GEMM arguments, as the single-context calls build them.
-GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w) {
+// w (FP64 / FP32 modes): rows of ldw weights; pad: rows padded with zeros.
+GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w, int64_t ldw = 0,
+                  int pad = 0) {
   qmk_ctx c = b->ctxs[m];
   const MolPlan& mp = b->plan[m];
   const bool planes = b->prec == Prec::kBF16P;
@@ -265,15 +279,16 @@ GemmArgs gemm_job(qmk_batch b, size_t m, GemmKind kind, void* out, const void* w
     g.N = mp.N;
     g.L = g.Lchunk = mp.K;
   } else if (kind == GemmKind::kGbar) {
-    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, planes ? mp.Nw : mp.N, c->d_C.p,
+    g = gbar_args(b->prec, planes ? static_cast<const void*>(w_hi) : w, w_lo, planes ? mp.Nw : ldw, c->d_C.p,
                   c->d_Ctb_hi.p,
                   c->d_Ctb_lo.p, gbp, mp.P, mp.Pp, mp.K, mp.Kp, mp.N, mp.Np);
   } else {
     g.A = w;
     g.sAi = 1;
-    g.sAl = 5 * mp.N;
-    g.oAc = mp.N;
-    g.oAs = mp.chunk * 5 * mp.N;
+    g.sAl = 5 * ldw;
+    g.oAc = ldw;
+    g.oAs = mp.chunk * 5 * ldw;
+    g.pad_ok = pad;
     g.B = aop;
     g.sBl = 1;
     g.sBj = 5 * mp.Pp;
@@ -396,6 +411,10 @@ qmk_status enqueue_all(qmk_batch b, bool with_adj, hipStream_t s) {
   };
   QMK_BHIP(b, gemm(GemmKind::kForward), "batch contraction");
   if (!with_adj) return QMK_OK;
+  if (b->n_pad)
+    QMK_BHIP(b, launch_pad_rows_batch(b->d_pad_jobs.as<PadJob>(), b->d_pad_prefix.as<int64_t>(), b->n_pad,
+                                      b->pad_total, b->tile_w32, s),
+             "batch W padding");
   if (b->prec == Prec::kBF16P)
     QMK_BHIP(b, launch_split_w_batch(b->d_split_jobs.as<SplitJob>(), b->d_split_prefix.as<int64_t>(), b->n_split,
                                      b->split_total, b->tile_w32, s),
@@ -526,6 +545,8 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
   std::vector<int64_t> nred_prefix{0};
   std::vector<SplitJob> split;
   std::vector<int64_t> split_prefix{0};
+  std::vector<PadJob> pads;
+  std::vector<int64_t> pad_prefix{0};
   for (size_t i = 0; i < n; ++i) {
     qmk_ctx c = b->ctxs[i];
     const MolPlan& mp = b->plan[i];
@@ -564,8 +585,21 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
         if (nj > 0xffffffffLL) return bfail(b, QMK_SIZE, "context " + std::to_string(i) + ": W too large to split");
         split_prefix.push_back(split_prefix.back() + nj);
       }
-      gj[1].push_back(gemm_job(b, i, GemmKind::kGbar, nullptr, ws[i]));
-      gj[2].push_back(gemm_job(b, i, GemmKind::kDcoef, nullptr, ws[i]));
+      // FP64 / FP32 products on weights of their own type read a padded copy
+      // where the caller's rows do not allow 16-byte loads
+      const void* wj = ws[i];
+      int64_t ldw = mp.N;
+      int padded = 0;
+      if (mp.pad_w && ((b->prec == Prec::kF64 && !w32) || (b->prec == Prec::kF32 && w32))) {
+        char* dst = static_cast<char*>(b->wpad.p) + mp.wp_off * (w32 ? 4 : 8);
+        pads.push_back(PadJob{ws[i], dst, 5 * mp.P, mp.N, mp.ldw});
+        pad_prefix.push_back(pad_prefix.back() + 5 * mp.P * (mp.ldw / 4));
+        wj = dst;
+        ldw = mp.ldw;
+        padded = 1;
+      }
+      gj[1].push_back(gemm_job(b, i, GemmKind::kGbar, nullptr, wj, ldw, padded));
+      gj[2].push_back(gemm_job(b, i, GemmKind::kDcoef, nullptr, wj, ldw, padded));
       red.push_back(RedJob{static_cast<double*>(b->ws_dc.p) + mp.dc_off, 5 * mp.nsplit, mp.N, mp.K,
                            mp.Kp, mp.Np * mp.Kp, dc, mp.K});
       red_prefix.push_back(red_prefix.back() + mp.N * mp.K);
@@ -589,6 +623,10 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
     QMK_BHIP(b, upload(b->d_split_prefix, split_prefix, s), "upload jobs");
     b->n_split = static_cast<int>(split.size());
     b->split_total = split_prefix.back();
+    QMK_BHIP(b, upload(b->d_pad_jobs, pads, s), "upload jobs");
+    QMK_BHIP(b, upload(b->d_pad_prefix, pad_prefix, s), "upload jobs");
+    b->n_pad = static_cast<int>(pads.size());
+    b->pad_total = pad_prefix.back();
     b->n_red = static_cast<int>(red.size());
     b->red_total = red_prefix.back();
     b->n_nred = static_cast<int>(nred.size());
@@ -611,6 +649,9 @@ qmk_status qmk_batch_run(qmk_batch b, void* const* outs, int32_t dtype, const vo
   addrs.push_back(b->d_split_jobs.p);
   addrs.push_back(b->d_split_prefix.p);
   addrs.push_back(b->wsplit.p);
+  addrs.push_back(b->d_pad_jobs.p);
+  addrs.push_back(b->d_pad_prefix.p);
+  addrs.push_back(b->wpad.p);
   for (int k = 0; k < 3; ++k) {
     addrs.push_back(b->d_g_jobs[k].p);
     addrs.push_back(b->d_g_items[k].p);

@@ -14,14 +14,12 @@ namespace qmk {
 namespace {
 
 // rows of n source values -> rows of ldd destination values (ldd a multiple
-// of 4, zeros from n on; FP64 -> FP32 rounds to nearest); one thread per four
-// output values of a row
+// of 4, zeros from n on; FP64 -> FP32 rounds to nearest); output quad q of
+// the copy (four values of one row)
 template <typename TS, typename TD>
-__global__ __launch_bounds__(256) void pad_rows_kernel(const TS* __restrict__ src, TD* __restrict__ dst,
-                                                       int64_t rows, int64_t n, int64_t ldd) {
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x, qpr = ldd / 4;
-  if (q >= rows * qpr) return;
-  const int64_t row = q / qpr, c0 = (q - row * qpr) * 4;
+__device__ __forceinline__ void pad_quad(const TS* __restrict__ src, TD* __restrict__ dst, int64_t n, int64_t ldd,
+                                         int64_t q) {
+  const int64_t qpr = ldd / 4, row = q / qpr, c0 = (q - row * qpr) * 4;
   const TS* sr = src + row * n;
   TD v[4];
 #pragma unroll
@@ -33,6 +31,25 @@ __global__ __launch_bounds__(256) void pad_rows_kernel(const TS* __restrict__ sr
     reinterpret_cast<double2*>(dr)[0] = make_double2(v[0], v[1]);
     reinterpret_cast<double2*>(dr)[1] = make_double2(v[2], v[3]);
   }
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void pad_rows_kernel(const TS* __restrict__ src, TD* __restrict__ dst,
+                                                       int64_t rows, int64_t n, int64_t ldd) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= rows * (ldd / 4)) return;
+  pad_quad(src, dst, n, ldd, q);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pad_rows_batch_kernel(const PadJob* __restrict__ jobs,
+                                                             const int64_t* __restrict__ prefix, int n_jobs,
+                                                             int64_t total) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int jb = find_job(prefix, n_jobs, e);
+  const PadJob& j = jobs[jb];
+  pad_quad(static_cast<const T*>(j.src), static_cast<T*>(j.dst), j.n, j.ldd, e - prefix[jb]);
 }
 
 // W[p][c][n] -> hi, lo planes [Pp][5][Nw]: hi = bf16(x), lo = bf16(x - hi) of
@@ -139,6 +156,20 @@ hipError_t launch_split_w_batch(const SplitJob* jobs, const int64_t* prefix, int
                        prefix, n_jobs, total);
   else
     hipLaunchKernelGGL(split_w_batch_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, jobs,
+                       prefix, n_jobs, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_rows_batch(const PadJob* jobs, const int64_t* prefix, int n_jobs, int64_t total, int f32,
+                                 hipStream_t s) {
+  if (total <= 0 || n_jobs <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (f32)
+    hipLaunchKernelGGL(pad_rows_batch_kernel<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, jobs,
+                       prefix, n_jobs, total);
+  else
+    hipLaunchKernelGGL(pad_rows_batch_kernel<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, jobs,
                        prefix, n_jobs, total);
   return hipGetLastError();
 }

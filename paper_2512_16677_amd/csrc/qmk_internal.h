@@ -443,6 +443,17 @@ struct SplitJob {
 };
 hipError_t launch_split_w_batch(const SplitJob* jobs, const int64_t* prefix, int n_jobs, int64_t total,
                                 int w_is_f32, hipStream_t s);
+// One molecule's weights copied into padded rows: rows rows of n values from
+// src into rows of ldd (a multiple of 4, zeros from n on) at dst.
+struct PadJob {
+  const void* src;
+  void* dst;
+  int64_t rows, n, ldd;
+};
+// Every job of the list, same element type (FP32 when f32, else FP64);
+// prefix[j] = sum of rows * ldd / 4 over the jobs before j, total the sum.
+hipError_t launch_pad_rows_batch(const PadJob* jobs, const int64_t* prefix, int n_jobs, int64_t total, int f32,
+                                 hipStream_t s);
 // Resident blocks per compute unit of the persistent kernels.
 int ao_persist_blocks_per_cu(int f32, size_t smem);
 int adj_persist_blocks_per_cu(int f32, size_t smem);
