@@ -314,7 +314,10 @@ qmk_status qmk_jastrow_een(qmk_ctx ctx, int64_t nord, double kappa, int64_t n_te
  * reads the AO array that the forward pass left for the same points
  * (Section 2.2: a value is kept until one of its inputs changes); see
  * qmk_set_ao_retention.  Deterministic: the same inputs give bitwise the
- * same outputs. */
+ * same outputs.  The context may copy w into an internal buffer with padded
+ * rows (FP64 weights in the FP32 mode, rounded to FP32; weights whose rows
+ * of 5 * mo values cannot be read in 16-byte pieces); w itself is only
+ * read. */
 qmk_status qmk_mo_vgl_adjoint(qmk_ctx ctx, const void* w, int32_t w_dtype, double* d_coef,
                               double* d_elec, double* d_nucl, void* hip_stream);
 

@@ -125,11 +125,12 @@ __device__ __forceinline__ bool dma_tile_ok(const GemmArgs& g, const void* Ap, c
 
 // K loop of one tile: At / Bt point at the tile's first row / column,
 // rows_a = M - i0 and rows_b = N - j0 (slots past them are clamped to the
-// last slot that holds an in-range element).  The K steps visited are first, next(first), next(next(first)),
-// ... up to the first one >= end, in increasing order (the caller's next()
-// returns the following step to visit, wave-uniform).  Step `part`, when
-// visited, is the last one and holds only tail < BK values of l.  The caller
-// synchronises the workgroup before the LDS is written again after the loop.
+// last slot that holds an in-range element).  The K steps visited are first,
+// next(first), next(next(first)), ... up to the first one >= end, in
+// increasing order (the caller's next() returns the following step to visit,
+// wave-uniform).  Step `part`, when visited, is the last one and holds only
+// tail < BK values of l.  The caller synchronises the workgroup before the LDS
+// is written again after the loop.
 template <typename T, int BK, bool B_J, int WGM, int WGN, int TM, int TN, class Next>
 __device__ __forceinline__ void dma_loop(T* stages, const T* At, const T* Bt, int64_t sAl, int64_t sBl,
                                          int64_t sBj, int64_t rows_a, int64_t rows_b, int64_t first,
@@ -147,12 +148,15 @@ __device__ __forceinline__ void dma_loop(T* stages, const T* At, const T* Bt, in
   const int wu = __builtin_amdgcn_readfirstlane(w);
   const uint32_t lds0 = __builtin_amdgcn_readfirstlane(dma_lds_address(stages));
 
-  // per instruction: this lane's source in step 0, the bytes a K step moves
-  // it, and the LDS offset of its block within a stage.  A wave short of
-  // blocks repeats one (the same bytes written twice).
+  // per instruction: this lane's source in step 0, whether it loads A (the
+  // bytes a K step moves it are stepA, else stepB), and the LDS offset of its
+  // block within a stage.  A wave short of blocks repeats one (the same bytes
+  // written twice).
   const char* gp[IPW];
-  int64_t step[IPW];
+  bool isa[IPW];
   uint32_t ldso[IPW];
+  const int64_t stepA = static_cast<int64_t>(BK) * sAl * SZ;
+  const int64_t stepB = static_cast<int64_t>(BK) * (B_J ? sBl : 1) * SZ;
 #pragma unroll
   for (int q = 0; q < IPW; ++q) {
     int ig = wu + NW * q;
@@ -163,25 +167,28 @@ __device__ __forceinline__ void dma_loop(T* stages, const T* At, const T* Bt, in
       const int sl = 64 * ig + lane, l = sl / (BM / E);
       const int i = (E * (sl % (BM / E))) ^ dma_xr<T, BM>(l);
       src = At + (i < rows_a ? i : (rows_a - 1) & ~int64_t(E - 1)) + l * sAl;
-      step[q] = static_cast<int64_t>(BK) * sAl * SZ;
     } else if constexpr (B_J) {
       const int sl = 64 * (ig - NIA) + lane, l = sl / (BN / E);
       const int j = (E * (sl % (BN / E))) ^ dma_xr<T, BN>(l);
       src = Bt + (j < rows_b ? j : (rows_b - 1) & ~int64_t(E - 1)) + l * sBl;
-      step[q] = static_cast<int64_t>(BK) * sBl * SZ;
     } else {
       const int sl = 64 * (ig - NIA) + lane, j = sl / (BK / E);
       const int l = E * ((sl % (BK / E)) ^ dma_kx<T, BK>(j));
       src = Bt + (j < rows_b ? j : rows_b - 1) * sBj + l;
-      step[q] = static_cast<int64_t>(BK) * SZ;
     }
     gp[q] = reinterpret_cast<const char*>(src);
+    isa[q] = ig < NIA;
   }
   auto issue = [&](int slot, int64_t kt) {
+    // two wave-uniform offsets per step, one for each operand
     const int64_t t = __builtin_amdgcn_readfirstlane(static_cast<int>(kt));
+    int64_t oa = t * stepA, ob = t * stepB;
+    // opaque to the compiler, which would otherwise fold the select below into
+    // one 64-bit multiply per instruction
+    asm("" : "+s"(oa), "+s"(ob));
     const uint32_t sb = lds0 + static_cast<uint32_t>(slot * STAGE * SZ);
 #pragma unroll
-    for (int q = 0; q < IPW; ++q) dma_b128(gp[q] + t * step[q], sb + ldso[q]);
+    for (int q = 0; q < IPW; ++q) dma_b128(gp[q] + (isa[q] ? oa : ob), sb + ldso[q]);
   };
   // fragments of sub-step kk + 1 are read before the products of kk
   auto compute = [&](const T* sa) {
@@ -483,9 +490,9 @@ __device__ __forceinline__ void gemm_body(const GemmArgs& g, int mt, int nt, int
               static_cast<int>(Ls % BK), [&](int64_t) -> int64_t { return ++pos < nk ? stage_list[pos] : end; },
               acc);
         } else {
-          dma_loop<T, BK, B_J, WGM, WGN, TM, TN>(stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, 0, nk,
-                                                 part, static_cast<int>(Ls % BK), [](int64_t t) { return t + 1; },
-                                                 acc);
+          dma_loop<T, BK, B_J, WGM, WGN, TM, TN>(stages, At, Bt, g.sAl, g.sBl, g.sBj, g.M - i0, g.N - j0, 0,
+                                                       nk, part, static_cast<int>(Ls % BK),
+                                                       [](int64_t t) { return t + 1; }, acc);
         }
       }
     }
