@@ -36,12 +36,17 @@ namespace {
 // (those of the first component before the radial sums, by the caller), so
 // that their latency overlaps the arithmetic; FP32 Gbar is loaded where it
 // is used (loading it ahead was slower).  At 800 AOs x 143,360 points the
-// unrolled form takes 0.89 ms (FP64) and 0.71 ms (FP32 Gbar), against 1.09
-// and 0.84 ms for a run-time component loop with selected powers.
+// unrolled form takes 0.89 ms (FP64), against 1.09 ms for a run-time
+// component loop with selected powers.
+// The arithmetic type is Gbar's: with FP32 Gbar (the mixed-precision modes)
+// the radial sums and the derivative contraction run in FP32 (0.53 ms, 0.71
+// ms with FP64 arithmetic on the same FP32 Gbar); the point-nucleus
+// distances, the cutoff decisions and the sums over shells and nuclei stay
+// FP64.
 template <typename GT>
-__device__ __forceinline__ void load_gbar(const GT* __restrict__ q, int64_t sC, double* G) {
+__device__ __forceinline__ void load_gbar(const GT* __restrict__ q, int64_t sC, GT* G) {
 #pragma unroll
-  for (int c = 0; c < 5; ++c) G[c] = static_cast<double>(q[c * sC]);
+  for (int c = 0; c < 5; ++c) G[c] = q[c * sC];
 }
 
 // Cartesian component `idx` of a shell of angular momentum l: (a, b, l-a-b)
@@ -64,25 +69,30 @@ constexpr int cart_b(int l, int idx) {
 }
 
 // Derivatives of t^E (E known at compile time) of order 0..3.
-template <int E>
-__device__ __forceinline__ AxisD axis_c(double t, double t2, double t3) {
-  AxisD r;
+template <typename CT>
+struct AxisT {
+  CT v0, v1, v2, v3;
+};
+template <int E, typename CT>
+__device__ __forceinline__ AxisT<CT> axis_c(CT t, CT t2, CT t3) {
+  AxisT<CT> r;
   if constexpr (E == 0) {
-    r = AxisD{1.0, 0.0, 0.0, 0.0};
+    r = AxisT<CT>{CT(1), CT(0), CT(0), CT(0)};
   } else if constexpr (E == 1) {
-    r = AxisD{t, 1.0, 0.0, 0.0};
+    r = AxisT<CT>{t, CT(1), CT(0), CT(0)};
   } else if constexpr (E == 2) {
-    r = AxisD{t2, 2.0 * t, 2.0, 0.0};
+    r = AxisT<CT>{t2, CT(2) * t, CT(2), CT(0)};
   } else {
-    r = AxisD{t3, 3.0 * t2, 6.0 * t, 6.0};
+    r = AxisT<CT>{t3, CT(3) * t2, CT(6) * t, CT(6)};
   }
   return r;
 }
 
-// Shell quantities shared by its components.
+// Shell quantities shared by its components (CT: the arithmetic type).
+template <typename CT>
 struct ShellRadial {
-  double dx, dy, dz, dx2, dy2, dz2, dx3, dy3, dz3;
-  double g0, g1, g2, tg1, fg2, fug2, eug3, c1, c2;
+  CT dx, dy, dz, dx2, dy2, dz2, dx3, dy3, dz3;
+  CT g0, g1, g2, tg1, fg2, fug2, eug3, c1, c2;
 };
 
 // Component I of a shell of angular momentum L, then the rest: the powers of
@@ -94,13 +104,14 @@ struct ShellRadial {
 // it is used.  A compiler barrier closes each component, so that the
 // unrolled components do not pile their loads and temporaries up at once.
 template <typename GT, int L, int I>
-__device__ __forceinline__ void adj_components(const ShellRadial& r, const double* __restrict__ M,
+__device__ __forceinline__ void adj_components(const ShellRadial<GT>& r, const double* __restrict__ M,
                                                const GT* __restrict__ gb, int64_t sK, int64_t sC,
-                                               const double* Gc, double& tx, double& ty, double& tz) {
+                                               const GT* Gc, GT& tx, GT& ty, GT& tz) {
+  typedef GT CT;
   if constexpr (I < (L + 1) * (L + 2) / 2) {
     constexpr int a = cart_a(L, I), b = cart_b(L, I), c = L - a - b;
     constexpr bool kAhead = std::is_same<GT, double>::value;
-    double G[5], Gn[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    CT G[5], Gn[5] = {CT(0), CT(0), CT(0), CT(0), CT(0)};
     if constexpr (kAhead) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) G[q] = Gc[q];
@@ -110,38 +121,38 @@ __device__ __forceinline__ void adj_components(const ShellRadial& r, const doubl
     }
     // fresh copies of the powers: without them common products of different
     // components would be kept alive across the whole shell
-    double px = r.dx, px2 = r.dx2, px3 = r.dx3, py = r.dy, py2 = r.dy2, py3 = r.dy3, pz = r.dz, pz2 = r.dz2,
-           pz3 = r.dz3;
+    CT px = r.dx, px2 = r.dx2, px3 = r.dx3, py = r.dy, py2 = r.dy2, py3 = r.dy3, pz = r.dz, pz2 = r.dz2,
+       pz3 = r.dz3;
     asm volatile("" : "+v"(px), "+v"(px2), "+v"(px3), "+v"(py), "+v"(py2), "+v"(py3), "+v"(pz), "+v"(pz2),
                  "+v"(pz3));
-    const AxisD X = axis_c<a>(px, px2, px3);
-    const AxisD Y = axis_c<b>(py, py2, py3);
-    const AxisD Z = axis_c<c>(pz, pz2, pz3);
-    const double G0 = G[0], G1 = G[1], G2 = G[2], G3 = G[3], G4 = G[4];
-    const double P = X.v0 * Y.v0 * Z.v0;
-    const double Px = X.v1 * Y.v0 * Z.v0, Py = X.v0 * Y.v1 * Z.v0, Pz = X.v0 * Y.v0 * Z.v1;
-    const double Pxx = X.v2 * Y.v0 * Z.v0, Pyy = X.v0 * Y.v2 * Z.v0, Pzz = X.v0 * Y.v0 * Z.v2;
-    const double Pxy = X.v1 * Y.v1 * Z.v0, Pxz = X.v1 * Y.v0 * Z.v1, Pyz = X.v0 * Y.v1 * Z.v1;
-    const double lapP = Pxx + Pyy + Pzz;
-    const double lPx = X.v3 * Y.v0 * Z.v0 + X.v1 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
-    const double lPy = Y.v3 * X.v0 * Z.v0 + Y.v1 * (X.v2 * Z.v0 + X.v0 * Z.v2);
-    const double lPz = Z.v3 * X.v0 * Y.v0 + Z.v1 * (X.v2 * Y.v0 + X.v0 * Y.v2);
-    const double Gd = G1 * r.dx + G2 * r.dy + G3 * r.dz;
-    const double GdP = G1 * Px + G2 * Py + G3 * Pz;
-    const double HGx = Pxx * G1 + Pxy * G2 + Pxz * G3;
-    const double HGy = Pxy * G1 + Pyy * G2 + Pyz * G3;
-    const double HGz = Pxz * G1 + Pyz * G2 + Pzz * G3;
-    const double m = M[I];
+    const AxisT<CT> X = axis_c<a>(px, px2, px3);
+    const AxisT<CT> Y = axis_c<b>(py, py2, py3);
+    const AxisT<CT> Z = axis_c<c>(pz, pz2, pz3);
+    const CT G0 = G[0], G1 = G[1], G2 = G[2], G3 = G[3], G4 = G[4];
+    const CT P = X.v0 * Y.v0 * Z.v0;
+    const CT Px = X.v1 * Y.v0 * Z.v0, Py = X.v0 * Y.v1 * Z.v0, Pz = X.v0 * Y.v0 * Z.v1;
+    const CT Pxx = X.v2 * Y.v0 * Z.v0, Pyy = X.v0 * Y.v2 * Z.v0, Pzz = X.v0 * Y.v0 * Z.v2;
+    const CT Pxy = X.v1 * Y.v1 * Z.v0, Pxz = X.v1 * Y.v0 * Z.v1, Pyz = X.v0 * Y.v1 * Z.v1;
+    const CT lapP = Pxx + Pyy + Pzz;
+    const CT lPx = X.v3 * Y.v0 * Z.v0 + X.v1 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
+    const CT lPy = Y.v3 * X.v0 * Z.v0 + Y.v1 * (X.v2 * Z.v0 + X.v0 * Z.v2);
+    const CT lPz = Z.v3 * X.v0 * Y.v0 + Z.v1 * (X.v2 * Y.v0 + X.v0 * Y.v2);
+    const CT Gd = G1 * r.dx + G2 * r.dy + G3 * r.dz;
+    const CT GdP = G1 * Px + G2 * Py + G3 * Pz;
+    const CT HGx = Pxx * G1 + Pxy * G2 + Pxz * G3;
+    const CT HGy = Pxy * G1 + Pyy * G2 + Pyz * G3;
+    const CT HGz = Pxz * G1 + Pyz * G2 + Pzz * G3;
+    const CT m = static_cast<CT>(M[I]);
     // per direction i: G0 d_i chi + sum_j Gj d_i d_j chi + G4 d_i lap chi (over M)
-    const double Pg = P * Gd * r.fg2, Pe = P * r.eug3, Pl = P * r.c2 * r.g2;
+    const CT Pg = P * Gd * r.fg2, Pe = P * r.eug3, Pl = P * r.c2 * r.g2;
     tx += m * (G0 * (Px * r.g0 + r.dx * P * r.tg1) + r.g0 * HGx + r.tg1 * (Px * Gd + r.dx * GdP + G1 * P) +
-               r.dx * Pg + G4 * (lPx * r.g0 + (2.0 * r.dx * lapP + r.c1 * Px) * r.g1 + r.dx * Pl + r.fug2 * Px +
+               r.dx * Pg + G4 * (lPx * r.g0 + (CT(2) * r.dx * lapP + r.c1 * Px) * r.g1 + r.dx * Pl + r.fug2 * Px +
                                  r.dx * Pe));
     ty += m * (G0 * (Py * r.g0 + r.dy * P * r.tg1) + r.g0 * HGy + r.tg1 * (Py * Gd + r.dy * GdP + G2 * P) +
-               r.dy * Pg + G4 * (lPy * r.g0 + (2.0 * r.dy * lapP + r.c1 * Py) * r.g1 + r.dy * Pl + r.fug2 * Py +
+               r.dy * Pg + G4 * (lPy * r.g0 + (CT(2) * r.dy * lapP + r.c1 * Py) * r.g1 + r.dy * Pl + r.fug2 * Py +
                                  r.dy * Pe));
     tz += m * (G0 * (Pz * r.g0 + r.dz * P * r.tg1) + r.g0 * HGz + r.tg1 * (Pz * Gd + r.dz * GdP + G3 * P) +
-               r.dz * Pg + G4 * (lPz * r.g0 + (2.0 * r.dz * lapP + r.c1 * Pz) * r.g1 + r.dz * Pl + r.fug2 * Pz +
+               r.dz * Pg + G4 * (lPz * r.g0 + (CT(2) * r.dz * lapP + r.c1 * Pz) * r.g1 + r.dz * Pl + r.fug2 * Pz +
                                  r.dz * Pe));
     asm volatile("" ::: "memory");  // keeps the next component's loads below this one
     adj_components<GT, L, I + 1>(r, M, gb, sK, sC, Gn, tx, ty, tz);
@@ -149,11 +160,12 @@ __device__ __forceinline__ void adj_components(const ShellRadial& r, const doubl
 }
 
 template <typename GT, int L>
-__device__ __forceinline__ void shell_adjoint_l(double dx, double dy, double dz, double u, double g0,
-                                                double g1, double g2, double g3, const double* __restrict__ M,
-                                                const GT* __restrict__ gb, int64_t sK, int64_t sC,
-                                                const double* G_first, double& tx, double& ty, double& tz) {
-  ShellRadial r;
+__device__ __forceinline__ void shell_adjoint_l(GT dx, GT dy, GT dz, GT u, GT g0, GT g1, GT g2, GT g3,
+                                                const double* __restrict__ M, const GT* __restrict__ gb,
+                                                int64_t sK, int64_t sC, const GT* G_first, GT& tx, GT& ty,
+                                                GT& tz) {
+  typedef GT CT;
+  ShellRadial<CT> r;
   r.dx = dx;
   r.dy = dy;
   r.dz = dz;
@@ -166,22 +178,22 @@ __device__ __forceinline__ void shell_adjoint_l(double dx, double dy, double dz,
   r.g0 = g0;
   r.g1 = g1;
   r.g2 = g2;
-  r.tg1 = 2.0 * g1;
-  r.fg2 = 4.0 * g2;
-  r.fug2 = 4.0 * u * g2;
-  r.eug3 = 8.0 * u * g3;
-  r.c1 = 4.0 * L + 6.0;
-  r.c2 = 8.0 * L + 20.0;
+  r.tg1 = CT(2) * g1;
+  r.fg2 = CT(4) * g2;
+  r.fug2 = CT(4) * u * g2;
+  r.eug3 = CT(8) * u * g3;
+  r.c1 = CT(4 * L + 6);
+  r.c2 = CT(8 * L + 20);
   adj_components<GT, L, 0>(r, M, gb, sK, sC, G_first, tx, ty, tz);
 }
 
 // Contracts the shell's third-order AO derivatives with Gbar (l <= 3,
 // wave-uniform).
 template <typename GT>
-__device__ __forceinline__ void shell_adjoint(int l, double dx, double dy, double dz, double u, double g0,
-                                              double g1, double g2, double g3, const double* __restrict__ M,
-                                              const GT* __restrict__ gb, int64_t sK, int64_t sC,
-                                              const double* G_first, double& tx, double& ty, double& tz) {
+__device__ __forceinline__ void shell_adjoint(int l, GT dx, GT dy, GT dz, GT u, GT g0, GT g1, GT g2, GT g3,
+                                              const double* __restrict__ M, const GT* __restrict__ gb,
+                                              int64_t sK, int64_t sC, const GT* G_first, GT& tx, GT& ty,
+                                              GT& tz) {
   switch (l) {
     case 0: shell_adjoint_l<GT, 0>(dx, dy, dz, u, g0, g1, g2, g3, M, gb, sK, sC, G_first, tx, ty, tz); break;
     case 1: shell_adjoint_l<GT, 1>(dx, dy, dz, u, g0, g1, g2, g3, M, gb, sK, sC, G_first, tx, ty, tz); break;
@@ -237,28 +249,37 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
     const bool near = valid && (nu.gmin * u < T);
     double tx = 0.0, ty = 0.0, tz = 0.0;
     if (__any(near)) {
+      typedef GT CT;  // the arithmetic type of the radial sums and the contraction
+      const CT cx = static_cast<CT>(dx), cy = static_cast<CT>(dy), cz = static_cast<CT>(dz);
+      const CT cu = static_cast<CT>(u);
       for (int s = nu.sh_begin; s < nu.sh_end; ++s) {
         const ShellDev sh = s_shell[s];
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-        double G_first[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        CT g0 = CT(0), g1 = CT(0), g2 = CT(0), g3 = CT(0);
+        CT G_first[5] = {CT(0), CT(0), CT(0), CT(0), CT(0)};
         if (std::is_same<GT, double>::value && near) load_gbar(gb_p + sh.ao_off * sK, sC, G_first);
         for (int k = sh.p_begin; k < sh.p_end; ++k) {
           const PrimDev pr = s_prim[k];
-          const double x = pr.gamma * u;
+          const double x = pr.gamma * u;  // the cutoff test in FP64, as in the forward pass
           const bool on = near && (x < T);
           if (!__any(on)) break;
           if (on) {
-            const double e = pr.coef * exp(-x);
-            const double ge = pr.gamma * e;
+            const CT gm = static_cast<CT>(pr.gamma);
+            const CT e = static_cast<CT>(pr.coef) * exp(static_cast<CT>(-x));
+            const CT ge = gm * e;
             g0 += e;
             g1 -= ge;
-            g2 += pr.gamma * ge;
-            g3 -= pr.gamma * pr.gamma * ge;
+            g2 += gm * ge;
+            g3 -= gm * gm * ge;
           }
         }
-        if (near)
-          shell_adjoint(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2, g3,
-                        t.ao_factor + sh.ao_off, gb_p + sh.ao_off * sK, sK, sC, G_first, tx, ty, tz);
+        if (near) {
+          CT sx = CT(0), sy = CT(0), sz = CT(0);
+          shell_adjoint(__builtin_amdgcn_readfirstlane(sh.l), cx, cy, cz, cu, g0, g1, g2, g3,
+                        t.ao_factor + sh.ao_off, gb_p + sh.ao_off * sK, sK, sC, G_first, sx, sy, sz);
+          tx += static_cast<double>(sx);
+          ty += static_cast<double>(sy);
+          tz += static_cast<double>(sz);
+        }
       }
     }
     ex += tx;
