@@ -26,6 +26,6 @@ def test_traffic_lookup_reads_the_committed_summary():
     assert d["mo"] == d["gbar"] == d["dcoef"]
     # a class the summary does not hold, or another mode, has no traffic figure
     assert bench.measured_traffic("fp64", "no_such_class") is None
-    assert bench.measured_traffic("mixed_bf16x3", "mo") is None
+    assert bench.measured_traffic("no_such_mode", "mo") is None
     v = bench.measured_traffic("fp64", "ao")
     assert v is None or v > 4e9  # the AO stage writes its 4.59 GB output
