@@ -55,6 +55,42 @@ __device__ __forceinline__ void st(Bf16Pair* p, double v, int64_t) {
   const uint32_t sel = (threadIdx.x & 1) ? 0x03020706u : 0x05040100u;
   *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(rp, pk, sel);
 }
+// The same split of a value already in FP32.
+__device__ __forceinline__ void st(Bf16Pair* p, float f, int64_t) {
+  const __bf16 h = static_cast<__bf16>(f);
+  const __bf16 l = static_cast<__bf16>(f - static_cast<float>(h));
+  const uint32_t pk = static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h)) |
+                      (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l)) << 16);
+  const uint32_t rp = static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(pk), 0xB1, 0xF, 0xF, true));
+  const uint32_t sel = (threadIdx.x & 1) ? 0x03020706u : 0x05040100u;
+  *reinterpret_cast<uint32_t*>(p) = __builtin_amdgcn_perm(rp, pk, sel);
+}
+
+// Arithmetic type of the AO values: FP64, except for the split planes, whose
+// hi / lo pair represents the FP32 rounding of a value to 16 significant bits
+// (FP32 arithmetic errors stay far below that).
+template <typename OutT>
+struct AoCalc {
+  typedef double type;
+};
+template <>
+struct AoCalc<Bf16Pair> {
+  typedef float type;
+};
+
+template <typename CT>
+struct AxisT {
+  CT v0, v1, v2, v3;
+};
+// Derivatives of t^e (e = 0..3, wave-uniform), given t, t^2, t^3: v0 = t^e,
+// v1 = e t^(e-1), v2 = e(e-1) t^(e-2), v3 = e(e-1)(e-2) t^(e-3).
+template <typename CT>
+__device__ __forceinline__ AxisT<CT> axis_derivs_t(int e, CT t, CT t2, CT t3) {
+  if (e == 0) return AxisT<CT>{CT(1), CT(0), CT(0), CT(0)};
+  if (e == 1) return AxisT<CT>{t, CT(1), CT(0), CT(0)};
+  if (e == 2) return AxisT<CT>{t2, CT(2) * t, CT(2), CT(0)};
+  return AxisT<CT>{t3, CT(3) * t2, CT(6) * t, CT(6)};
+}
 
 // Stores value, gradient and Laplacian of the (l+1)(l+2)/2 Cartesian AOs of
 // one shell for this lane's point.  l is wave-uniform; the components run in
@@ -62,15 +98,14 @@ __device__ __forceinline__ void st(Bf16Pair* p, double v, int64_t) {
 //   chi      = M P g0
 //   d_i chi  = M (d_i P g0 + 2 d_i P g1)          (d_i: displacement)
 //   lap chi  = M (lap P g0 + (4l+6) P g1 + 4 u P g2)
-template <typename OutT>
-__device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz, double u,
-                                          double g0, double g1, double g2,
+template <typename OutT, typename CT = typename AoCalc<OutT>::type>
+__device__ __forceinline__ void shell_vgl(int l, CT dx, CT dy, CT dz, CT u, CT g0, CT g1, CT g2,
                                           const double* __restrict__ M, OutT* __restrict__ o,
                                           int64_t sK, int64_t sC, int64_t plane) {
-  const double lapr = (4.0 * l + 6.0) * g1 + 4.0 * u * g2;
-  const double tg1 = 2.0 * g1;
-  const double dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
-  const double dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
+  const CT lapr = CT(4 * l + 6) * g1 + CT(4) * u * g2;
+  const CT tg1 = CT(2) * g1;
+  const CT dx2 = dx * dx, dy2 = dy * dy, dz2 = dz * dz;
+  const CT dx3 = dx2 * dx, dy3 = dy2 * dy, dz3 = dz2 * dz;
   // components (a, b, c) with a descending, then b descending, in one loop
   const int ncart = (l + 1) * (l + 2) / 2;
   int a = l, b = 0;
@@ -78,14 +113,14 @@ __device__ __forceinline__ void shell_vgl(int l, double dx, double dy, double dz
   for (int idx = 0; idx < ncart; ++idx) {
     {
       const int c = l - a - b;
-      const AxisD X = axis_derivs(a, dx, dx2, dx3);
-      const AxisD Y = axis_derivs(b, dy, dy2, dy3);
-      const AxisD Z = axis_derivs(c, dz, dz2, dz3);
-      const double yz = Y.v0 * Z.v0;
-      const double P = X.v0 * yz;
-      const double lapP = X.v2 * yz + X.v0 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
-      const double m = M[idx];
-      const double tp = P * tg1;
+      const AxisT<CT> X = axis_derivs_t(a, dx, dx2, dx3);
+      const AxisT<CT> Y = axis_derivs_t(b, dy, dy2, dy3);
+      const AxisT<CT> Z = axis_derivs_t(c, dz, dz2, dz3);
+      const CT yz = Y.v0 * Z.v0;
+      const CT P = X.v0 * yz;
+      const CT lapP = X.v2 * yz + X.v0 * (Y.v2 * Z.v0 + Y.v0 * Z.v2);
+      const CT m = static_cast<CT>(M[idx]);
+      const CT tp = P * tg1;
       OutT* q = o + idx * sK;
       st(q, m * P * g0, plane);
       st(q + sC, m * (X.v1 * yz * g0 + dx * tp), plane);
@@ -218,28 +253,31 @@ __device__ __forceinline__ void ao_vgl_body(const AoTables& t, const PointArgs& 
           continue;
         }
       }
-      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+      typedef typename AoCalc<OutT>::type CT;  // the radial sums' arithmetic type
+      CT g0 = CT(0), g1 = CT(0), g2 = CT(0);
       for (int k = sh.p_begin; k < sh.p_end; ++k) {
         const PrimDev pr = s_prim[k];
-        const double x = pr.gamma * u;
+        const double x = pr.gamma * u;  // the cutoff test in FP64 in every mode
         const bool on = near && (x < T);
         if (!__any(on)) break;  // ascending exponents: every later one is cut too
         if (on) {
-          const double e = pr.coef * exp(-x);
+          const CT gm = static_cast<CT>(pr.gamma);
+          const CT e = static_cast<CT>(pr.coef) * exp(static_cast<CT>(-x));
           g0 += e;
-          g1 -= pr.gamma * e;
-          g2 += pr.gamma * pr.gamma * e;
+          g1 -= gm * e;
+          g2 += gm * gm * e;
         }
       }
       // (the split-plane store needs both lanes of every pair: lanes past the
       // last point store the zeros their empty sums give)
       if (valid || kPairs) {
         if (VAL)
-          shell_value(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, g0,
+          shell_value(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, static_cast<double>(g0),
                       t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK);
         else
-          shell_vgl(__builtin_amdgcn_readfirstlane(sh.l), dx, dy, dz, u, g0, g1, g2,
-                    t.ao_factor + sh.ao_off, obase + sh.ao_off * out.sK, out.sK, out.sC, out.plane);
+          shell_vgl<OutT>(__builtin_amdgcn_readfirstlane(sh.l), static_cast<CT>(dx), static_cast<CT>(dy),
+                          static_cast<CT>(dz), static_cast<CT>(u), g0, g1, g2, t.ao_factor + sh.ao_off,
+                          obase + sh.ao_off * out.sK, out.sK, out.sC, out.plane);
       }
     }
   }

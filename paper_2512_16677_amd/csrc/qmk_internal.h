@@ -227,20 +227,6 @@ inline dim3 grid_of(const GemmArgs& g, int nM, int nN) {
   return dim3(gx, nz);
 }
 
-// Derivatives of t^e (e in 0..3, wave-uniform) of order 0..3, given t, t^2,
-// t^3: v0 = t^e, v1 = e t^(e-1), v2 = e(e-1) t^(e-2), v3 = e(e-1)(e-2) t^(e-3).
-struct AxisD {
-  double v0, v1, v2, v3;
-};
-__device__ __forceinline__ AxisD axis_derivs(int e, double t, double t2, double t3) {
-  AxisD r;
-  r.v0 = e == 0 ? 1.0 : (e == 1 ? t : (e == 2 ? t2 : t3));
-  r.v1 = e == 0 ? 0.0 : (e == 1 ? 1.0 : (e == 2 ? 2.0 * t : 3.0 * t2));
-  r.v2 = e < 2 ? 0.0 : (e == 2 ? 2.0 : 6.0 * t);
-  r.v3 = e == 3 ? 6.0 : 0.0;
-  return r;
-}
-
 enum class GemmKind { kForward, kGbar, kDcoef, kDensity, kJastrow };
 // kBF16P: BF16x3 products on operands pre-split into bf16 hi / lo planes.
 // The values are part of the persisted tile-table keys.
