@@ -14,8 +14,6 @@
 // early exit over the ascending exponents.  Reductions are deterministic:
 // per-wave nucleus sums are written to a partial array and summed in a
 // fixed order by a second kernel.
-#include <type_traits>
-
 #include "qmk_internal.h"
 
 namespace qmk {
@@ -32,17 +30,16 @@ namespace {
 //                    + ((8l+20) d_i P + 4 u P_i) g2 + 8 u d_i P g3)
 // Summed against Gbar as  sum_j Gj d_i d_j chi  =  M (g0 (Hess P . G)_i
 //   + 2 g1 (P_i (G.d) + d_i (G.grad P) + G_i P) + 4 g2 d_i P (G.d)).
-// FP64 Gbar: the five values of a component are loaded one component ahead
-// (those of the first component before the radial sums, by the caller), so
-// that their latency overlaps the arithmetic; FP32 Gbar is loaded where it
-// is used (loading it ahead was slower).  At 800 AOs x 143,360 points the
+// The five Gbar values of a component are loaded one component ahead (those
+// of the first component before the radial sums, by the caller), so that
+// their latency overlaps the arithmetic.  At 800 AOs x 143,360 points the
 // unrolled form takes 0.89 ms (FP64), against 1.09 ms for a run-time
 // component loop with selected powers.
 // The arithmetic type is Gbar's: with FP32 Gbar (the mixed-precision modes)
-// the radial sums and the derivative contraction run in FP32 (0.53 ms, 0.71
-// ms with FP64 arithmetic on the same FP32 Gbar); the point-nucleus
-// distances, the cutoff decisions and the sums over shells and nuclei stay
-// FP64.
+// the radial sums and the derivative contraction run in FP32 (0.47 ms; 0.71
+// ms with FP64 arithmetic on the same FP32 Gbar, loaded where used); the
+// point-nucleus distances, the cutoff decisions and the sums over shells and
+// nuclei stay FP64.
 template <typename GT>
 __device__ __forceinline__ void load_gbar(const GT* __restrict__ q, int64_t sC, GT* G) {
 #pragma unroll
@@ -98,11 +95,11 @@ struct ShellRadial {
 // Component I of a shell of angular momentum L, then the rest: the powers of
 // the displacement are compile-time choices (no selects), and the component
 // loop is unrolled per L.
-// Gc holds the component's five Gbar values.  FP64 Gbar is loaded one
-// component ahead (the first component's by the caller, before the radial
-// sums), so that the loads overlap the arithmetic; FP32 Gbar is loaded where
-// it is used.  A compiler barrier closes each component, so that the
-// unrolled components do not pile their loads and temporaries up at once.
+// Gc holds the component's five Gbar values, loaded one component ahead
+// (the first component's by the caller, before the radial sums), so that the
+// loads overlap the arithmetic.  A compiler barrier closes each component,
+// so that the unrolled components do not pile their loads and temporaries
+// up at once.
 template <typename GT, int L, int I>
 __device__ __forceinline__ void adj_components(const ShellRadial<GT>& r, const double* __restrict__ M,
                                                const GT* __restrict__ gb, int64_t sK, int64_t sC,
@@ -110,15 +107,10 @@ __device__ __forceinline__ void adj_components(const ShellRadial<GT>& r, const d
   typedef GT CT;
   if constexpr (I < (L + 1) * (L + 2) / 2) {
     constexpr int a = cart_a(L, I), b = cart_b(L, I), c = L - a - b;
-    constexpr bool kAhead = std::is_same<GT, double>::value;
     CT G[5], Gn[5] = {CT(0), CT(0), CT(0), CT(0), CT(0)};
-    if constexpr (kAhead) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) G[q] = Gc[q];
-      if constexpr (I + 1 < (L + 1) * (L + 2) / 2) load_gbar(gb + (I + 1) * sK, sC, Gn);
-    } else {
-      load_gbar(gb + I * sK, sC, G);
-    }
+    for (int q = 0; q < 5; ++q) G[q] = Gc[q];
+    if constexpr (I + 1 < (L + 1) * (L + 2) / 2) load_gbar(gb + (I + 1) * sK, sC, Gn);
     // fresh copies of the powers: without them common products of different
     // components would be kept alive across the whole shell
     CT px = r.dx, px2 = r.dx2, px3 = r.dx3, py = r.dy, py2 = r.dy2, py3 = r.dy3, pz = r.dz, pz2 = r.dz2,
@@ -256,7 +248,7 @@ __device__ __forceinline__ void ao_adjoint_body(const AoTables& t, const PointAr
         const ShellDev sh = s_shell[s];
         CT g0 = CT(0), g1 = CT(0), g2 = CT(0), g3 = CT(0);
         CT G_first[5] = {CT(0), CT(0), CT(0), CT(0), CT(0)};
-        if (std::is_same<GT, double>::value && near) load_gbar(gb_p + sh.ao_off * sK, sC, G_first);
+        if (near) load_gbar(gb_p + sh.ao_off * sK, sC, G_first);
         for (int k = sh.p_begin; k < sh.p_end; ++k) {
           const PrimDev pr = s_prim[k];
           const double x = pr.gamma * u;  // the cutoff test in FP64, as in the forward pass
