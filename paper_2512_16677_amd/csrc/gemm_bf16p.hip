@@ -172,15 +172,18 @@ __device__ __forceinline__ bf16x8 frag_k(const __bf16* t, int r0, int lane) {
 
 // MN-major ring tile of R rows: 16-byte chunk c of k-row l sits at chunk
 // c ^ mn_xor(l).  A 16-lane group of the transposing fragment read touches
-// 32 consecutive bytes of each of four consecutive k-rows; with the k-row
-// pitch R * 2 bytes = 0 (mod 128) the permutation moves them to four
-// different 32-byte bank windows, with pitch = 64 (mod 128) it separates
-// the two pairs of rows that would coincide, and with 32 or 96 the rows
-// already fall apart.  Rows l and l + 4 always share the permutation.
+// 32 consecutive bytes of each of four consecutive k-rows (l0 .. l0+3), and
+// the 32 lanes served together touch the rows l0 .. l0+3 and l0+8 .. l0+11:
+// eight 32-byte windows, which the permutation puts on eight different
+// 32-byte bank windows for every k-row pitch R * 2 that is a multiple of 64
+// bytes (pitch = 0 mod 256: rows by their bits 0, 1 and 3; 128: bits 1 and
+// 3; 64 or 192: bit 3).  Rows l and l + 4 share the permutation.
 template <int R>
 __device__ __forceinline__ int mn_xor(int l) {
-  if constexpr ((R * 2) % 128 == 0) return 2 * (l & 3);
-  else if constexpr ((R * 2) % 128 == 64) return 2 * ((l >> 1) & 1);
+  constexpr int p = (R * 2) % 256;
+  if constexpr (p == 0) return 2 * (l & 3) + 8 * ((l >> 3) & 1);
+  else if constexpr (p == 128) return 2 * ((l >> 1) & 1) + 4 * ((l >> 3) & 1);
+  else if constexpr (p == 64 || p == 192) return 2 * ((l >> 3) & 1);
   else return 0;
 }
 
