@@ -32,8 +32,9 @@
 //     ahead and stores them to one of two LDS buffers;
 //   DEPTH >= 3: an LDS ring of DEPTH stages filled by global_load_lds_dwordx4
 //     (each lane's 16 bytes go from global memory straight to LDS), so the
-//     loads of step kt + DEPTH - 1 are in flight while step kt computes and
-//     no registers hold operand data.  The ring lays a tile out without
+//     loads of steps kt + 1 .. kt + DEPTH are in flight while step kt
+//     computes and no registers hold operand data; the MFMA fragments of
+//     step kt + 1 are read from LDS under the MFMAs of step kt.  The ring lays a tile out without
 //     padding (a load instruction fills 1 KB of consecutive LDS); an
 //     MN-major tile permutes the 16-byte chunks of each k-row instead (see
 //     mn_xor), and rows past the operand's row count hold copies of the last
@@ -237,7 +238,15 @@ __device__ __forceinline__ void ring_sync() {
 // K loop of one tile on an S-stage ring.  Every wave issues the same number
 // of load instructions per stage (IPW; a wave short of real ones repeats
 // one, writing the same bytes again), so vmcnt counts stages.
-template <bool A_MN, int WGM, int WGN, int TM, int TN, int S, bool LIST>
+// PF: the MFMA fragments of stage kt + 1 are read into a second register
+// set right after the barrier of step kt and under the MFMAs of stage kt, so
+// the LDS reads of one stage overlap the MFMAs of the previous one.  The
+// barrier of step kt then also means that every wave holds its fragments of
+// stage kt: that stage's slot is free, and the loads of stage kt + S go into
+// it (all S slots are in flight or being read).  Without PF (fewer
+// registers) step kt waits for stage kt, reads its fragments and computes,
+// with the loads of stage kt + S - 1 going into the slot read in step kt - 1.
+template <bool A_MN, int WGM, int WGN, int TM, int TN, int S, bool LIST, bool PF>
 __device__ __forceinline__ void bf16p_ring(__bf16* ring, const __bf16* Ah, const __bf16* Al, const __bf16* Bh,
                                            const __bf16* Bl, int64_t sAi, int64_t sAl, int64_t sBj, int64_t sBl,
                                            int64_t rows_a, int64_t rows_b, int64_t nk, const int16_t* list,
@@ -246,7 +255,8 @@ __device__ __forceinline__ void bf16p_ring(__bf16* ring, const __bf16* Ah, const
   constexpr int NI = (BM + BN) / 8;  // load instructions per stage: 1 KB each
   constexpr int IPW = (NI + NW - 1) / NW;
   constexpr int STAGE = RingSmem<BM, BN, S>::STAGE;
-  static_assert((S - 2) * IPW < 64, "outstanding loads exceed vmcnt");
+  static_assert(S >= 3 && S <= 5, "ring depth");
+  static_assert((S - 1) * IPW < 64, "outstanding loads exceed vmcnt");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WGN, wn = w % WGN;
   const int wu = __builtin_amdgcn_readfirstlane(w);
@@ -288,57 +298,113 @@ __device__ __forceinline__ void bf16p_ring(__bf16* ring, const __bf16* Ah, const
 #pragma unroll
     for (int i = 0; i < IPW; ++i) dma16(gp[i] + t * step[i], sb + ldso[i]);
   };
-  auto compute = [&](const __bf16* st) {
-    const __bf16* A0 = st;
-    const __bf16* A1 = st + BM * BK;
-    const __bf16* B0 = st + 2 * BM * BK;
-    const __bf16* B1 = B0 + BN * BK;
+  struct Frags {
     bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-    for (int a = 0; a < TM; ++a) {
-      const int r0 = (wm * TM + a) * 16;
-      if constexpr (A_MN) {
-        ah[a] = frag_mnx<BM>(A0, r0, lane);
-        al[a] = frag_mnx<BM>(A1, r0, lane);
-      } else {
-        ah[a] = frag_k(A0, r0, lane);
-        al[a] = frag_k(A1, r0, lane);
-      }
+  };
+  auto read_a = [&](int slot, int a, Frags& f) {
+    const __bf16* A0 = ring + slot * STAGE;
+    const __bf16* A1 = A0 + BM * BK;
+    const int r0 = (wm * TM + a) * 16;
+    if constexpr (A_MN) {
+      f.ah[a] = frag_mnx<BM>(A0, r0, lane);
+      f.al[a] = frag_mnx<BM>(A1, r0, lane);
+    } else {
+      f.ah[a] = frag_k(A0, r0, lane);
+      f.al[a] = frag_k(A1, r0, lane);
     }
+  };
+  auto read_b = [&](int slot, Frags& f) {
+    const __bf16* B0 = ring + slot * STAGE + 2 * BM * BK;
+    const __bf16* B1 = B0 + BN * BK;
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
       const int r0 = (wn * TN + b) * 16;
-      bh[b] = frag_k(B0, r0, lane);
-      bl[b] = frag_k(B1, r0, lane);
+      f.bh[b] = frag_k(B0, r0, lane);
+      f.bl[b] = frag_k(B1, r0, lane);
     }
-#pragma unroll
-    for (int a = 0; a < TM; ++a)
-#pragma unroll
-      for (int b = 0; b < TN; ++b) {
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-      }
   };
   auto sync = [&](int64_t later) {  // stages issued after the one to read
-    static_assert(S <= 5, "ring_sync cases");
-    if (later >= 3) ring_sync<(S > 4 ? 3 : 0) * IPW>();
-    else if (later == 2) ring_sync<(S > 3 ? 2 : 0) * IPW>();
+    if (later >= 4) ring_sync<(S > 4 ? 4 : 0) * IPW>();
+    else if (later == 3) ring_sync<(S > 3 ? 3 : 0) * IPW>();
+    else if (later == 2) ring_sync<2 * IPW>();
     else if (later == 1) ring_sync<IPW>();
     else ring_sync<0>();
   };
+  // Step kt: f holds stage kt (slot rs).  With MORE (a stage kt + 1
+  // follows) the B fragments of stage kt + 1 are read into g first and its
+  // A fragments of row block a after the MFMAs of row block a, which frees
+  // f.ah[a], f.al[a]; the scheduling barriers keep the reads in that order,
+  // so both sets together hold one stage plus the B fragments.
+  auto step_kt = [&](auto more_c, int64_t kt, int rs, Frags& f, Frags& g) {
+    constexpr bool MORE = decltype(more_c)::value;
+    const int ns = rs + 1 == S ? 0 : rs + 1;
+    if constexpr (MORE) {
+      sync(min(nk - 2 - kt, static_cast<int64_t>(S - 2)));
+      if (kt + S < nk) issue(rs, kt + S);
+      read_b(ns, g);
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      // the three products of one accumulator are TN instructions apart
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.al[a], f.bh[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[a], f.bl[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[a], f.bh[b], acc[a][b], 0, 0, 0);
+      if constexpr (MORE) {
+        __builtin_amdgcn_sched_barrier(0);
+        read_a(ns, a, g);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  };
+  using More = std::integral_constant<bool, true>;
+  using Last = std::integral_constant<bool, false>;
 
   if (nk <= 0) return;
+  if constexpr (!PF) {
 #pragma unroll
-  for (int st = 0; st < S - 1; ++st)
+    for (int st = 0; st < S - 1; ++st)
+      if (st < nk) issue(st, st);
+    int slot = 0;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      sync(min(nk - 1 - kt, static_cast<int64_t>(S - 2)));
+      if (kt + S - 1 < nk) issue(slot == 0 ? S - 1 : slot - 1, kt + S - 1);
+      Frags f;
+      read_b(slot, f);
+#pragma unroll
+      for (int a = 0; a < TM; ++a) read_a(slot, a, f);
+      step_kt(Last{}, kt, slot, f, f);
+      slot = slot + 1 == S ? 0 : slot + 1;
+    }
+    return;
+  }
+#pragma unroll
+  for (int st = 0; st < S; ++st)
     if (st < nk) issue(st, st);
+  sync(min(nk - 1, static_cast<int64_t>(S - 1)));
+  Frags f0, f1;
+  read_b(0, f0);
+#pragma unroll
+  for (int a = 0; a < TM; ++a) read_a(0, a, f0);
   int slot = 0;
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    sync(min(nk - 1 - kt, static_cast<int64_t>(S - 2)));
-    // the slot read in step kt - 1 is free once every wave has passed the barrier
-    if (kt + S - 1 < nk) issue(slot == 0 ? S - 1 : slot - 1, kt + S - 1);
-    compute(ring + slot * STAGE);
+  int64_t kt = 0;
+  for (; kt + 2 < nk; kt += 2) {
+    step_kt(More{}, kt, slot, f0, f1);
     slot = slot + 1 == S ? 0 : slot + 1;
+    step_kt(More{}, kt + 1, slot, f1, f0);
+    slot = slot + 1 == S ? 0 : slot + 1;
+  }
+  if (kt + 1 < nk) {
+    step_kt(More{}, kt, slot, f0, f1);
+    slot = slot + 1 == S ? 0 : slot + 1;
+    step_kt(Last{}, kt + 1, slot, f1, f0);
+  } else {
+    step_kt(Last{}, kt, slot, f0, f1);
   }
 }
 
@@ -445,11 +511,13 @@ __device__ __forceinline__ void bf16p_loop(PSmem<16 * WGM * TM, 16 * WGN * TN, A
 //     64-point block has an active chunk among the tile's AO columns.
 // Skipped steps and tiles hold exact zeros of the AO operand, so every
 // output is a sum of the same non-zero terms as in the dense product.
+// PF: ring tiles read the next stage's fragments under the current MFMAs
+// (the persistent form, which holds more state, does without).
 template <bool A_MN, int WGM, int WGN, int TM, int TN, int DEPTH>
 using SmemOf = std::conditional_t<(DEPTH >= 3), RingSmem<16 * WGM * TM, 16 * WGN * TN, DEPTH>,
                                   PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>>;
 
-template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR>
+template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR, bool PF = true>
 __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, int z,
                                            SmemOf<A_MN, WGM, WGN, TM, TN, DEPTH>& sm,
                                            int16_t* s_list, int* s_n) {
@@ -527,7 +595,7 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
   }
   constexpr bool LIST = SCR == 2 || SCR == 4;
   if constexpr (DEPTH >= 3) {
-    bf16p_ring<A_MN, WGM, WGN, TM, TN, DEPTH, LIST>(sm.ring, Ah, Al, Bh, Bl, g.sAi, g.sAl, g.sBj, g.sBl, rows_a,
+    bf16p_ring<A_MN, WGM, WGN, TM, TN, DEPTH, LIST, PF>(sm.ring, Ah, Al, Bh, Bl, g.sAi, g.sAl, g.sBj, g.sBl, rows_a,
                                                     rows_b, nk, s_list, acc);
   } else {
     // DEPTH register stages: the global loads of K step k + DEPTH are issued
@@ -588,7 +656,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmA
   __shared__ int s_n;
   for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
     const WorkItem it = items[i];
-    bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, 0>(jobs[it.job], it.a, it.b, it.c, sm, s_list, &s_n);
+    bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, 0, false>(jobs[it.job], it.a, it.b, it.c, sm, s_list, &s_n);
     __syncthreads();  // LDS is restaged by the next item
   }
 }
