@@ -30,7 +30,8 @@
 // Two staging schemes (the tile's DEPTH):
 //   DEPTH 1, 2: each thread loads its chunks into registers DEPTH K steps
 //     ahead and stores them to one of two LDS buffers;
-//   DEPTH >= 3: an LDS ring of DEPTH stages filled by global_load_lds_dwordx4
+//   DEPTH >= 3 (or -2): an LDS ring of DEPTH (2) stages filled by
+//     global_load_lds_dwordx4
 //     (each lane's 16 bytes go from global memory straight to LDS), so the
 //     loads of steps kt + 1 .. kt + DEPTH are in flight while step kt
 //     computes and no registers hold operand data; the MFMA fragments of
@@ -169,7 +170,11 @@ __device__ __forceinline__ bf16x8 frag_k(const __bf16* t, int r0, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS ring staging (DEPTH >= 3).
+// LDS ring staging (DEPTH >= 3, or -2 for a two-stage ring small enough
+// that two workgroups share a CU).
+
+// Ring stages of a tile's DEPTH (0: register staging).
+constexpr int ring_stages(int depth) { return depth >= 3 ? depth : (depth < 0 ? -depth : 0); }
 
 // MN-major ring tile of R rows: 16-byte chunk c of k-row l sits at chunk
 // c ^ mn_xor(l).  A 16-lane group of the transposing fragment read touches
@@ -255,7 +260,7 @@ __device__ __forceinline__ void bf16p_ring(__bf16* ring, const __bf16* Ah, const
   constexpr int NI = (BM + BN) / 8;  // load instructions per stage: 1 KB each
   constexpr int IPW = (NI + NW - 1) / NW;
   constexpr int STAGE = RingSmem<BM, BN, S>::STAGE;
-  static_assert(S >= 3 && S <= 5, "ring depth");
+  static_assert(S >= 2 && S <= 5, "ring depth");
   static_assert((S - 1) * IPW < 64, "outstanding loads exceed vmcnt");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WGN, wn = w % WGN;
@@ -512,9 +517,12 @@ __device__ __forceinline__ void bf16p_loop(PSmem<16 * WGM * TM, 16 * WGN * TN, A
 // Skipped steps and tiles hold exact zeros of the AO operand, so every
 // output is a sum of the same non-zero terms as in the dense product.
 // PF: ring tiles read the next stage's fragments under the current MFMAs
-// (the persistent form, which holds more state, does without).
+// (the persistent form, which holds more state, and the two-stage tiles,
+// which must fit two workgroups per CU, do without).
 template <bool A_MN, int WGM, int WGN, int TM, int TN, int DEPTH>
-using SmemOf = std::conditional_t<(DEPTH >= 3), RingSmem<16 * WGM * TM, 16 * WGN * TN, DEPTH>,
+using SmemOf = std::conditional_t<(ring_stages(DEPTH) > 0),
+                                  RingSmem<16 * WGM * TM, 16 * WGN * TN,
+                                           (ring_stages(DEPTH) > 0 ? ring_stages(DEPTH) : 1)>,
                                   PSmem<16 * WGM * TM, 16 * WGN * TN, A_MN>>;
 
 template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR, bool PF = true>
@@ -594,9 +602,9 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
     if (!on) nk = 0;
   }
   constexpr bool LIST = SCR == 2 || SCR == 4;
-  if constexpr (DEPTH >= 3) {
-    bf16p_ring<A_MN, WGM, WGN, TM, TN, DEPTH, LIST, PF>(sm.ring, Ah, Al, Bh, Bl, g.sAi, g.sAl, g.sBj, g.sBl, rows_a,
-                                                    rows_b, nk, s_list, acc);
+  if constexpr (ring_stages(DEPTH) > 0) {
+    bf16p_ring<A_MN, WGM, WGN, TM, TN, ring_stages(DEPTH), LIST, PF>(sm.ring, Ah, Al, Bh, Bl, g.sAi, g.sAl, g.sBj,
+                                                                     g.sBl, rows_a, rows_b, nk, s_list, acc);
   } else {
     // DEPTH register stages: the global loads of K step k + DEPTH are issued
     // before the MFMAs of step k, so each load has DEPTH steps of MFMA work
@@ -636,21 +644,20 @@ __device__ __forceinline__ void bf16p_body(const GemmArgs& g, int mt, int nt, in
 }
 
 template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH, int SCR>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_kernel(GemmArgs g, int nM, int nN) {
+__global__ __launch_bounds__(64 * WGM * WGN, DEPTH < 0 ? 2 : 1) void gemm_bf16p_kernel(GemmArgs g, int nM, int nN) {
   __shared__ __align__(16) SmemOf<A_MN, WGM, WGN, TM, TN, DEPTH> sm;
   __shared__ int16_t s_list[(SCR == 2 || SCR == 4) ? kSparseMaxStages : 1];
   __shared__ int s_n;
   int mt, nt, z;
   if (!grid_tile(g, nM, nN, blockIdx.x, mt, nt, z)) return;
-  bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR>(g, mt, nt, z, sm, s_list, &s_n);
+  bf16p_body<A_MN, TD, WGM, WGN, TM, TN, DEPTH, SCR, (DEPTH > 0)>(g, mt, nt, z, sm, s_list, &s_n);
 }
 
 // Persistent form (batch executor): the grid walks a list of (job, M tile,
 // N tile, z) items, each job holding one molecule's arguments.
 template <bool A_MN, typename TD, int WGM, int WGN, int TM, int TN, int DEPTH>
-__global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmArgs* __restrict__ jobs,
-                                                                    const WorkItem* __restrict__ items,
-                                                                    int n_items) {
+__global__ __launch_bounds__(64 * WGM * WGN, DEPTH < 0 ? 2 : 1) void gemm_bf16p_persist(
+    const GemmArgs* __restrict__ jobs, const WorkItem* __restrict__ items, int n_items) {
   __shared__ __align__(16) SmemOf<A_MN, WGM, WGN, TM, TN, DEPTH> sm;
   __shared__ int16_t s_list[1];
   __shared__ int s_n;
@@ -662,7 +669,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmA
 }
 
 // {WGM, WGN, TM, TN, DEPTH}; the reduction step is always 32.  DEPTH 1, 2:
-// register staging; DEPTH >= 3: LDS ring of DEPTH stages.
+// register staging; DEPTH >= 3: LDS ring of DEPTH stages; DEPTH -2: LDS ring
+// of two stages, compiled for two waves per SIMD so that two 4-wave
+// workgroups share a CU (one's output stores and barrier waits overlap the
+// other's K loop); these read each stage's fragments after its barrier.
 #define QMK_BF16P_TILE_LIST(X) \
   X(0, 2, 2, 4, 4, 1)          \
   X(1, 2, 2, 4, 4, 2)          \
@@ -688,7 +698,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void gemm_bf16p_persist(const GemmA
   X(21, 2, 2, 5, 5, 3)         \
   X(22, 1, 2, 5, 5, 4)         \
   X(23, 2, 4, 5, 4, 3)         \
-  X(24, 8, 1, 2, 5, 3)
+  X(24, 8, 1, 2, 5, 3)         \
+  X(25, 2, 2, 4, 5, -2)        \
+  X(26, 2, 2, 5, 4, -2)
 
 [[maybe_unused]] constexpr TileCfg kBfpTiles[] = {
 #define QMK_BFP_ENTRY(id, wgm, wgn, tm, tn, depth) {wgm, wgn, tm, tn, BK},
@@ -802,7 +814,8 @@ TileCfg gemm_bf16p_tile(int cfg) { return kBfpTiles[cfg]; }
 size_t gemm_bf16p_tile_lds_bytes(int cfg) {
   const TileCfg& t = kBfpTiles[cfg];
   const int bm = 16 * t.wgm * t.tm, bn = 16 * t.wgn * t.tn;
-  if (kBfpDepth[cfg] >= 3) return static_cast<size_t>(kBfpDepth[cfg]) * (bm + bn) * BK * 4;  // ring
+  const int rs = ring_stages(kBfpDepth[cfg]);
+  if (rs > 0) return static_cast<size_t>(rs) * (bm + bn) * BK * 4;  // ring
   // the larger of the two staging layouts of A (MN-major for the forward and
   // W^T ao products, K-major for the W C product)
   const size_t a = std::max<size_t>(static_cast<size_t>(BK) * mn_pitch(bm), static_cast<size_t>(bm) * KLD);
